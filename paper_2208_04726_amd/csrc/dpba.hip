@@ -1,0 +1,534 @@
+// Kernels and C ABI of the gfx950 bundle-adjustment library (include/dpba.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dpba.h"
+#include "dpba_common.h"
+#include "dpba_prep.h"
+#include "dpba_assemble.h"
+#include "dpba_solve.h"
+
+using namespace dpba;
+
+// ---------------------------------------------------------------------------
+// kernels
+__global__ void __launch_bounds__(WG) k_prep(Params P) {
+  __shared__ int lds[WG + 16];
+  wg_prep(P, blockIdx.x, lds);
+}
+
+template <typename T, int MAXT>
+__global__ void __launch_bounds__(WG) k_assemble(Params P, int iter, int Rcap) {
+  extern __shared__ __align__(16) char smem[];
+  wg_assemble<T, MAXT>(P, blockIdx.x, iter, smem, Rcap);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_chol(Params P, int iter) {
+  extern __shared__ __align__(16) char smem[];
+  wg_chol<T>(P, blockIdx.x, iter, smem);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_backsub(Params P, int iter, int Rcap) {
+  extern __shared__ __align__(16) char smem[];
+  wg_backsub<T>(P, blockIdx.x, iter, smem, Rcap);
+}
+
+__global__ void __launch_bounds__(WG) k_finalize(Params P) { wg_finalize(P, blockIdx.x); }
+
+// Persistent form: each workgroup takes whole windows (one chunk each) and
+// runs preparation and every stage of every iteration without leaving the
+// kernel.
+template <typename T, int MAXT>
+__global__ void __launch_bounds__(WG) k_fused(Params P, int Rcap) {
+  extern __shared__ __align__(16) char smem[];
+  for (int w = blockIdx.x; w < P.n_windows; w += gridDim.x) {
+    wg_prep(P, w, (int*)smem);
+    __syncthreads();
+    const int c = P.win[w].chunk_off;
+    for (int it = 0; it < P.iterations; ++it) {
+      wg_assemble<T, MAXT>(P, c, it, smem, Rcap);
+      __syncthreads();
+      wg_chol<T>(P, w, it, smem);
+      __syncthreads();
+      wg_backsub<T>(P, c, it, smem, Rcap);
+      __syncthreads();
+    }
+    wg_finalize(P, w);
+    __syncthreads();
+  }
+}
+
+// Dense S, s of one window from the chunk partials (inspection).
+template <typename T>
+__global__ void __launch_bounds__(WG) k_debug_gather(Params P, int w, double* S, double* s) {
+  extern __shared__ __align__(16) char smem[];
+  const WinDesc W = P.win[w];
+  const int n = 6 * (W.n_frames - W.n_fixed);
+  const int lda = n + 1;
+  double* A = (double*)(smem + 64);
+  double* b = A + n * lda;
+  if (n == 0) return;
+  gather_partials<T>(P, w, W, A, lda, b, n);
+  for (int i = threadIdx.x; i < n * n; i += WG) {
+    const int r = i / n, c = i % n;
+    S[i] = (c <= r ? A[r * lda + c] : A[c * lda + r]) + (r == c ? P.lambda : 0.0);
+  }
+  for (int i = threadIdx.x; i < n; i += WG) s[i] = b[i];
+}
+
+template <typename T>
+__global__ void k_debug_mfma(const T* A, const T* B, T* D) {
+  typedef typename AccT<T>::type Acc;
+  const int l = threadIdx.x;
+  Acc acc = Acc{T(0), T(0), T(0), T(0)};
+  acc = mfma16(A[(l & 15) * 4 + (l >> 4)], B[(l >> 4) * 16 + (l & 15)], acc);
+  for (int r = 0; r < 4; ++r) D[acc_row(T(0), l >> 4, r) * 16 + (l & 15)] = acc[r];
+}
+
+// ---------------------------------------------------------------------------
+// handle
+struct ba_handle {
+  ba_config cfg;
+  int device = 0;
+  int n_cu = 256;
+  int64_t cap_chunks = 0;
+  int64_t cap_partial = 0;   // elements
+  WinDesc* d_win = nullptr;
+  ChunkDesc* d_chunk = nullptr;
+  WinDesc* h_win = nullptr;
+  ChunkDesc* h_chunk = nullptr;
+  hipEvent_t staging_ev = nullptr;
+  bool staging_pending = false;
+  hipStream_t last_stream = nullptr;
+  int last_W = 0;
+  int32_t *status = nullptr, *wmeta = nullptr, *cnt = nullptr, *ptr = nullptr, *fill = nullptr;
+  int32_t *acnt = nullptr, *afill = nullptr, *plist = nullptr, *csr = nullptr, *arange = nullptr,
+          *cstate = nullptr;
+  double* partial = nullptr;
+  double *dxi = nullptr, *pose_buf = nullptr, *depth_buf = nullptr;
+  std::string err;
+};
+
+namespace {
+
+int fail(ba_handle* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+#define HIPCHK(h, call)                                                              \
+  do {                                                                                \
+    hipError_t _e = (call);                                                           \
+    if (_e != hipSuccess)                                                             \
+      return fail(h, BA_E_HIP, std::string(#call) + ": " + hipGetErrorString(_e));    \
+  } while (0)
+
+template <typename T>
+int set_kernel_attrs() {
+  const int lds = 160 * 1024;
+  if (hipFuncSetAttribute((const void*)k_assemble<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_assemble<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_fused<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_fused<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chol<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_backsub<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_debug_gather<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
+  return 0;
+}
+
+struct Plan {
+  int W = 0, C = 0, Rcap = 1, nmax = 0, maxt = 4;
+  bool fused = false;
+  int64_t F = 0, Pn = 0, E = 0;
+};
+
+int validate_and_plan(ba_handle* h, const ba_problem* p, Plan& pl) {
+  const ba_config& cfg = h->cfg;
+  if (!p) return fail(h, BA_E_INVAL, "problem is NULL");
+  const int W = p->n_windows;
+  if (W < 0) return fail(h, BA_E_INVAL, "n_windows < 0");
+  if (W > cfg.max_windows) return fail(h, BA_E_CAPACITY, "n_windows exceeds max_windows");
+  pl.W = W;
+  if (W == 0) return BA_OK;
+  if (!p->frame_off || !p->patch_off || !p->edge_off || !p->n_fixed || !p->intrinsics)
+    return fail(h, BA_E_INVAL, "host offset / n_fixed / intrinsics pointer is NULL");
+  if (p->frame_off[0] != 0 || p->patch_off[0] != 0 || p->edge_off[0] != 0)
+    return fail(h, BA_E_INVAL, "offsets must start at 0");
+  for (int w = 0; w < W; ++w) {
+    const int64_t N = p->frame_off[w + 1] - p->frame_off[w];
+    const int64_t M = p->patch_off[w + 1] - p->patch_off[w];
+    const int64_t E = p->edge_off[w + 1] - p->edge_off[w];
+    if (N < 0 || M < 0 || E < 0) return fail(h, BA_E_INVAL, "offsets must be non-decreasing");
+    if (N > cfg.max_frames_per_window)
+      return fail(h, BA_E_CAPACITY, "window " + std::to_string(w) + " has more frames than max_frames_per_window");
+    if (M > INT32_MAX / 2 || E > INT32_MAX / 2) return fail(h, BA_E_CAPACITY, "window too large");
+    const int nf = p->n_fixed[w];
+    if (nf < 0 || nf > N) return fail(h, BA_E_INVAL, "n_fixed outside [0, frames] in window " + std::to_string(w));
+    const int n = 6 * (int)(N - nf);
+    if (n > NCHOL_MAX)
+      return fail(h, BA_E_CAPACITY, "window " + std::to_string(w) + ": more than 21 free frames");
+    pl.nmax = std::max(pl.nmax, n);
+    {
+      // accumulator tiles per wave: lower-triangle 16x16 tiles of (n+1)^2 over 8 waves
+      const int T16 = (n + 1 + 15) / 16;
+      const int L = T16 * (T16 + 1) / 2;
+      if (L > NWAVES * 4) pl.maxt = 8;
+    }
+    pl.Rcap = std::max<int>(pl.Rcap, (int)N);
+    const double* K = p->intrinsics + 4 * w;
+    for (int m = 0; m < 4; ++m)
+      if (!std::isfinite(K[m])) return fail(h, BA_E_INVAL, "non-finite intrinsics");
+    if (K[0] == 0.0 || K[1] == 0.0) return fail(h, BA_E_INVAL, "zero focal length");
+  }
+  pl.F = p->frame_off[W];
+  pl.Pn = p->patch_off[W];
+  pl.E = p->edge_off[W];
+  if (pl.F > cfg.max_frames || pl.Pn > cfg.max_patches || pl.E > cfg.max_edges)
+    return fail(h, BA_E_CAPACITY, "batch totals exceed the handle's capacities");
+  if (pl.F > 0 && (!p->poses_in || !p->poses_out)) return fail(h, BA_E_INVAL, "pose pointer is NULL");
+  if (pl.Pn > 0 && (!p->patches_in || !p->anchor || !p->depth_out))
+    return fail(h, BA_E_INVAL, "patch pointer is NULL");
+  if (pl.E > 0 && (!p->kk || !p->jj || !p->targets || !p->weights))
+    return fail(h, BA_E_INVAL, "edge pointer is NULL");
+  return BA_OK;
+}
+
+// Chunking: split each window into runs of `c` consecutive source frames.
+// The fused schedule uses one chunk per window.
+int build_descriptors(ba_handle* h, const ba_problem* p, Plan& pl) {
+  const ba_config& cfg = h->cfg;
+  const int W = pl.W;
+  int64_t total_anchor = 0;
+  for (int w = 0; w < W; ++w) total_anchor += p->frame_off[w + 1] - p->frame_off[w];
+  if (cfg.schedule == BA_SCHED_FUSED) pl.fused = true;
+  else if (cfg.schedule == BA_SCHED_SPLIT) pl.fused = false;
+  else pl.fused = W >= h->n_cu / 4;
+  // anchors per chunk for the split schedule: aim for ~2 workgroups per CU
+  int c = 1;
+  if (!pl.fused) {
+    const int64_t target = 2LL * h->n_cu;
+    c = (int)std::max<int64_t>(1, (total_anchor + target - 1) / target);
+  }
+  for (;;) {
+    int64_t chunks = 0, part = 0;
+    for (int w = 0; w < W; ++w) {
+      const int N = (int)(p->frame_off[w + 1] - p->frame_off[w]);
+      const int cw = pl.fused ? std::max(N, 1) : c;
+      const int nc = N == 0 ? 0 : (N + cw - 1) / cw;
+      const int64_t D = 6LL * (N - p->n_fixed[w]);
+      chunks += nc;
+      part += nc * (D * D + D);
+    }
+    if (chunks <= h->cap_chunks && part <= h->cap_partial) break;
+    if (pl.fused) return fail(h, BA_E_CAPACITY, "partial workspace too small");
+    if (c >= cfg.max_frames_per_window) { pl.fused = true; continue; }
+    c *= 2;
+  }
+  if (h->staging_pending) {
+    HIPCHK(h, hipEventSynchronize(h->staging_ev));
+    h->staging_pending = false;
+  }
+  int64_t part_off = 0;
+  int ci = 0;
+  for (int w = 0; w < W; ++w) {
+    WinDesc& d = h->h_win[w];
+    const int N = (int)(p->frame_off[w + 1] - p->frame_off[w]);
+    d.frame_off = p->frame_off[w];
+    d.patch_off = p->patch_off[w];
+    d.edge_off = p->edge_off[w];
+    d.n_frames = N;
+    d.n_patches = (int)(p->patch_off[w + 1] - p->patch_off[w]);
+    d.n_edges = (int)(p->edge_off[w + 1] - p->edge_off[w]);
+    d.n_fixed = p->n_fixed[w];
+    d.fx = p->intrinsics[4 * w + 0];
+    d.fy = p->intrinsics[4 * w + 1];
+    d.cx = p->intrinsics[4 * w + 2];
+    d.cy = p->intrinsics[4 * w + 3];
+    const int cw = pl.fused ? std::max(N, 1) : c;
+    const int nc = N == 0 ? 0 : (N + cw - 1) / cw;
+    const int64_t D = 6LL * (N - d.n_fixed);
+    d.chunk_off = ci;
+    d.n_chunks = nc;
+    d.part_off = part_off;
+    d.part_stride = D * D + D;
+    for (int q = 0; q < nc; ++q) {
+      ChunkDesc& cd = h->h_chunk[ci++];
+      cd.window = w;
+      cd.a_lo = q * cw;
+      cd.a_hi = std::min(N, (q + 1) * cw);
+      cd.pad = 0;
+    }
+    part_off += nc * d.part_stride;
+  }
+  pl.C = ci;
+  return BA_OK;
+}
+
+template <typename T>
+int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t s) {
+  Params P;
+  memset(&P, 0, sizeof(P));
+  P.win = h->d_win;
+  P.chunk = h->d_chunk;
+  P.n_windows = pl.W;
+  P.n_chunks = pl.C;
+  P.iterations = h->cfg.iterations;
+  P.lambda = h->cfg.lambda;
+  P.z_min = h->cfg.z_min;
+  P.poses_in = p->poses_in;
+  P.patches_in = p->patches_in;
+  P.anchor = p->anchor;
+  P.kk = p->kk;
+  P.jj = p->jj;
+  P.targets = p->targets;
+  P.weights = p->weights;
+  P.poses_out = p->poses_out;
+  P.depth_out = p->depth_out;
+  P.status = h->status;
+  P.wmeta = h->wmeta;
+  P.cnt = h->cnt;
+  P.ptr = h->ptr;
+  P.fill = h->fill;
+  P.acnt = h->acnt;
+  P.afill = h->afill;
+  P.plist = h->plist;
+  P.csr = h->csr;
+  P.arange = h->arange;
+  P.cstate = h->cstate;
+  P.partial = h->partial;
+  P.dxi = h->dxi;
+  P.pose_buf = h->pose_buf;
+  P.depth_buf = h->depth_buf;
+  P.n_frames_total = h->cfg.max_frames;
+
+  HIPCHK(h, hipMemcpyAsync(h->d_win, h->h_win, sizeof(WinDesc) * pl.W, hipMemcpyHostToDevice, s));
+  if (pl.C > 0)
+    HIPCHK(h, hipMemcpyAsync(h->d_chunk, h->h_chunk, sizeof(ChunkDesc) * pl.C, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipEventRecord(h->staging_ev, s));
+  h->staging_pending = true;
+
+  const int Rcap = pl.Rcap;
+  const int asm_lds = asm_layout(Rcap, (int)sizeof(T)).total;
+  const int chol_lds = chol_lds_bytes(pl.nmax);
+  const int bs_lds = backsub_lds_bytes(Rcap, (int)sizeof(T));
+  if (pl.fused) {
+    const int lds = std::max(std::max(asm_lds, chol_lds), std::max(bs_lds, (WG + 16) * 4));
+    const int grid = std::min(pl.W, 4 * h->n_cu);
+    if (pl.maxt == 4) hipLaunchKernelGGL((k_fused<T, 4>), dim3(grid), dim3(WG), lds, s, P, Rcap);
+    else hipLaunchKernelGGL((k_fused<T, 8>), dim3(grid), dim3(WG), lds, s, P, Rcap);
+    HIPCHK(h, hipGetLastError());
+  } else {
+    hipLaunchKernelGGL(k_prep, dim3(pl.W), dim3(WG), 0, s, P);
+    HIPCHK(h, hipGetLastError());
+    for (int it = 0; it < P.iterations; ++it) {
+      if (pl.C > 0) {
+        if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<T, 4>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
+        else hipLaunchKernelGGL((k_assemble<T, 8>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
+        HIPCHK(h, hipGetLastError());
+      }
+      hipLaunchKernelGGL(k_chol<T>, dim3(pl.W), dim3(WG), chol_lds, s, P, it);
+      HIPCHK(h, hipGetLastError());
+      if (pl.C > 0) {
+        hipLaunchKernelGGL(k_backsub<T>, dim3(pl.C), dim3(WG), bs_lds, s, P, it, Rcap);
+        HIPCHK(h, hipGetLastError());
+      }
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(pl.W), dim3(WG), 0, s, P);
+    HIPCHK(h, hipGetLastError());
+  }
+  return BA_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+extern "C" {
+
+int ba_create(const ba_config* cfg, ba_handle** out) {
+  if (!out) return BA_E_INVAL;
+  *out = nullptr;
+  if (!cfg) return BA_E_INVAL;
+  if (cfg->precision != BA_PREC_FP64 && cfg->precision != BA_PREC_FP32) return BA_E_INVAL;
+  if (cfg->iterations < 0 || cfg->iterations > 64) return BA_E_INVAL;
+  if (!(cfg->lambda >= 0.0) || !std::isfinite(cfg->lambda) || !std::isfinite(cfg->z_min)) return BA_E_INVAL;
+  if (cfg->schedule < 0 || cfg->schedule > 2) return BA_E_INVAL;
+  if (cfg->max_windows < 1 || cfg->max_frames_per_window < 1 || cfg->max_frames_per_window > RMAX)
+    return BA_E_INVAL;
+  if (cfg->precision == BA_PREC_FP64 && cfg->max_frames_per_window > 32) return BA_E_INVAL;
+  if (cfg->max_frames < 1 || cfg->max_patches < 0 || cfg->max_edges < 0) return BA_E_INVAL;
+
+  ba_handle* h = new ba_handle();
+  h->cfg = *cfg;
+  auto cleanup = [&](int code) { ba_destroy(h); return code; };
+  if (hipGetDevice(&h->device) != hipSuccess) return cleanup(BA_E_HIP);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, h->device) != hipSuccess) return cleanup(BA_E_HIP);
+  h->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  const int r = cfg->precision == BA_PREC_FP32 ? set_kernel_attrs<float>() : set_kernel_attrs<double>();
+  if (r != 0) return cleanup(BA_E_HIP);
+
+  const int64_t W = cfg->max_windows, F = cfg->max_frames, Pn = std::max<int64_t>(cfg->max_patches, 1),
+                E = std::max<int64_t>(cfg->max_edges, 1);
+  const int64_t Dmax = 6LL * cfg->max_frames_per_window;
+  const size_t esz = cfg->precision == BA_PREC_FP32 ? 4 : 8;
+  h->cap_chunks = std::max<int64_t>(F, W);
+  h->cap_partial = std::max<int64_t>(W, 32) * (Dmax * Dmax + Dmax);
+  bool ok = true;
+  auto dmalloc = [&](void** ptr, size_t bytes) {
+    if (!ok) return;
+    if (hipMalloc(ptr, std::max<size_t>(bytes, 256)) != hipSuccess) ok = false;
+  };
+  dmalloc((void**)&h->d_win, sizeof(WinDesc) * W);
+  dmalloc((void**)&h->d_chunk, sizeof(ChunkDesc) * h->cap_chunks);
+  dmalloc((void**)&h->status, 4 * W);
+  dmalloc((void**)&h->wmeta, 16 * W);
+  dmalloc((void**)&h->cnt, 4 * Pn);
+  dmalloc((void**)&h->ptr, 4 * Pn);
+  dmalloc((void**)&h->fill, 4 * Pn);
+  dmalloc((void**)&h->acnt, 4 * (F + W));
+  dmalloc((void**)&h->afill, 4 * F);
+  dmalloc((void**)&h->plist, 4 * Pn);
+  dmalloc((void**)&h->csr, 4 * E);
+  dmalloc((void**)&h->arange, 8 * F);
+  dmalloc((void**)&h->cstate, 8 * h->cap_chunks);
+  dmalloc((void**)&h->partial, 8 * h->cap_partial);
+  dmalloc((void**)&h->dxi, 8 * 6 * F);
+  dmalloc((void**)&h->pose_buf, 8 * 2 * 7 * F);
+  dmalloc((void**)&h->depth_buf, 8 * Pn);
+  if (!ok) return cleanup(BA_E_HIP);
+  if (hipHostMalloc((void**)&h->h_win, sizeof(WinDesc) * W) != hipSuccess) return cleanup(BA_E_HIP);
+  if (hipHostMalloc((void**)&h->h_chunk, sizeof(ChunkDesc) * h->cap_chunks) != hipSuccess) return cleanup(BA_E_HIP);
+  if (hipEventCreateWithFlags(&h->staging_ev, hipEventDisableTiming) != hipSuccess) return cleanup(BA_E_HIP);
+  if (hipMemset(h->status, 0, 4 * W) != hipSuccess) return cleanup(BA_E_HIP);
+  *out = h;
+  return BA_OK;
+}
+
+int ba_solve(ba_handle* h, const ba_problem* p, void* stream) {
+  if (!h) return BA_E_INVAL;
+  h->err.clear();
+  Plan pl;
+  int r = validate_and_plan(h, p, pl);
+  if (r != BA_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  h->last_W = pl.W;
+  if (pl.W == 0) return BA_OK;
+  r = build_descriptors(h, p, pl);
+  if (r != BA_OK) return r;
+  return h->cfg.precision == BA_PREC_FP32 ? launch_solve<float>(h, p, pl, s)
+                                          : launch_solve<double>(h, p, pl, s);
+}
+
+int ba_backward(ba_handle* h, const ba_problem*, const double*, const double*, void*, void*, void*) {
+  if (!h) return BA_E_INVAL;
+  return fail(h, BA_E_STATE, "ba_backward: not available in this build");
+}
+
+int ba_status(ba_handle* h, int32_t* host_flags) {
+  if (!h || !host_flags) return BA_E_INVAL;
+  HIPCHK(h, hipStreamSynchronize(h->last_stream));
+  if (h->last_W > 0)
+    HIPCHK(h, hipMemcpy(host_flags, h->status, 4 * h->last_W, hipMemcpyDeviceToHost));
+  return BA_OK;
+}
+
+const char* ba_last_error(const ba_handle* h) { return h ? h->err.c_str() : "null handle"; }
+
+void ba_destroy(ba_handle* h) {
+  if (!h) return;
+  hipDeviceSynchronize();
+  hipFree(h->d_win);
+  hipFree(h->d_chunk);
+  hipFree(h->status);
+  hipFree(h->wmeta);
+  hipFree(h->cnt);
+  hipFree(h->ptr);
+  hipFree(h->fill);
+  hipFree(h->acnt);
+  hipFree(h->afill);
+  hipFree(h->plist);
+  hipFree(h->csr);
+  hipFree(h->arange);
+  hipFree(h->cstate);
+  hipFree(h->partial);
+  hipFree(h->dxi);
+  hipFree(h->pose_buf);
+  hipFree(h->depth_buf);
+  if (h->h_win) hipHostFree(h->h_win);
+  if (h->h_chunk) hipHostFree(h->h_chunk);
+  if (h->staging_ev) hipEventDestroy(h->staging_ev);
+  delete h;
+}
+
+int ba_debug_reduced_system(ba_handle* h, const ba_problem* p, int32_t window, double* S_out,
+                            double* s_out, void* stream) {
+  if (!h) return BA_E_INVAL;
+  h->err.clear();
+  Plan pl;
+  int r = validate_and_plan(h, p, pl);
+  if (r != BA_OK) return r;
+  if (window < 0 || window >= pl.W) return fail(h, BA_E_INVAL, "window index out of range");
+  if (!S_out || !s_out) return fail(h, BA_E_INVAL, "output pointer is NULL");
+  const int saved = h->cfg.schedule;
+  h->cfg.schedule = BA_SCHED_SPLIT;
+  r = build_descriptors(h, p, pl);
+  h->cfg.schedule = saved;
+  if (r != BA_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  h->last_W = pl.W;
+  Params P;
+  memset(&P, 0, sizeof(P));
+  P.win = h->d_win; P.chunk = h->d_chunk; P.n_windows = pl.W; P.n_chunks = pl.C;
+  P.iterations = 1; P.lambda = h->cfg.lambda; P.z_min = h->cfg.z_min;
+  P.poses_in = p->poses_in; P.patches_in = p->patches_in; P.anchor = p->anchor; P.kk = p->kk;
+  P.jj = p->jj; P.targets = p->targets; P.weights = p->weights;
+  P.status = h->status; P.wmeta = h->wmeta; P.cnt = h->cnt; P.ptr = h->ptr; P.fill = h->fill;
+  P.acnt = h->acnt; P.afill = h->afill; P.plist = h->plist; P.csr = h->csr; P.arange = h->arange;
+  P.cstate = h->cstate; P.partial = h->partial; P.dxi = h->dxi; P.pose_buf = h->pose_buf;
+  P.depth_buf = h->depth_buf; P.n_frames_total = h->cfg.max_frames;
+  HIPCHK(h, hipMemcpyAsync(h->d_win, h->h_win, sizeof(WinDesc) * pl.W, hipMemcpyHostToDevice, s));
+  if (pl.C > 0)
+    HIPCHK(h, hipMemcpyAsync(h->d_chunk, h->h_chunk, sizeof(ChunkDesc) * pl.C, hipMemcpyHostToDevice, s));
+  HIPCHK(h, hipEventRecord(h->staging_ev, s));
+  h->staging_pending = true;
+  const bool f32 = h->cfg.precision == BA_PREC_FP32;
+  const int esz = f32 ? 4 : 8;
+  hipLaunchKernelGGL(k_prep, dim3(pl.W), dim3(WG), 0, s, P);
+  HIPCHK(h, hipGetLastError());
+  if (pl.C > 0) {
+    const int al = asm_layout(pl.Rcap, esz).total;
+    if (f32) hipLaunchKernelGGL((k_assemble<float, 8>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
+    else hipLaunchKernelGGL((k_assemble<double, 8>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
+    HIPCHK(h, hipGetLastError());
+  }
+  const int lds = chol_lds_bytes(pl.nmax);
+  if (f32) hipLaunchKernelGGL(k_debug_gather<float>, dim3(1), dim3(WG), lds, s, P, window, S_out, s_out);
+  else hipLaunchKernelGGL(k_debug_gather<double>, dim3(1), dim3(WG), lds, s, P, window, S_out, s_out);
+  HIPCHK(h, hipGetLastError());
+  return BA_OK;
+}
+
+int ba_debug_mfma(int32_t precision, const void* A, const void* B, void* D, void* stream) {
+  if (!A || !B || !D) return BA_E_INVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (precision == BA_PREC_FP32)
+    hipLaunchKernelGGL(k_debug_mfma<float>, dim3(1), dim3(64), 0, s, (const float*)A, (const float*)B, (float*)D);
+  else if (precision == BA_PREC_FP64)
+    hipLaunchKernelGGL(k_debug_mfma<double>, dim3(1), dim3(64), 0, s, (const double*)A, (const double*)B, (double*)D);
+  else
+    return BA_E_INVAL;
+  return hipGetLastError() == hipSuccess ? BA_OK : BA_E_HIP;
+}
+
+}  // extern "C"

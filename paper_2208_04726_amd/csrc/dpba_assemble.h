@@ -1,0 +1,551 @@
+// Edge linearisation and assembly of the depth-eliminated pose system.
+//
+// Objective (Sec. 3.1, Eq. 6): sum over edges e = (k, j), patch k anchored in
+// frame i, of w_x r_x^2 + w_y r_y^2 with r = pi(p) - target, where
+//   p = R_ji (xbar, ybar, 1) + t_ji d_k           (Eq. 2 on (x, y, 1, d), K of Eq. 3)
+//   pi(p) = (fx X / Z + cx, fy Y / Z + cy)       (divide by the third element)
+// Per edge, with Pi = d pi / d p and left perturbations of T_i, T_j:
+//   J_j = Pi [d I | -hat(p)],  J_i = -J_j Ad(T_ji),  J_d = Pi t_ji.
+// Damped normal equations over (free poses, depths) eliminate every depth by
+// the Schur complement (Sec. 3.1): with C_k = lambda + sum_e J_d^T W J_d,
+// w_k = sum_e J_d^T W r and E_ak = sum_e J_a^T W J_d,
+//   S = B + lambda I - sum_k E_k E_k^T / C_k,   s = v - sum_k E_k w_k / C_k,
+// where B, v collect J_a^T W J_b and J_a^T W r over all edges.
+//
+// One workgroup handles one chunk: a run of consecutive source frames of one
+// window, and writes the chunk's share of S and s (lower triangle, dense over
+// the free frames its patches touch) to a partial buffer that the Cholesky
+// stage sums in a fixed order.  Within the chunk:
+//   * patches are taken in sub-batches of SB; each patch is a lane segment of
+//     the wave (one lane per edge), segment sums give C_k, w_k, E_ik;
+//   * the scaled row u_k = (E_k, w_k) / sqrt(C_k) of every patch is staged in
+//     LDS (column-major, dof x patch) and the outer products sum_k u_k u_k^T
+//     are accumulated with 16x16x4 matrix-core instructions into register
+//     tiles of the lower triangle;
+//   * B and v are gathered per (source frame i, target frame j) pair as
+//     Q_ij = sum_k J_j^T W J_j and V_ij = sum_k J_j^T W r (per-wave LDS tables,
+//     summed in wave order), then mapped to the (i,i), (i,j), (j,j) blocks
+//     through A = Ad(T_ji): B_jj += Q, B_ij -= A^T Q, B_ii += A^T Q A,
+//     v_j += V, v_i -= A^T V.
+#pragma once
+#include "dpba_common.h"
+
+namespace dpba {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <typename T> struct AccT;
+template <> struct AccT<float> { typedef f32x4 type; };
+template <> struct AccT<double> { typedef f64x4 type; };
+
+__device__ inline f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline f64x4 mfma16(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Row of the 16x16 result held in accumulator register r of a lane in lane
+// group g = lane / 16 (the column is lane % 16).  The f32 16x16x4 product
+// keeps four consecutive rows per lane group, the f64 product interleaves them.
+__device__ inline int acc_row(float, int g, int r) { return 4 * g + r; }
+__device__ inline int acc_row(double, int g, int r) { return 4 * r + g; }
+
+constexpr int SB = 32;          // patches per sub-batch (K block of the Schur product)
+constexpr int LDK = SB + 4;     // LDS row length of the staged u rows
+constexpr int RELW = 24;        // LDS words per relative pose: R(9) t(3) hat(t)R(9)
+
+// packed index of (m, n), m <= n, in the 21-entry upper triangle of a 6x6
+__device__ inline int sym6(int m, int n) {
+  if (m > n) { int t = m; m = n; n = t; }
+  return m * 6 - (m * (m - 1)) / 2 + (n - m);
+}
+
+// LDS layout of the assembly stage, in bytes, for a chunk range of at most
+// Rcap frames.  Shared with the host to size the launch.
+struct AsmLayout {
+  int rel, tbl, G, U, tiles, misc, total;
+  int Tcap;
+};
+__host__ __device__ inline AsmLayout asm_layout(int Rcap, int esize) {
+  AsmLayout L;
+  const int Dcap = 6 * Rcap;
+  L.Tcap = (Dcap + 1 + 15) / 16;
+  int o = 0;
+  L.rel = o;   o += RMAX * RELW * esize;
+  L.tbl = o;   o += NWAVES * Rcap * TBL * esize;
+  L.G = o;     o += (Rcap * 36 + 42) * esize;
+  L.U = o;     o += 16 * L.Tcap * LDK * esize;
+  L.tiles = o; o += 4 * ((L.Tcap * (L.Tcap + 1)) / 2 + 4);
+  L.misc = o;  o += 64;
+  L.total = (o + 255) & ~255;
+  return L;
+}
+
+template <typename T>
+struct EdgeOut {
+  T cd, wd;        // J_d^T W J_d, J_d^T W r
+  T Ej[6];         // J_j^T W J_d
+  T Ei[6];         // J_i^T W J_d = -Ad^T Ej
+  T J0[6], J1[6];  // rows of J_j
+  T r0, r1, w0, w1;
+  bool active;
+  int j;
+};
+
+// Linearise one edge.  rel: R (9), t (3), hat(t)R (9) of T_ji in LDS.
+template <typename T>
+__device__ inline void linearize_edge(const T* rel, T xb, T yb, T d, T tx, T ty, T w0,
+                                      T w1, T fx, T fy, T cx, T cy, T zmin, bool valid,
+                                      EdgeOut<T>& o) {
+  const T X = rel[0] * xb + rel[1] * yb + rel[2] + rel[9] * d;
+  const T Y = rel[3] * xb + rel[4] * yb + rel[5] + rel[10] * d;
+  const T Z = rel[6] * xb + rel[7] * yb + rel[8] + rel[11] * d;
+  o.active = valid && (Z > zmin);
+  const T iz = o.active ? T(1) / Z : T(0);
+  const T a = fx * iz, b = fy * iz;
+  const T c0 = -fx * X * iz * iz, c1 = -fy * Y * iz * iz;
+  o.w0 = o.active ? w0 : T(0);
+  o.w1 = o.active ? w1 : T(0);
+  o.r0 = o.active ? (fx * X * iz + cx - tx) : T(0);
+  o.r1 = o.active ? (fy * Y * iz + cy - ty) : T(0);
+  // rows of Pi [d I | -hat(p)]:  -Pi_c hat(p) = p x Pi_c
+  o.J0[0] = d * a;  o.J0[1] = T(0);  o.J0[2] = d * c0;
+  o.J0[3] = Y * c0; o.J0[4] = Z * a - X * c0; o.J0[5] = -Y * a;
+  o.J1[0] = T(0);   o.J1[1] = d * b; o.J1[2] = d * c1;
+  o.J1[3] = Y * c1 - Z * b; o.J1[4] = -X * c1; o.J1[5] = X * b;
+  const T jd0 = a * rel[9] + c0 * rel[11];
+  const T jd1 = b * rel[10] + c1 * rel[11];
+  const T g0 = o.w0 * jd0, g1 = o.w1 * jd1;
+  o.cd = g0 * jd0 + g1 * jd1;
+  o.wd = g0 * o.r0 + g1 * o.r1;
+#pragma unroll
+  for (int m = 0; m < 6; ++m) o.Ej[m] = g0 * o.J0[m] + g1 * o.J1[m];
+  // Ei = -Ad^T Ej with Ad^T = [[R^T, 0], [(hat(t)R)^T, R^T]]
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    o.Ei[m] = -(rel[m] * o.Ej[0] + rel[3 + m] * o.Ej[1] + rel[6 + m] * o.Ej[2]);
+    o.Ei[3 + m] = -(rel[12 + m] * o.Ej[0] + rel[15 + m] * o.Ej[1] + rel[18 + m] * o.Ej[2] +
+                    rel[m] * o.Ej[3] + rel[3 + m] * o.Ej[4] + rel[6 + m] * o.Ej[5]);
+  }
+}
+
+// Broadcast a value computed by thread 0 to the workgroup.
+__device__ inline int wg_bcast_status(const int32_t* status, int w, int* slot) {
+  if (threadIdx.x == 0) *slot = status[w];
+  __syncthreads();
+  const int s = *slot;
+  __syncthreads();
+  return s;
+}
+
+// Frame range of a chunk: union of its anchors' ranges.
+__device__ inline void chunk_range(const Params& P, const WinDesc& W, const ChunkDesc& cd,
+                                   int& f_lo, int& f_hi) {
+  const int32_t* ar = P.arange + 2 * W.frame_off;
+  f_lo = 1 << 30;
+  f_hi = -1;
+  for (int a = cd.a_lo; a < cd.a_hi; ++a) {
+    f_lo = min(f_lo, ar[2 * a]);
+    f_hi = max(f_hi, ar[2 * a + 1]);
+  }
+}
+
+// Relative poses T_ja for j in [lo, hi] into rel[(j - f_lo) * RELW].
+template <typename T>
+__device__ inline void load_relposes(const double* poses, int a, int lo, int hi, int f_lo, T* rel) {
+  for (int j = lo + (int)threadIdx.x; j <= hi; j += WG) {
+    double R[9], t[3];
+    relative_pose(poses + 7 * a, poses + 7 * j, R, t);
+    T* o = rel + (j - f_lo) * RELW;
+#pragma unroll
+    for (int m = 0; m < 9; ++m) o[m] = (T)R[m];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) o[9 + m] = (T)t[m];
+    // hat(t) R
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      o[12 + c] = (T)(-t[2] * R[3 + c] + t[1] * R[6 + c]);
+      o[15 + c] = (T)(t[2] * R[c] - t[0] * R[6 + c]);
+      o[18 + c] = (T)(-t[1] * R[c] + t[0] * R[3 + c]);
+    }
+  }
+}
+
+// A[p][q] of Ad(T_ji) = [[R, hat(t)R], [0, R]] from the LDS relative pose.
+template <typename T>
+__device__ inline T adj_at(const T* rel, int p, int q) {
+  if (p < 3) return q < 3 ? rel[3 * p + q] : rel[12 + 3 * p + (q - 3)];
+  return q < 3 ? T(0) : rel[3 * (p - 3) + (q - 3)];
+}
+
+template <typename T>
+__device__ inline const double* state_poses(const Params& P, const WinDesc& W, int iter) {
+  return iter == 0 ? P.poses_in + 7 * W.frame_off
+                   : P.pose_buf + (int64_t)(iter & 1) * 7 * P.n_frames_total + 7 * W.frame_off;
+}
+__device__ inline double state_depth(const Params& P, const WinDesc& W, int iter, int k) {
+  return iter == 0 ? P.patches_in[3 * (W.patch_off + k) + 2] : P.depth_buf[W.patch_off + k];
+}
+
+// Running sums of the tile elements across source frames.  FP32 assembly:
+// each source frame's contribution (its B / v entries minus its outer
+// products, formed in FP32) is added into FP64 registers `sh`, so no FP32
+// value ever carries the whole window's sum.  FP64 assembly: the matrix-core
+// accumulators themselves are the running sums (of the negated entries).
+
+// Lane segment width for a window's largest patch degree.
+__device__ inline int seg_width(int maxdeg) { return maxdeg <= 16 ? 16 : (maxdeg <= 32 ? 32 : 64); }
+
+template <typename T, int MAXT>
+__device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rcap) {
+  typedef typename AccT<T>::type Acc;
+  const AsmLayout L = asm_layout(Rcap, (int)sizeof(T));
+  T* rel = (T*)(smem + L.rel);
+  T* tbl = (T*)(smem + L.tbl);
+  T* G = (T*)(smem + L.G);
+  T* U = (T*)(smem + L.U);
+  int* tiles = (int*)(smem + L.tiles);
+  int* misc = (int*)(smem + L.misc);
+
+  const ChunkDesc cd = P.chunk[c];
+  const int w = cd.window;
+  const WinDesc W = P.win[w];
+  const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  const int st = wg_bcast_status(P.status, w, misc);
+  if (st != 0) {
+    if (tid == 0) { P.cstate[2 * c] = 0; P.cstate[2 * c + 1] = 0; }
+    return;
+  }
+  const int N = W.n_frames, nfix = W.n_fixed;
+  int f_lo, f_hi;
+  chunk_range(P, W, cd, f_lo, f_hi);
+  const int lo_free = max(f_lo, nfix);
+  const int D = (f_hi >= lo_free) ? 6 * (f_hi - lo_free + 1) : 0;
+  if (tid == 0) { P.cstate[2 * c] = lo_free; P.cstate[2 * c + 1] = D; }
+  double* part = P.partial + W.part_off + (int64_t)(c - W.chunk_off) * W.part_stride;
+  if (D == 0) return;   // every frame the chunk touches is fixed: nothing to assemble
+
+  const double* poses = state_poses<T>(P, W, iter);
+  const int32_t* plist = P.plist + W.patch_off;
+  const int32_t* acnt = P.acnt + W.frame_off + w;
+  const int32_t* ar = P.arange + 2 * W.frame_off;
+  const int32_t* cnt = P.cnt + W.patch_off;
+  const int32_t* ptr = P.ptr + W.patch_off;
+  const int32_t* csr = P.csr + W.edge_off;
+  const int32_t* jjw = P.jj + W.edge_off;
+  const T* tg = (const T*)P.targets + 2 * W.edge_off;
+  const T* wt = (const T*)P.weights + 2 * W.edge_off;
+  const T fx = (T)W.fx, fy = (T)W.fy, cx = (T)W.cx, cy = (T)W.cy;
+  const T zmin = (T)P.z_min, lam = (T)P.lambda;
+  const int SEG = seg_width(P.wmeta[4 * w]);
+  const int segs = 64 / SEG;                 // patches per wave pass
+  const int spw = SB / NWAVES;               // patch slots per wave per sub-batch
+  const int npass = (spw + segs - 1) / segs;
+  const int lseg = lane & (SEG - 1), sidx = lane / SEG;
+  const int maxdeg = P.wmeta[4 * w];
+  const int nch = (maxdeg + SEG - 1) / SEG;  // edge chunks per patch (1 unless degree > 64)
+
+  // lower-triangle tiles of the (D+1) x (D+1) product, row-major
+  const int Daug = D + 1;
+  const int T16 = (Daug + 15) / 16;
+  const int Ltot = (T16 * (T16 + 1)) / 2;
+  for (int t = tid; t < Ltot; t += WG) {
+    int ti = 0;
+    while (((ti + 1) * (ti + 2)) / 2 <= t) ++ti;
+    tiles[t] = (ti << 16) | (t - (ti * (ti + 1)) / 2);
+  }
+  const int per_pass = NWAVES * MAXT;
+  const int npasses_t = (Ltot + per_pass - 1) / per_pass;
+  bool nonfinite = false;
+
+  for (int tp = 0; tp < npasses_t; ++tp) {
+    const int p0 = tp * per_pass;
+    const int Lp = min(per_pass, Ltot - p0);
+    const int t_beg = p0 + (wv * Lp) / NWAVES, t_end = p0 + ((wv + 1) * Lp) / NWAVES;
+    const int ntl = t_end - t_beg;
+    Acc acc[MAXT];
+    double sh[4 * MAXT];
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) acc[t] = Acc{T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int t = 0; t < 4 * MAXT; ++t) sh[t] = 0.0;
+    __syncthreads();
+
+    for (int a = cd.a_lo; a < cd.a_hi; ++a) {
+      const int lo = ar[2 * a], hi = ar[2 * a + 1];
+      const int Ra = hi - lo + 1;
+      load_relposes<T>(poses, a, lo, hi, f_lo, rel);
+      for (int i = tid; i < NWAVES * Ra * TBL; i += WG) tbl[i] = T(0);
+      const int pb = acnt[a], pe = acnt[a + 1];
+      // nonzero column range of this anchor's u rows (plus the w column D)
+      const int nz_lo = 6 * (max(lo, lo_free) - lo_free);
+      const int nz_hi = (hi >= lo_free) ? 6 * (hi - lo_free + 1) : 0;
+      const bool a_free = a >= nfix;
+      T* mytbl = tbl + wv * Ra * TBL;
+
+      for (int sb0 = pb; sb0 < pe; sb0 += SB) {
+        const int nsb = min(SB, pe - sb0);
+        for (int i = tid; i < 16 * T16 * LDK; i += WG) U[i] = T(0);
+        __syncthreads();
+
+        // ---- linearise this wave's patches, one lane segment per patch
+        for (int ps = 0; ps < npass; ++ps) {
+          const int slot_in_wave = ps * segs + sidx;
+          const int slot = wv * spw + slot_in_wave;
+          const bool pv = (slot_in_wave < spw) && (slot < nsb);
+          const int k = pv ? plist[sb0 + slot] : 0;
+          const int deg = pv ? cnt[k] : 0;
+          const int base = pv ? ptr[k] : 0;
+          const double* pt = P.patches_in + 3 * (W.patch_off + k);
+          const T xb = (T)((pt[0] - W.cx) / W.fx);
+          const T yb = (T)((pt[1] - W.cy) / W.fy);
+          const T dk = (T)state_depth(P, W, iter, k);
+
+          T s_cd = 0, s_wd = 0, s_ei[6] = {0, 0, 0, 0, 0, 0};
+          EdgeOut<T> eo;
+          for (int ch = 0; ch < nch; ++ch) {
+            const int es = ch * SEG + lseg;
+            const bool has = es < deg;
+            const int e = has ? csr[base + es] : 0;
+            const int j = has ? jjw[e] : a;
+            const T t0 = has ? tg[2 * e] : T(0), t1 = has ? tg[2 * e + 1] : T(0);
+            const T w0 = has ? wt[2 * e] : T(0), w1 = has ? wt[2 * e + 1] : T(0);
+            if (has && !(__builtin_isfinite(t0) && __builtin_isfinite(t1) &&
+                         __builtin_isfinite(w0) && __builtin_isfinite(w1)))
+              nonfinite = true;
+            linearize_edge<T>(rel + (j - f_lo) * RELW, xb, yb, dk, t0, t1, w0, w1, fx, fy, cx,
+                              cy, zmin, has && (j != a), eo);
+            eo.j = j;
+            s_cd += eo.cd;
+            s_wd += eo.wd;
+#pragma unroll
+            for (int m = 0; m < 6; ++m) s_ei[m] += eo.Ei[m];
+            // pair tables Q_aj (21) and V_aj (6); segments of a wave take turns,
+            // and duplicate (k, j) edges inside a segment are added one lane at a time
+            const int jprev = __shfl_up(j, 1, 64);
+            const bool dup = eo.active && lseg > 0 && es - 1 < deg && jprev == j;
+            const bool anydup = __any(dup);
+            T* tb = mytbl + (j - lo) * TBL;
+            for (int sgi = 0; sgi < segs; ++sgi) {
+              if (!anydup) {
+                if (sidx == sgi && eo.active) {
+                  int q = 0;
+#pragma unroll
+                  for (int m = 0; m < 6; ++m)
+#pragma unroll
+                    for (int n = m; n < 6; ++n, ++q)
+                      tb[q] += eo.w0 * eo.J0[m] * eo.J0[n] + eo.w1 * eo.J1[m] * eo.J1[n];
+#pragma unroll
+                  for (int m = 0; m < 6; ++m)
+                    tb[21 + m] += eo.w0 * eo.r0 * eo.J0[m] + eo.w1 * eo.r1 * eo.J1[m];
+                }
+              } else {
+                for (int ln = 0; ln < SEG; ++ln) {
+                  if (sidx == sgi && lseg == ln && eo.active) {
+                    int q = 0;
+#pragma unroll
+                    for (int m = 0; m < 6; ++m)
+#pragma unroll
+                      for (int n = m; n < 6; ++n, ++q)
+                        tb[q] += eo.w0 * eo.J0[m] * eo.J0[n] + eo.w1 * eo.J1[m] * eo.J1[n];
+#pragma unroll
+                    for (int m = 0; m < 6; ++m)
+                      tb[21 + m] += eo.w0 * eo.r0 * eo.J0[m] + eo.w1 * eo.r1 * eo.J1[m];
+                  }
+                }
+              }
+            }
+          }
+          const T Ck = lam + seg_sum(s_cd, SEG);
+          const T Wk = seg_sum(s_wd, SEG);
+          T Eik[6];
+#pragma unroll
+          for (int m = 0; m < 6; ++m) Eik[m] = seg_sum(s_ei[m], SEG);
+          const T rs = T(1) / __builtin_sqrt(Ck);
+          // staged row u_k: E_jk / sqrt(C_k) at target columns, E_ik / sqrt(C_k) at
+          // the anchor's columns, w_k / sqrt(C_k) at column D
+          for (int ch = 0; ch < nch; ++ch) {
+            const int es = ch * SEG + lseg;
+            if (nch > 1) {   // degree above 64: recompute each lane chunk
+              const bool has = es < deg;
+              const int e = has ? csr[base + es] : 0;
+              const int j = has ? jjw[e] : a;
+              linearize_edge<T>(rel + (j - f_lo) * RELW, xb, yb, dk,
+                                has ? tg[2 * e] : T(0), has ? tg[2 * e + 1] : T(0),
+                                has ? wt[2 * e] : T(0), has ? wt[2 * e + 1] : T(0), fx, fy,
+                                cx, cy, zmin, has && (j != a), eo);
+              eo.j = has ? j : a;
+            }
+            const int j = eo.j;
+            const int jprev = __shfl_up(j, 1, 64);
+            const bool dup = eo.active && lseg > 0 && es - 1 < deg && jprev == j;
+            const bool anydup = __any(dup);
+            T* ucol = U + (6 * (j - lo_free)) * LDK + slot;
+            if (!anydup) {
+              if (pv && eo.active && j >= lo_free) {
+#pragma unroll
+                for (int m = 0; m < 6; ++m) ucol[m * LDK] += eo.Ej[m] * rs;
+              }
+            } else {
+              for (int ln = 0; ln < SEG; ++ln)
+                if (lseg == ln && pv && eo.active && j >= lo_free) {
+#pragma unroll
+                  for (int m = 0; m < 6; ++m) ucol[m * LDK] += eo.Ej[m] * rs;
+                }
+            }
+          }
+          if (pv && lseg == 0) {
+            if (a_free) {
+              T* ua = U + (6 * (a - lo_free)) * LDK + slot;
+#pragma unroll
+              for (int m = 0; m < 6; ++m) ua[m * LDK] = Eik[m] * rs;
+            }
+            U[D * LDK + slot] = Wk * rs;
+          }
+        }
+        __syncthreads();
+
+        // ---- matrix-core outer products of the staged rows
+        {
+          const int l16 = lane & 15, g = lane >> 4;
+#pragma unroll
+          for (int t = 0; t < MAXT; ++t) {
+            if (t < ntl) {
+              const int code = tiles[t_beg + t];
+              const int ti = code >> 16, tj = code & 0xffff;
+              const bool rows_nz = (16 * ti < nz_hi && 16 * ti + 16 > nz_lo) ||
+                                   (16 * ti <= D && D < 16 * ti + 16);
+              const bool cols_nz = (16 * tj < nz_hi && 16 * tj + 16 > nz_lo) ||
+                                   (16 * tj <= D && D < 16 * tj + 16);
+              if (rows_nz && cols_nz) {
+                const T* ua = U + (16 * ti + l16) * LDK + 4 * g;
+                const T* ub = U + (16 * tj + l16) * LDK + 4 * g;
+#pragma unroll
+                for (int kb = 0; kb < SB / 16; ++kb) {
+#pragma unroll
+                  for (int s = 0; s < 4; ++s)
+                    acc[t] = mfma16(ua[16 * kb + s], ub[16 * kb + s], acc[t]);
+                }
+              }
+            }
+          }
+        }
+        __syncthreads();
+      }
+
+      // ---- pair blocks of this anchor
+      for (int i = tid; i < Ra * TBL; i += WG) {
+        T sum = 0;
+        for (int x = 0; x < NWAVES; ++x) sum += tbl[x * Ra * TBL + i];
+        tbl[i] = sum;
+      }
+      __syncthreads();
+      // G_j = A_j^T Q_j
+      for (int i = tid; i < Ra * 36; i += WG) {
+        const int jr = i / 36, m = (i % 36) / 6, n = i % 6;
+        const T* rj = rel + (lo + jr - f_lo) * RELW;
+        const T* Q = tbl + jr * TBL;
+        T sum = 0;
+#pragma unroll
+        for (int p = 0; p < 6; ++p) sum += adj_at(rj, p, m) * Q[sym6(p, n)];
+        G[i] = sum;
+      }
+      __syncthreads();
+      // anchor block sum_j A^T Q A and anchor gradient -sum_j A^T V (targets in
+      // fixed frames included: J_i = -J_j Ad(T_ji) whatever frame j is)
+      T* AQA = G + Ra * 36;
+      if (a_free) {
+        for (int i = tid; i < 42; i += WG) {
+          T sum = 0;
+          if (i < 36) {
+            const int m = i / 6, n = i % 6;
+            for (int jr = 0; jr < Ra; ++jr) {
+              if (lo + jr == a) continue;
+              const T* rj = rel + (lo + jr - f_lo) * RELW;
+#pragma unroll
+              for (int q2 = 0; q2 < 6; ++q2) sum += G[jr * 36 + m * 6 + q2] * adj_at(rj, q2, n);
+            }
+          } else {
+            const int m = i - 36;
+            for (int jr = 0; jr < Ra; ++jr) {
+              if (lo + jr == a) continue;
+              const T* rj = rel + (lo + jr - f_lo) * RELW;
+              const T* Q = tbl + jr * TBL;
+#pragma unroll
+              for (int p = 0; p < 6; ++p) sum -= adj_at(rj, p, m) * Q[21 + p];
+            }
+          }
+          AQA[i] = sum;
+        }
+      }
+      __syncthreads();
+      // Each lane folds this anchor's B / v entries of its tile elements and
+      // the staged outer products into its FP64 running sums:
+      //   (j,j) += Q_j, (a,j) -= A^T Q_j, (a,a) += sum A^T Q A, v_j += V_j,
+      //   v_a -= sum A^T V, and -= sum_k u_k u_k^T.
+      {
+        const int l16 = lane & 15, g = lane >> 4;
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) {
+          if (t < ntl) {
+            const int code = tiles[t_beg + t];
+            const int ti = code >> 16, tj = code & 0xffff;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * ti + acc_row(T(0), g, r), col = 16 * tj + l16;
+              T val = 0;
+              if (col < D && (row < D ? col <= row : row == D)) {
+                const int fc = lo_free + col / 6, n = col % 6;
+                if (row == D) {
+                  if (fc == a) val = AQA[36 + n];
+                  else if (fc >= lo && fc <= hi) val = tbl[(fc - lo) * TBL + 21 + n];
+                } else {
+                  const int fr = lo_free + row / 6, m = row % 6;
+                  if (fr == fc) {
+                    if (fr == a) val = AQA[m * 6 + n];
+                    else if (fr >= lo && fr <= hi) val = tbl[(fr - lo) * TBL + sym6(m, n)];
+                  } else if (fr == a && fc >= lo && fc <= hi) {
+                    val = -G[(fc - lo) * 36 + m * 6 + n];
+                  } else if (fc == a && fr >= lo && fr <= hi) {
+                    val = -G[(fr - lo) * 36 + n * 6 + m];
+                  }
+                }
+              }
+              if constexpr (sizeof(T) == 4) {
+                sh[t * 4 + r] += (double)val - (double)acc[t][r];
+                acc[t][r] = T(0);
+              } else {
+                acc[t][r] -= val;
+              }
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+
+    // ---- chunk partial: lower triangle of S and s, FP64
+    {
+      const int l16 = lane & 15, g = lane >> 4;
+#pragma unroll
+      for (int t = 0; t < MAXT; ++t) {
+        if (t < ntl) {
+          const int code = tiles[t_beg + t];
+          const int ti = code >> 16, tj = code & 0xffff;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * ti + acc_row(T(0), g, r), col = 16 * tj + l16;
+            const double v = (sizeof(T) == 4) ? sh[t * 4 + r] : -(double)acc[t][r];
+            if (row < D && col <= row) part[row * D + col] = v;
+            else if (row == D && col < D) part[D * D + col] = v;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (nonfinite) atomicOr(&P.status[w], W_NONFINITE);
+}
+
+}  // namespace dpba

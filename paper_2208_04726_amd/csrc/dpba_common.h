@@ -1,0 +1,194 @@
+// Shared definitions of the gfx950 bundle-adjustment kernels: launch
+// constants, window / chunk descriptors, workspace layout, wave helpers and
+// the FP64 SE(3) helpers used for relative poses and the retraction.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpba {
+
+constexpr int WG = 512;            // threads per workgroup (8 wave64s)
+constexpr int NWAVES = WG / 64;
+constexpr int RMAX = 64;           // frames per window (and per chunk range)
+constexpr int NCHOL_MAX = 126;     // reduced pose system held in LDS (21 free frames)
+constexpr int TBL = 27;            // pair table entries: 21 (6x6 sym) + 6
+
+// status bits (match include/dpba.h)
+constexpr int W_NOT_SPD = 1;
+constexpr int W_NONFINITE = 2;
+constexpr int W_BAD_INDEX = 4;
+
+// ---------------------------------------------------------------------------
+// Descriptors, built on the host for every call and copied to the device.
+struct WinDesc {
+  int64_t frame_off, patch_off, edge_off;
+  int32_t n_frames, n_patches, n_edges, n_fixed;
+  double fx, fy, cx, cy;
+  int32_t chunk_off, n_chunks;    // chunks of this window in the chunk table
+  int64_t part_off;               // first element of this window's partials
+  int64_t part_stride;            // elements per chunk partial (D*D + D, D = 6*(N-nfix))
+};
+
+struct ChunkDesc {
+  int32_t window, a_lo, a_hi, pad;  // anchor frames [a_lo, a_hi) of the window
+};
+
+struct Params {
+  const WinDesc* win;
+  const ChunkDesc* chunk;
+  int32_t n_windows, n_chunks;
+  int32_t iterations;
+  double lambda, z_min;
+  // problem (caller buffers)
+  const double* poses_in;
+  const double* patches_in;
+  const int32_t* anchor;
+  const int32_t* kk;
+  const int32_t* jj;
+  const void* targets;
+  const void* weights;
+  double* poses_out;
+  double* depth_out;
+  // workspace
+  int32_t* status;      // [W]
+  int32_t* wmeta;       // [W*4]: max degree, edges-sorted flag, anchors-sorted flag
+  int32_t* cnt;         // [P] edges per patch
+  int32_t* ptr;         // [P] first CSR slot of each patch (window-local)
+  int32_t* fill;        // [P] scatter cursor
+  int32_t* acnt;        // [F+W] patches per anchor -> offsets
+  int32_t* afill;       // [F] scatter cursor
+  int32_t* plist;       // [P] patches sorted by (anchor, index), window-local
+  int32_t* csr;         // [E] edges sorted by (patch, target, index), window-local
+  int32_t* arange;      // [F*2] frame range touched by each anchor's patches
+  int32_t* cstate;      // [C*2] chunk: first free frame of its range, D
+  double* partial;      // chunk partials of S (lower, D x D) and s (D), FP64
+  double* dxi;          // [F*6] pose steps
+  double* pose_buf;     // [2][F*7] pose state double buffer
+  double* depth_buf;    // [P] depth state
+  int64_t n_frames_total;
+};
+
+// ---------------------------------------------------------------------------
+// wave / workgroup helpers
+__device__ inline int lane_id() { return threadIdx.x & 63; }
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+template <typename T>
+__device__ inline T seg_sum(T v, int seg) {
+  // butterfly all-reduce inside aligned power-of-two lane groups; every lane
+  // of a group ends with the bitwise-identical sum
+  for (int o = seg >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline bool isfinite_d(double x) { return __builtin_isfinite(x); }
+__device__ inline bool isfinite_f(float x) { return __builtin_isfinite(x); }
+
+// Exclusive scan of data[0..n) in place by the whole workgroup; returns the
+// total.  lds must hold WG ints.  All threads must call it.
+__device__ inline int wg_exclusive_scan(int32_t* data, int n, int* lds) {
+  const int tid = threadIdx.x;
+  const int per = (n + WG - 1) / WG;
+  const int b = tid * per, e = min(n, b + per);
+  int s = 0;
+  for (int i = b; i < e; ++i) s += data[i];
+  lds[tid] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over WG partial sums
+  for (int o = 1; o < WG; o <<= 1) {
+    int v = (tid >= o) ? lds[tid - o] : 0;
+    __syncthreads();
+    lds[tid] += v;
+    __syncthreads();
+  }
+  int run = lds[tid] - s;
+  const int total = lds[WG - 1];
+  for (int i = b; i < e; ++i) {
+    int c = data[i];
+    data[i] = run;
+    run += c;
+  }
+  __syncthreads();
+  return total;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 SE(3) helpers.  Pose 7-vector: t (3), unit quaternion (x, y, z, w).
+__device__ inline void quat_to_rot(const double* q, double* R) {
+  const double x = q[0], y = q[1], z = q[2], w = q[3];
+  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - z * w);     R[2] = 2 * (x * z + y * w);
+  R[3] = 2 * (x * y + z * w);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - x * w);
+  R[6] = 2 * (x * z - y * w);     R[7] = 2 * (y * z + x * w);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+// Relative pose T_ji = T_j T_i^{-1}: R = R_j R_i^T, t = t_j - R t_i.
+__device__ inline void relative_pose(const double* pi, const double* pj, double* R, double* t) {
+  double Ri[9], Rj[9];
+  quat_to_rot(pi + 3, Ri);
+  quat_to_rot(pj + 3, Rj);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      R[3 * a + b] = Rj[3 * a] * Ri[3 * b] + Rj[3 * a + 1] * Ri[3 * b + 1] + Rj[3 * a + 2] * Ri[3 * b + 2];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    t[a] = pj[a] - (R[3 * a] * pi[0] + R[3 * a + 1] * pi[1] + R[3 * a + 2] * pi[2]);
+}
+
+// T <- Exp(xi) T, xi = (rho, phi).  Exp(xi) = (R(phi), V(phi) rho) with
+// Rodrigues' R = I + A K + B K^2, V = I + B K + C K^2, K = hat(phi); the
+// rotation is applied to the quaternion as q_exp (x) q, then renormalised.
+// Series forms of A, B, C and of the half-angle terms below theta = 1e-2.
+__device__ inline void retract_left(const double* xi, const double* pin, double* pout) {
+  const double rx = xi[0], ry = xi[1], rz = xi[2];
+  const double px = xi[3], py = xi[4], pz = xi[5];
+  const double th2 = px * px + py * py + pz * pz;
+  double A, B, C, hs, hc;
+  if (th2 < 1e-4) {
+    A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0 - th2 * th2 * th2 / 5040.0;
+    B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0 - th2 * th2 * th2 / 40320.0;
+    C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0 - th2 * th2 * th2 / 362880.0;
+    hs = 0.5 - th2 / 48.0 + th2 * th2 / 3840.0;
+    hc = 1.0 - th2 / 8.0 + th2 * th2 / 384.0;
+  } else {
+    const double th = sqrt(th2);
+    const double s = sin(th), c = cos(th);
+    A = s / th;
+    B = (1.0 - c) / th2;
+    C = (th - s) / (th2 * th);
+    hs = sin(0.5 * th) / th;
+    hc = cos(0.5 * th);
+  }
+  // K = hat(phi), K2 = K K
+  const double K[9] = {0, -pz, py, pz, 0, -px, -py, px, 0};
+  double K2[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      K2[3 * a + b] = K[3 * a] * K[b] + K[3 * a + 1] * K[3 + b] + K[3 * a + 2] * K[6 + b];
+  double R[9], V[9];
+#pragma unroll
+  for (int m = 0; m < 9; ++m) {
+    const double I = (m == 0 || m == 4 || m == 8) ? 1.0 : 0.0;
+    R[m] = I + A * K[m] + B * K2[m];
+    V[m] = I + B * K[m] + C * K2[m];
+  }
+  const double rho[3] = {rx, ry, rz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    pout[a] = R[3 * a] * pin[0] + R[3 * a + 1] * pin[1] + R[3 * a + 2] * pin[2] +
+              V[3 * a] * rho[0] + V[3 * a + 1] * rho[1] + V[3 * a + 2] * rho[2];
+  // q_exp = (hs * phi, hc);  q' = q_exp (x) q  (Hamilton)
+  const double ax = hs * px, ay = hs * py, az = hs * pz, aw = hc;
+  const double bx = pin[3], by = pin[4], bz = pin[5], bw = pin[6];
+  double qx = aw * bx + bw * ax + (ay * bz - az * by);
+  double qy = aw * by + bw * ay + (az * bx - ax * bz);
+  double qz = aw * bz + bw * az + (ax * by - ay * bx);
+  double qw = aw * bw - (ax * bx + ay * by + az * bz);
+  const double inv = 1.0 / sqrt(qx * qx + qy * qy + qz * qz + qw * qw);
+  pout[3] = qx * inv; pout[4] = qy * inv; pout[5] = qz * inv; pout[6] = qw * inv;
+}
+
+}  // namespace dpba

@@ -1,0 +1,79 @@
+"""ctypes view of the C ABI in include/dpba.h (libdpba.so, built for gfx950).
+
+Argument marshalling only: every step of the solve runs in the HIP kernels of
+the library.  Importing this module does not load the library; the first call
+to `lib()` does, and raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdpba.so")
+
+BA_OK, BA_E_INVAL, BA_E_CAPACITY, BA_E_HIP, BA_E_STATE = 0, -1, -2, -3, -4
+BA_PREC_FP64, BA_PREC_FP32 = 0, 1
+BA_SCHED_AUTO, BA_SCHED_SPLIT, BA_SCHED_FUSED = 0, 1, 2
+BA_W_OK, BA_W_NOT_SPD, BA_W_NONFINITE, BA_W_BAD_INDEX = 0, 1, 2, 4
+
+EXPORTED = ("ba_create", "ba_solve", "ba_backward", "ba_status", "ba_last_error",
+            "ba_destroy", "ba_debug_reduced_system", "ba_debug_mfma")
+
+
+class BAConfig(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("lambda_", ctypes.c_double), ("z_min", ctypes.c_double),
+                ("schedule", ctypes.c_int32), ("max_windows", ctypes.c_int32),
+                ("max_frames_per_window", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_frames", ctypes.c_int64), ("max_patches", ctypes.c_int64),
+                ("max_edges", ctypes.c_int64)]
+
+
+class BAProblem(ctypes.Structure):
+    _fields_ = [("n_windows", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("frame_off", ctypes.c_void_p), ("patch_off", ctypes.c_void_p),
+                ("edge_off", ctypes.c_void_p), ("n_fixed", ctypes.c_void_p),
+                ("intrinsics", ctypes.c_void_p),
+                ("poses_in", ctypes.c_void_p), ("patches_in", ctypes.c_void_p),
+                ("anchor", ctypes.c_void_p), ("kk", ctypes.c_void_p), ("jj", ctypes.c_void_p),
+                ("targets", ctypes.c_void_p), ("weights", ctypes.c_void_p),
+                ("poses_out", ctypes.c_void_p), ("depth_out", ctypes.c_void_p)]
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises RuntimeError when it is missing."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                               "(the solver has no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i32p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)
+        L.ba_create.argtypes = [ctypes.POINTER(BAConfig), ctypes.POINTER(vp)]
+        L.ba_create.restype = ctypes.c_int
+        L.ba_solve.argtypes = [vp, ctypes.POINTER(BAProblem), vp]
+        L.ba_solve.restype = ctypes.c_int
+        L.ba_backward.argtypes = [vp, ctypes.POINTER(BAProblem), vp, vp, vp, vp, vp]
+        L.ba_backward.restype = ctypes.c_int
+        L.ba_status.argtypes = [vp, i32p]
+        L.ba_status.restype = ctypes.c_int
+        L.ba_last_error.argtypes = [vp]
+        L.ba_last_error.restype = ctypes.c_char_p
+        L.ba_destroy.argtypes = [vp]
+        L.ba_destroy.restype = None
+        L.ba_debug_reduced_system.argtypes = [vp, ctypes.POINTER(BAProblem), i32, vp, vp, vp]
+        L.ba_debug_reduced_system.restype = ctypes.c_int
+        L.ba_debug_mfma.argtypes = [i32, vp, vp, vp, vp]
+        L.ba_debug_mfma.restype = ctypes.c_int
+        _LIB = L
+    return _LIB
+
+
+class BAError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"dpba error {code}: {msg}")
+        self.code = code

@@ -1,0 +1,193 @@
+"""Python front end of the gfx950 bundle-adjustment library.
+
+`Solver` owns a library handle; `Batch` holds one call's device buffers
+(torch tensors on the GPU) and host offsets.  PyTorch provides device memory
+and the stream only; the solve runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import native
+from .native import BAConfig, BAError, BAProblem
+
+PRECISIONS = {"fp64": native.BA_PREC_FP64, "fp32": native.BA_PREC_FP32}
+SCHEDULES = {"auto": native.BA_SCHED_AUTO, "split": native.BA_SCHED_SPLIT,
+             "fused": native.BA_SCHED_FUSED}
+
+
+@dataclasses.dataclass
+class Batch:
+    """Device buffers of a batch of windows (layout of include/dpba.h)."""
+    frame_off: np.ndarray      # host int64 [W+1]
+    patch_off: np.ndarray
+    edge_off: np.ndarray
+    n_fixed: np.ndarray        # host int32 [W]
+    intrinsics: np.ndarray     # host f64 [W,4]
+    poses: torch.Tensor        # dev f64 [F,7]
+    patches: torch.Tensor      # dev f64 [P,3]
+    anchor: torch.Tensor       # dev int32 [P]
+    kk: torch.Tensor           # dev int32 [E]
+    jj: torch.Tensor           # dev int32 [E]
+    targets: torch.Tensor      # dev f32/f64 [E,2]
+    weights: torch.Tensor      # dev f32/f64 [E,2]
+
+    @property
+    def n_windows(self) -> int:
+        return int(len(self.n_fixed))
+
+    @property
+    def totals(self):
+        return int(self.frame_off[-1]), int(self.patch_off[-1]), int(self.edge_off[-1])
+
+
+def make_batch(windows: Sequence, precision: str = "fp32", device="cuda") -> Batch:
+    """Concatenate synth.Window-like objects into device buffers."""
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    W = len(windows)
+    fo = np.zeros(W + 1, np.int64)
+    po = np.zeros(W + 1, np.int64)
+    eo = np.zeros(W + 1, np.int64)
+    for i, w in enumerate(windows):
+        fo[i + 1] = fo[i] + w.poses.shape[0]
+        po[i + 1] = po[i] + w.patches.shape[0]
+        eo[i + 1] = eo[i] + w.kk.shape[0]
+
+    def cat(arrs, dtype):
+        if len(arrs) == 0:
+            return np.zeros(0, dtype)
+        return np.concatenate([np.asarray(a, dtype) for a in arrs], 0)
+
+    to = lambda a, d: torch.as_tensor(a).to(device=device, dtype=d).contiguous()
+    return Batch(
+        frame_off=fo, patch_off=po, edge_off=eo,
+        n_fixed=np.asarray([w.n_fixed for w in windows], np.int32),
+        intrinsics=np.ascontiguousarray(np.stack([np.asarray(w.intrinsics, np.float64) for w in windows])
+                                        if W else np.zeros((0, 4))),
+        poses=to(cat([w.poses for w in windows], np.float64).reshape(-1, 7), torch.float64),
+        patches=to(cat([w.patches for w in windows], np.float64).reshape(-1, 3), torch.float64),
+        anchor=to(cat([w.anchor for w in windows], np.int32), torch.int32),
+        kk=to(cat([w.kk for w in windows], np.int32), torch.int32),
+        jj=to(cat([w.jj for w in windows], np.int32), torch.int32),
+        targets=to(cat([w.targets for w in windows], np.float64).reshape(-1, 2), dt),
+        weights=to(cat([w.weights for w in windows], np.float64).reshape(-1, 2), dt))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None or t.numel() == 0 else ctypes.c_void_p(t.data_ptr())
+
+
+def _host(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Solver:
+    """A library handle with fixed capacities.
+
+    precision: "fp32" (FP32 linearisation and assembly, FP64 Cholesky and
+    back-substitution) or "fp64".  schedule: "auto", "split" (one launch per
+    stage) or "fused" (one persistent launch)."""
+
+    def __init__(self, precision: str = "fp32", iterations: int = 2, lam: float = 1e-4,
+                 z_min: float = 0.1, schedule: str = "auto", max_windows: int = 1,
+                 max_frames_per_window: int = 22, max_frames: Optional[int] = None,
+                 max_patches: int = 4096, max_edges: int = 65536):
+        self.lib = native.lib()
+        self.precision = precision
+        cfg = BAConfig()
+        cfg.precision = PRECISIONS[precision]
+        cfg.iterations = iterations
+        cfg.lambda_ = lam
+        cfg.z_min = z_min
+        cfg.schedule = SCHEDULES[schedule]
+        cfg.max_windows = max_windows
+        cfg.max_frames_per_window = max_frames_per_window
+        cfg.max_frames = max_frames if max_frames is not None else max_windows * max_frames_per_window
+        cfg.max_patches = max_patches
+        cfg.max_edges = max_edges
+        self.cfg = cfg
+        h = ctypes.c_void_p()
+        r = self.lib.ba_create(ctypes.byref(cfg), ctypes.byref(h))
+        if r != native.BA_OK:
+            raise BAError(r, "ba_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.ba_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, r: int):
+        if r != native.BA_OK:
+            raise BAError(r, self.lib.ba_last_error(self.h).decode())
+
+    def _problem(self, b: Batch, poses_out, depth_out) -> BAProblem:
+        p = BAProblem()
+        p.n_windows = b.n_windows
+        self._keep = [np.ascontiguousarray(b.frame_off, np.int64), np.ascontiguousarray(b.patch_off, np.int64),
+                      np.ascontiguousarray(b.edge_off, np.int64), np.ascontiguousarray(b.n_fixed, np.int32),
+                      np.ascontiguousarray(b.intrinsics, np.float64)]
+        p.frame_off, p.patch_off, p.edge_off, p.n_fixed, p.intrinsics = [_host(a) for a in self._keep]
+        p.poses_in, p.patches_in = _ptr(b.poses), _ptr(b.patches)
+        p.anchor, p.kk, p.jj = _ptr(b.anchor), _ptr(b.kk), _ptr(b.jj)
+        p.targets, p.weights = _ptr(b.targets), _ptr(b.weights)
+        p.poses_out, p.depth_out = _ptr(poses_out), _ptr(depth_out)
+        return p
+
+    def solve(self, b: Batch, poses_out: Optional[torch.Tensor] = None,
+              depth_out: Optional[torch.Tensor] = None, stream: Optional[torch.cuda.Stream] = None):
+        """Enqueue the solve on `stream` (default: torch's current stream).
+        Returns (poses_out [F,7] f64, depth_out [P] f64) device tensors."""
+        F, P, _ = b.totals
+        dev = b.poses.device
+        if poses_out is None:
+            poses_out = torch.empty((F, 7), dtype=torch.float64, device=dev)
+        if depth_out is None:
+            depth_out = torch.empty((P,), dtype=torch.float64, device=dev)
+        p = self._problem(b, poses_out, depth_out)
+        s = (stream or torch.cuda.current_stream(dev)).cuda_stream
+        self._check(self.lib.ba_solve(self.h, ctypes.byref(p), ctypes.c_void_p(s)))
+        self._last_w = b.n_windows
+        return poses_out, depth_out
+
+    def status(self) -> np.ndarray:
+        """Per-window BA_W_* bits of the last call (waits for its stream)."""
+        out = np.zeros(int(self.cfg.max_windows), np.int32)
+        self._check(self.lib.ba_status(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return out[:int(getattr(self, "_last_w", 0))]
+
+    def reduced_system(self, b: Batch, window: int = 0, stream=None):
+        """(S [n,n], s [n]) of `window` at the input state, from the GPU kernels."""
+        N = int(b.frame_off[window + 1] - b.frame_off[window])
+        n = 6 * (N - int(b.n_fixed[window]))
+        dev = b.poses.device
+        S = torch.zeros((n, n), dtype=torch.float64, device=dev)
+        s = torch.zeros((n,), dtype=torch.float64, device=dev)
+        F, P, _ = b.totals
+        scratch_p = torch.empty((max(F, 1), 7), dtype=torch.float64, device=dev)
+        scratch_d = torch.empty((max(P, 1),), dtype=torch.float64, device=dev)
+        p = self._problem(b, scratch_p, scratch_d)
+        st = (stream or torch.cuda.current_stream(dev)).cuda_stream
+        self._check(self.lib.ba_debug_reduced_system(self.h, ctypes.byref(p), window,
+                                                     _ptr(S), _ptr(s), ctypes.c_void_p(st)))
+        return S, s
+
+
+def capacities_for(windows: Sequence, slack: float = 1.0):
+    """Capacities (keyword arguments of Solver) that fit `windows`."""
+    return dict(max_windows=max(1, len(windows)),
+                max_frames_per_window=max([w.poses.shape[0] for w in windows] + [1]),
+                max_frames=max(1, sum(w.poses.shape[0] for w in windows)),
+                max_patches=max(1, int(slack * sum(w.patches.shape[0] for w in windows))),
+                max_edges=max(1, int(slack * sum(w.kk.shape[0] for w in windows))))

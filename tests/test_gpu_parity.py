@@ -1,0 +1,140 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ba_oracle as O
+from paper_2208_04726_amd import synth
+from tests.gpu_util import compare, need_gpu, solve_gpu
+
+pytestmark = pytest.mark.gpu
+
+# Tolerances: FP64 path 1e-6 m / 1e-4 deg (expected near rounding);
+# FP32 assembly with FP64 Cholesky: 1e-4 m / 1e-2 deg; inverse depth relative.
+FP64_TOL = (1e-6, 1e-4, 1e-6)
+FP32_TOL = (1e-4, 1e-2, 1e-3)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_mfma_lane_layout(precision):
+    need_gpu()
+    from paper_2208_04726_amd import native
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    A = torch.randn(16, 4, dtype=dt, device="cuda")
+    B = torch.randn(4, 16, dtype=dt, device="cuda")
+    D = torch.zeros(16, 16, dtype=dt, device="cuda")
+    prec = native.BA_PREC_FP32 if precision == "fp32" else native.BA_PREC_FP64
+    r = native.lib().ba_debug_mfma(prec, A.data_ptr(), B.data_ptr(), D.data_ptr(), None)
+    assert r == 0
+    torch.cuda.synchronize()
+    ref = (A.double() @ B.double()).cpu()
+    tol = 1e-5 if precision == "fp32" else 1e-13
+    assert torch.allclose(D.double().cpu(), ref, atol=tol, rtol=tol)
+
+
+@pytest.mark.parametrize("precision,win", [("fp64", 0), ("fp32", 1)])
+def test_reduced_system_matches_oracle(precision, win):
+    need_gpu()
+    from paper_2208_04726_amd.solver import Solver, make_batch, capacities_for
+    w = synth.plain_fp64_window(win) if precision == "fp64" else synth.method_scale_window(win)
+    s = Solver(precision=precision, **capacities_for([w]))
+    S, sv = s.reduced_system(make_batch([w], precision))
+    torch.cuda.synchronize()
+    S_ref, s_ref = O.reduced_system(w)
+    S, sv = S.cpu().numpy(), sv.cpu().numpy()
+    rel = 1e-10 if precision == "fp64" else 2e-4
+    print("S rel err", np.abs(S - S_ref).max() / np.abs(S_ref).max(),
+          "s rel err", np.abs(sv - s_ref).max() / np.abs(s_ref).max())
+    assert np.abs(S - S_ref).max() <= rel * np.abs(S_ref).max()
+    assert np.abs(sv - s_ref).max() <= rel * np.abs(s_ref).max()
+    s.close()
+
+
+@pytest.mark.parametrize("schedule", ["split", "fused"])
+def test_fp64_small_window_matches_oracle(schedule):
+    need_gpu()
+    wins = [synth.plain_fp64_window(i) for i in range(4)]
+    out, st = solve_gpu(wins, "fp64", schedule)
+    assert (st == 0).all()
+    for w, (p, d) in zip(wins, out):
+        pr, dr_ = O.solve(w)
+        dc, drot, dd = compare(p, d, pr, dr_)
+        print(schedule, "fp64 err m", dc, "deg", drot, "depth rel", dd)
+        assert dc < FP64_TOL[0] and drot < FP64_TOL[1] and dd < FP64_TOL[2]
+
+
+@pytest.mark.parametrize("schedule", ["split", "fused"])
+def test_fp32_method_scale_matches_oracle(schedule):
+    need_gpu()
+    wins = [synth.method_scale_window(i) for i in range(2)]
+    out, st = solve_gpu(wins, "fp32", schedule)
+    assert (st == 0).all()
+    for w, (p, d) in zip(wins, out):
+        pr, dr_ = O.solve(w)
+        dc, drot, dd = compare(p, d, pr, dr_)
+        print(schedule, "fp32 err m", dc, "deg", drot, "depth rel", dd)
+        assert dc < FP32_TOL[0] and drot < FP32_TOL[1] and dd < FP32_TOL[2]
+
+
+def test_exact_correspondence_converges_on_gpu():
+    need_gpu()
+    w = synth.make_window(8, 16, 3, seed=[14], exact=True)
+    out, st = solve_gpu([w], "fp64", "split", iterations=10)
+    p, d = out[0]
+    assert st[0] == 0
+    dc, dr = synth.pose_errors(p, w.poses_gt)
+    assert dc < 1e-9 and dr < 1e-7
+    assert np.abs(d - w.depth_gt).max() < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_edge_order_does_not_change_result(precision):
+    """Edges are regrouped by (patch, target frame) on the device, so a shuffled
+    edge list gives bitwise the same output."""
+    need_gpu()
+    w = synth.plain_fp64_window(7) if precision == "fp64" else synth.method_scale_window(3)
+    (a,), _ = solve_gpu([w], precision, "split")
+    (b,), _ = solve_gpu([synth.shuffled(w, 5)], precision, "split")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_fixed_poses_unchanged_bitwise():
+    need_gpu()
+    w = synth.method_scale_window(4)
+    (r,), _ = solve_gpu([w], "fp32", "fused")
+    assert np.array_equal(r[0][:w.n_fixed], w.poses[:w.n_fixed])
+
+
+def test_alone_and_in_batch_identical():
+    """A window solved alone and inside a batch of uneven windows gives the same
+    bits (fused schedule: one workgroup per window, fixed reduction order)."""
+    need_gpu()
+    wins = [synth.serving_window(i) for i in range(6)]
+    batch_out, st = solve_gpu(wins, "fp32", "fused")
+    assert (st == 0).all()
+    for i in (0, 3, 5):
+        (alone,), _ = solve_gpu([wins[i]], "fp32", "fused")
+        assert np.array_equal(alone[0], batch_out[i][0]) and np.array_equal(alone[1], batch_out[i][1])
+
+
+def test_bad_index_window_reports_and_keeps_inputs():
+    need_gpu()
+    good = synth.plain_fp64_window(1)
+    bad = synth.plain_fp64_window(2)
+    bad.jj = bad.jj.copy()
+    bad.jj[5] = 99
+    out, st = solve_gpu([good, bad], "fp64", "split")
+    assert st[0] == 0 and st[1] & 4
+    assert np.array_equal(out[1][0], bad.poses) and np.array_equal(out[1][1], bad.patches[:, 2])
+    pr, dr_ = O.solve(good)
+    assert compare(out[0][0], out[0][1], pr, dr_)[0] < 1e-6
+
+
+def test_nonfinite_target_reports_and_keeps_inputs():
+    need_gpu()
+    w = synth.method_scale_window(5)
+    w.targets = w.targets.copy()
+    w.targets[100, 0] = np.nan
+    (r,), st = solve_gpu([w], "fp32", "split")
+    assert st[0] & 2
+    assert np.array_equal(r[0], w.poses) and np.array_equal(r[1], w.patches[:, 2])
