@@ -82,7 +82,8 @@ enum {
   BA_W_OK = 0,
   BA_W_NOT_SPD = 1,     /* reduced pose system not positive definite            */
   BA_W_NONFINITE = 2,   /* a non-finite input or intermediate value             */
-  BA_W_BAD_INDEX = 4    /* anchor / kk / jj outside the window                  */
+  BA_W_BAD_INDEX = 4,   /* anchor / kk / jj outside the window                  */
+  BA_W_DEGREE = 8       /* a patch has more than 64 edges                       */
 };
 
 typedef struct {
@@ -92,7 +93,7 @@ typedef struct {
   double z_min;                   /* active-edge threshold on homogeneous depth   */
   int32_t schedule;               /* BA_SCHED_*                                   */
   int32_t max_windows;            /* windows per call                             */
-  int32_t max_frames_per_window;  /* 1..64                                        */
+  int32_t max_frames_per_window;  /* 1..64 (1..24 for BA_PREC_FP64)               */
   int32_t reserved;
   int64_t max_frames;             /* total frames per call                        */
   int64_t max_patches;            /* total patches per call                       */

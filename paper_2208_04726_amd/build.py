@@ -21,6 +21,9 @@ def build(verbose: bool = False) -> str:
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            # no packed FP32 instructions (v_pk_*_f32) in device code
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           # multiply-add fusion only inside one source expression, so the
+           # arithmetic of a window does not depend on which kernel variant ran
+           "-ffp-contract=on",
            "-Wno-unused-command-line-argument",
            SRC, "-o", OUT + ".tmp"]
     if verbose:

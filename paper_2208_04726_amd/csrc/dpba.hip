@@ -18,9 +18,10 @@ using namespace dpba;
 
 // ---------------------------------------------------------------------------
 // kernels
+template <typename T>
 __global__ void __launch_bounds__(WG) k_prep(Params P) {
-  __shared__ int lds[WG + 16];
-  wg_prep(P, blockIdx.x, lds);
+  __shared__ int lds[WG + 16 + 2 * RMAX];
+  wg_prep<T>(P, blockIdx.x, lds);
 }
 
 template <typename T, int MAXT>
@@ -50,7 +51,7 @@ template <typename T, int MAXT>
 __global__ void __launch_bounds__(WG) k_fused(Params P, int Rcap) {
   extern __shared__ __align__(16) char smem[];
   for (int w = blockIdx.x; w < P.n_windows; w += gridDim.x) {
-    wg_prep(P, w, (int*)smem);
+    wg_prep<T>(P, w, (int*)smem);
     __syncthreads();
     const int c = P.win[w].chunk_off;
     for (int it = 0; it < P.iterations; ++it) {
@@ -76,7 +77,7 @@ __global__ void __launch_bounds__(WG) k_debug_gather(Params P, int w, double* S,
   double* A = (double*)(smem + 64);
   double* b = A + n * lda;
   if (n == 0) return;
-  gather_partials<T>(P, w, W, A, lda, b, n);
+  gather_partials(P, w, W, A, lda, b, n);
   for (int i = threadIdx.x; i < n * n; i += WG) {
     const int r = i / n, c = i % n;
     S[i] = (c <= r ? A[r * lda + c] : A[c * lda + r]) + (r == c ? P.lambda : 0.0);
@@ -111,7 +112,10 @@ struct ba_handle {
   int last_W = 0;
   int32_t *status = nullptr, *wmeta = nullptr, *cnt = nullptr, *ptr = nullptr, *fill = nullptr;
   int32_t *acnt = nullptr, *afill = nullptr, *plist = nullptr, *csr = nullptr, *arange = nullptr,
-          *cstate = nullptr;
+          *cstate = nullptr, *estart = nullptr, *sbstart = nullptr, *gj = nullptr;
+  int4* sbd = nullptr;
+  void *pxy = nullptr, *gt = nullptr, *gw = nullptr;
+  int64_t cap_sb = 0;
   double* partial = nullptr;
   double *dxi = nullptr, *pose_buf = nullptr, *depth_buf = nullptr;
   std::string err;
@@ -236,7 +240,7 @@ int build_descriptors(ba_handle* h, const ba_problem* p, Plan& pl) {
     HIPCHK(h, hipEventSynchronize(h->staging_ev));
     h->staging_pending = false;
   }
-  int64_t part_off = 0;
+  int64_t part_off = 0, sb_off = 0;
   int ci = 0;
   for (int w = 0; w < W; ++w) {
     WinDesc& d = h->h_win[w];
@@ -259,6 +263,8 @@ int build_descriptors(ba_handle* h, const ba_problem* p, Plan& pl) {
     d.n_chunks = nc;
     d.part_off = part_off;
     d.part_stride = D * D + D;
+    d.sb_off = sb_off;
+    sb_off += (d.n_patches + 15) / 16 + N + 1;
     for (int q = 0; q < nc; ++q) {
       ChunkDesc& cd = h->h_chunk[ci++];
       cd.window = w;
@@ -269,6 +275,7 @@ int build_descriptors(ba_handle* h, const ba_problem* p, Plan& pl) {
     part_off += nc * d.part_stride;
   }
   pl.C = ci;
+  if (sb_off > h->cap_sb) return fail(h, BA_E_CAPACITY, "sub-batch table too small");
   return BA_OK;
 }
 
@@ -308,6 +315,13 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
   P.pose_buf = h->pose_buf;
   P.depth_buf = h->depth_buf;
   P.n_frames_total = h->cfg.max_frames;
+  P.estart = h->estart;
+  P.sbstart = h->sbstart;
+  P.sbd = h->sbd;
+  P.pxy = h->pxy;
+  P.gj = h->gj;
+  P.gt = h->gt;
+  P.gw = h->gw;
 
   HIPCHK(h, hipMemcpyAsync(h->d_win, h->h_win, sizeof(WinDesc) * pl.W, hipMemcpyHostToDevice, s));
   if (pl.C > 0)
@@ -320,13 +334,13 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
   const int chol_lds = chol_lds_bytes(pl.nmax);
   const int bs_lds = backsub_lds_bytes(Rcap, (int)sizeof(T));
   if (pl.fused) {
-    const int lds = std::max(std::max(asm_lds, chol_lds), std::max(bs_lds, (WG + 16) * 4));
+    const int lds = std::max(std::max(asm_lds, chol_lds), std::max(bs_lds, (WG + 16 + 2 * RMAX) * 4));
     const int grid = std::min(pl.W, 4 * h->n_cu);
     if (pl.maxt == 4) hipLaunchKernelGGL((k_fused<T, 4>), dim3(grid), dim3(WG), lds, s, P, Rcap);
     else hipLaunchKernelGGL((k_fused<T, 8>), dim3(grid), dim3(WG), lds, s, P, Rcap);
     HIPCHK(h, hipGetLastError());
   } else {
-    hipLaunchKernelGGL(k_prep, dim3(pl.W), dim3(WG), 0, s, P);
+    hipLaunchKernelGGL(k_prep<T>, dim3(pl.W), dim3(WG), 0, s, P);
     HIPCHK(h, hipGetLastError());
     for (int it = 0; it < P.iterations; ++it) {
       if (pl.C > 0) {
@@ -363,7 +377,7 @@ int ba_create(const ba_config* cfg, ba_handle** out) {
   if (cfg->schedule < 0 || cfg->schedule > 2) return BA_E_INVAL;
   if (cfg->max_windows < 1 || cfg->max_frames_per_window < 1 || cfg->max_frames_per_window > RMAX)
     return BA_E_INVAL;
-  if (cfg->precision == BA_PREC_FP64 && cfg->max_frames_per_window > 32) return BA_E_INVAL;
+  if (cfg->precision == BA_PREC_FP64 && cfg->max_frames_per_window > 24) return BA_E_INVAL;
   if (cfg->max_frames < 1 || cfg->max_patches < 0 || cfg->max_edges < 0) return BA_E_INVAL;
 
   ba_handle* h = new ba_handle();
@@ -404,6 +418,14 @@ int ba_create(const ba_config* cfg, ba_handle** out) {
   dmalloc((void**)&h->dxi, 8 * 6 * F);
   dmalloc((void**)&h->pose_buf, 8 * 2 * 7 * F);
   dmalloc((void**)&h->depth_buf, 8 * Pn);
+  h->cap_sb = Pn / 16 + F + 2 * W;
+  dmalloc((void**)&h->estart, 4 * (Pn + W));
+  dmalloc((void**)&h->sbstart, 4 * (F + W));
+  dmalloc((void**)&h->sbd, 16 * h->cap_sb);
+  dmalloc(&h->pxy, 16 * Pn);
+  dmalloc((void**)&h->gj, 4 * E);
+  dmalloc(&h->gt, 2 * esz * E);
+  dmalloc(&h->gw, 2 * esz * E);
   if (!ok) return cleanup(BA_E_HIP);
   if (hipHostMalloc((void**)&h->h_win, sizeof(WinDesc) * W) != hipSuccess) return cleanup(BA_E_HIP);
   if (hipHostMalloc((void**)&h->h_chunk, sizeof(ChunkDesc) * h->cap_chunks) != hipSuccess) return cleanup(BA_E_HIP);
@@ -464,6 +486,13 @@ void ba_destroy(ba_handle* h) {
   hipFree(h->dxi);
   hipFree(h->pose_buf);
   hipFree(h->depth_buf);
+  hipFree(h->estart);
+  hipFree(h->sbstart);
+  hipFree(h->sbd);
+  hipFree(h->pxy);
+  hipFree(h->gj);
+  hipFree(h->gt);
+  hipFree(h->gw);
   if (h->h_win) hipHostFree(h->h_win);
   if (h->h_chunk) hipHostFree(h->h_chunk);
   if (h->staging_ev) hipEventDestroy(h->staging_ev);
@@ -497,6 +526,8 @@ int ba_debug_reduced_system(ba_handle* h, const ba_problem* p, int32_t window, d
   P.acnt = h->acnt; P.afill = h->afill; P.plist = h->plist; P.csr = h->csr; P.arange = h->arange;
   P.cstate = h->cstate; P.partial = h->partial; P.dxi = h->dxi; P.pose_buf = h->pose_buf;
   P.depth_buf = h->depth_buf; P.n_frames_total = h->cfg.max_frames;
+  P.estart = h->estart; P.sbstart = h->sbstart; P.sbd = h->sbd; P.pxy = h->pxy;
+  P.gj = h->gj; P.gt = h->gt; P.gw = h->gw;
   HIPCHK(h, hipMemcpyAsync(h->d_win, h->h_win, sizeof(WinDesc) * pl.W, hipMemcpyHostToDevice, s));
   if (pl.C > 0)
     HIPCHK(h, hipMemcpyAsync(h->d_chunk, h->h_chunk, sizeof(ChunkDesc) * pl.C, hipMemcpyHostToDevice, s));
@@ -504,7 +535,8 @@ int ba_debug_reduced_system(ba_handle* h, const ba_problem* p, int32_t window, d
   h->staging_pending = true;
   const bool f32 = h->cfg.precision == BA_PREC_FP32;
   const int esz = f32 ? 4 : 8;
-  hipLaunchKernelGGL(k_prep, dim3(pl.W), dim3(WG), 0, s, P);
+  if (f32) hipLaunchKernelGGL(k_prep<float>, dim3(pl.W), dim3(WG), 0, s, P);
+  else hipLaunchKernelGGL(k_prep<double>, dim3(pl.W), dim3(WG), 0, s, P);
   HIPCHK(h, hipGetLastError());
   if (pl.C > 0) {
     const int al = asm_layout(pl.Rcap, esz).total;

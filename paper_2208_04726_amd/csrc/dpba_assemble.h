@@ -29,6 +29,7 @@
 //     v_j += V, v_i -= A^T V.
 #pragma once
 #include "dpba_common.h"
+#include "dpba_prep.h"
 
 namespace dpba {
 
@@ -51,35 +52,49 @@ __device__ inline f64x4 mfma16(double a, double b, f64x4 c) {
 __device__ inline int acc_row(float, int g, int r) { return 4 * g + r; }
 __device__ inline int acc_row(double, int g, int r) { return 4 * r + g; }
 
-constexpr int SB = 32;          // patches per sub-batch (K block of the Schur product)
-constexpr int LDK = SB + 4;     // LDS row length of the staged u rows
+constexpr int SBMAX = 32;       // patches per sub-batch (K block of the Schur product)
+constexpr int SBE = 1024;       // staged edges per sub-batch (SB x lane segment width)
+constexpr int LDK = SBMAX + 4;  // LDS row length of the staged u rows
 constexpr int RELW = 24;        // LDS words per relative pose: R(9) t(3) hat(t)R(9)
 
-// packed index of (m, n), m <= n, in the 21-entry upper triangle of a 6x6
-__device__ inline int sym6(int m, int n) {
-  if (m > n) { int t = m; m = n; n = t; }
-  return m * 6 - (m * (m - 1)) / 2 + (n - m);
-}
-
-// LDS layout of the assembly stage, in bytes, for a chunk range of at most
-// Rcap frames.  Shared with the host to size the launch.
+// LDS layout of the assembly and back-substitution stages, in bytes, for
+// windows of at most Rcap frames.  Shared with the host to size the launch.
 struct AsmLayout {
-  int rel, tbl, G, U, tiles, misc, total;
+  int poses, rel, tbl, G, U, tiles, stage, misc, total;
   int Tcap;
 };
+__host__ __device__ inline int stage_bytes(int esize) {
+  return SBE * (4 + 4 * esize) + SBMAX * (4 + 2 * esize + 8) + (SBMAX + 1) * 4;
+}
 __host__ __device__ inline AsmLayout asm_layout(int Rcap, int esize) {
   AsmLayout L;
   const int Dcap = 6 * Rcap;
   L.Tcap = (Dcap + 1 + 15) / 16;
   int o = 0;
-  L.rel = o;   o += RMAX * RELW * esize;
+  L.poses = o; o += Rcap * 7 * 8;
+  L.rel = o;   o += Rcap * RELW * esize;
   L.tbl = o;   o += NWAVES * Rcap * TBL * esize;
   L.G = o;     o += (Rcap * 36 + 42) * esize;
   L.U = o;     o += 16 * L.Tcap * LDK * esize;
   L.tiles = o; o += 4 * ((L.Tcap * (L.Tcap + 1)) / 2 + 4);
+  o = (o + 15) & ~15;
+  L.stage = o; o += stage_bytes(esize);
+  o = (o + 15) & ~15;
   L.misc = o;  o += 64;
   L.total = (o + 255) & ~255;
   return L;
+}
+// back-substitution: poses, relative poses, pose steps, stage
+__host__ __device__ inline int backsub_lds_bytes(int Rcap, int esize) {
+  int o = Rcap * 7 * 8 + Rcap * RELW * esize + Rcap * 6 * 8;
+  o = (o + 15) & ~15;
+  return o + stage_bytes(esize) + 64;
+}
+
+// packed index of (m, n), m <= n, in the 21-entry upper triangle of a 6x6
+__device__ inline int sym6(int m, int n) {
+  if (m > n) { int t = m; m = n; n = t; }
+  return m * 6 - (m * (m - 1)) / 2 + (n - m);
 }
 
 template <typename T>
@@ -139,17 +154,6 @@ __device__ inline int wg_bcast_status(const int32_t* status, int w, int* slot) {
   return s;
 }
 
-// Frame range of a chunk: union of its anchors' ranges.
-__device__ inline void chunk_range(const Params& P, const WinDesc& W, const ChunkDesc& cd,
-                                   int& f_lo, int& f_hi) {
-  const int32_t* ar = P.arange + 2 * W.frame_off;
-  f_lo = 1 << 30;
-  f_hi = -1;
-  for (int a = cd.a_lo; a < cd.a_hi; ++a) {
-    f_lo = min(f_lo, ar[2 * a]);
-    f_hi = max(f_hi, ar[2 * a + 1]);
-  }
-}
 
 // Relative poses T_ja for j in [lo, hi] into rel[(j - f_lo) * RELW].
 template <typename T>
@@ -184,8 +188,158 @@ __device__ inline const double* state_poses(const Params& P, const WinDesc& W, i
   return iter == 0 ? P.poses_in + 7 * W.frame_off
                    : P.pose_buf + (int64_t)(iter & 1) * 7 * P.n_frames_total + 7 * W.frame_off;
 }
-__device__ inline double state_depth(const Params& P, const WinDesc& W, int iter, int k) {
-  return iter == 0 ? P.patches_in[3 * (W.patch_off + k) + 2] : P.depth_buf[W.patch_off + k];
+
+// ---------------------------------------------------------------------------
+// Sub-batch staging.  A sub-batch is a run of at most SB positions of one
+// source frame (descriptor from the preparation pass: first position,
+// source frame << 8 | count, edge range [e0, e1)).  Its edges (target frame,
+// target, weight) and per-patch data (patch index, edge offset, normalised
+// pixel, inverse depth) are copied into LDS with coalesced loads.  The loads
+// of the next sub-batch are issued into registers before the current one is
+// processed and written to LDS after its edges have been consumed, so global
+// latency overlaps the linearisation and the matrix-core work.
+template <typename T>
+struct Stage {
+  int32_t* j; T* t; T* w; int32_t* pk; int32_t* pe; T* px; T* py; double* pd;
+  __device__ Stage(char* base) {
+    j = (int32_t*)base;
+    t = (T*)(base + SBE * 4);
+    w = (T*)(base + SBE * (4 + 2 * sizeof(T)));
+    char* q = base + SBE * (4 + 4 * sizeof(T));
+    pd = (double*)q; q += SBMAX * 8;
+    px = (T*)q; q += SBMAX * sizeof(T);
+    py = (T*)q; q += SBMAX * sizeof(T);
+    pk = (int32_t*)q; q += SBMAX * 4;
+    pe = (int32_t*)q;
+  }
+};
+
+template <typename T>
+struct StageRegs {
+  int32_t j[2];
+  T t[4], w[4];
+  int32_t pk, pe;
+  T px, py;
+  double pd;
+};
+
+struct WinEdges {   // edge arrays in edge order (inputs, or the gathered copies)
+  const int32_t* j;
+  const void* t;
+  const void* w;
+};
+
+__device__ inline WinEdges win_edges(const Params& P, const WinDesc& W, int gathered, int esize) {
+  WinEdges e;
+  if (gathered) {
+    e.j = P.gj + W.edge_off;
+    e.t = (const char*)P.gt + 2 * esize * W.edge_off;
+    e.w = (const char*)P.gw + 2 * esize * W.edge_off;
+  } else {
+    e.j = P.jj + W.edge_off;
+    e.t = (const char*)P.targets + 2 * esize * W.edge_off;
+    e.w = (const char*)P.weights + 2 * esize * W.edge_off;
+  }
+  return e;
+}
+
+template <typename T>
+__device__ inline void stage_issue(const Params& P, const WinDesc& W, int w, const WinEdges& we,
+                                   int4 d, StageRegs<T>& R) {
+  const int tid = threadIdx.x;
+  const int pos0 = d.x, n = d.y & 255, e0 = d.z, e1 = d.w;
+  const T* tg = (const T*)we.t;
+  const T* wt = (const T*)we.w;
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int q = e0 + tid + r * WG;
+    if (q < e1) {
+      R.j[r] = we.j[q];
+      R.t[2 * r] = tg[2 * q];
+      R.t[2 * r + 1] = tg[2 * q + 1];
+      R.w[2 * r] = wt[2 * q];
+      R.w[2 * r + 1] = wt[2 * q + 1];
+    }
+  }
+  if (tid <= n) {
+    const int32_t* est = P.estart + W.patch_off + w;
+    R.pe = (tid < n ? est[pos0 + tid] : e1) - e0;
+  }
+  if (tid < n) {
+    R.pk = P.plist[W.patch_off + pos0 + tid];
+    const T* pxy = (const T*)P.pxy + 2 * (W.patch_off + pos0 + tid);
+    R.px = pxy[0];
+    R.py = pxy[1];
+    R.pd = P.depth_buf[W.patch_off + pos0 + tid];
+  }
+}
+
+template <typename T>
+__device__ inline void stage_store(int4 d, const StageRegs<T>& R, Stage<T>& S) {
+  const int tid = threadIdx.x;
+  const int n = d.y & 255, ne = d.w - d.z;
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int q = tid + r * WG;
+    if (q < ne) {
+      S.j[q] = R.j[r];
+      S.t[2 * q] = R.t[2 * r];
+      S.t[2 * q + 1] = R.t[2 * r + 1];
+      S.w[2 * q] = R.w[2 * r];
+      S.w[2 * q + 1] = R.w[2 * r + 1];
+    }
+  }
+  if (tid <= n) S.pe[tid] = R.pe;
+  if (tid < n) {
+    S.pk[tid] = R.pk;
+    S.px[tid] = R.px;
+    S.py[tid] = R.py;
+    S.pd[tid] = R.pd;
+  }
+}
+
+// One lane's edge of the staged sub-batch: slot `slot` (patch), lane `lseg`
+// of its segment.
+template <typename T>
+struct LaneEdge {
+  bool pv, has;
+  int slot, deg, q, j;
+  T t0, t1, w0, w1, xb, yb;
+  double d;
+};
+
+template <typename T>
+__device__ inline LaneEdge<T> lane_edge(const Stage<T>& S, int slot, bool slot_ok, int n, int lseg, int a) {
+  LaneEdge<T> L;
+  L.slot = slot;
+  L.pv = slot_ok && slot < n;
+  const int s = L.pv ? slot : 0;
+  const int base = S.pe[s];
+  L.deg = L.pv ? S.pe[s + 1] - base : 0;
+  L.has = lseg < L.deg;
+  L.q = base + lseg;
+  const int q = L.has ? L.q : 0;
+  L.j = L.has ? S.j[q] : a;
+  L.t0 = L.has ? S.t[2 * q] : T(0);
+  L.t1 = L.has ? S.t[2 * q + 1] : T(0);
+  L.w0 = L.has ? S.w[2 * q] : T(0);
+  L.w1 = L.has ? S.w[2 * q + 1] : T(0);
+  L.xb = S.px[s];
+  L.yb = S.py[s];
+  L.d = S.pd[s];
+  return L;
+}
+
+// Frame range of a chunk: union of its anchors' ranges.
+__device__ inline void chunk_range(const Params& P, const WinDesc& W, const ChunkDesc& cd,
+                                   int& f_lo, int& f_hi) {
+  const int32_t* ar = P.arange + 2 * W.frame_off;
+  f_lo = 1 << 30;
+  f_hi = -1;
+  for (int a = cd.a_lo; a < cd.a_hi; ++a) {
+    f_lo = min(f_lo, ar[2 * a]);
+    f_hi = max(f_hi, ar[2 * a + 1]);
+  }
 }
 
 // Running sums of the tile elements across source frames.  FP32 assembly:
@@ -193,20 +347,18 @@ __device__ inline double state_depth(const Params& P, const WinDesc& W, int iter
 // products, formed in FP32) is added into FP64 registers `sh`, so no FP32
 // value ever carries the whole window's sum.  FP64 assembly: the matrix-core
 // accumulators themselves are the running sums (of the negated entries).
-
-// Lane segment width for a window's largest patch degree.
-__device__ inline int seg_width(int maxdeg) { return maxdeg <= 16 ? 16 : (maxdeg <= 32 ? 32 : 64); }
-
 template <typename T, int MAXT>
 __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rcap) {
   typedef typename AccT<T>::type Acc;
   const AsmLayout L = asm_layout(Rcap, (int)sizeof(T));
+  double* lp = (double*)(smem + L.poses);
   T* rel = (T*)(smem + L.rel);
   T* tbl = (T*)(smem + L.tbl);
   T* G = (T*)(smem + L.G);
   T* U = (T*)(smem + L.U);
   int* tiles = (int*)(smem + L.tiles);
   int* misc = (int*)(smem + L.misc);
+  Stage<T> S(smem + L.stage);
 
   const ChunkDesc cd = P.chunk[c];
   const int w = cd.window;
@@ -227,24 +379,20 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
   if (D == 0) return;   // every frame the chunk touches is fixed: nothing to assemble
 
   const double* poses = state_poses<T>(P, W, iter);
-  const int32_t* plist = P.plist + W.patch_off;
-  const int32_t* acnt = P.acnt + W.frame_off + w;
+  for (int i = tid; i < 7 * N; i += WG) lp[i] = poses[i];
   const int32_t* ar = P.arange + 2 * W.frame_off;
-  const int32_t* cnt = P.cnt + W.patch_off;
-  const int32_t* ptr = P.ptr + W.patch_off;
-  const int32_t* csr = P.csr + W.edge_off;
-  const int32_t* jjw = P.jj + W.edge_off;
-  const T* tg = (const T*)P.targets + 2 * W.edge_off;
-  const T* wt = (const T*)P.weights + 2 * W.edge_off;
+  const int32_t* sbs = P.sbstart + W.frame_off + w;
+  const int4* sbd = P.sbd + W.sb_off;
+  const WinEdges we = win_edges(P, W, P.wmeta[4 * w + 1], (int)sizeof(T));
   const T fx = (T)W.fx, fy = (T)W.fy, cx = (T)W.cx, cy = (T)W.cy;
   const T zmin = (T)P.z_min, lam = (T)P.lambda;
   const int SEG = seg_width(P.wmeta[4 * w]);
+  const int SBw = sb_width(SEG);
   const int segs = 64 / SEG;                 // patches per wave pass
-  const int spw = SB / NWAVES;               // patch slots per wave per sub-batch
+  const int spw = SBw / NWAVES;              // patch slots per wave per sub-batch
   const int npass = (spw + segs - 1) / segs;
   const int lseg = lane & (SEG - 1), sidx = lane / SEG;
-  const int maxdeg = P.wmeta[4 * w];
-  const int nch = (maxdeg + SEG - 1) / SEG;  // edge chunks per patch (1 unless degree > 64)
+  const int s_lo = sbs[cd.a_lo], s_hi = sbs[cd.a_hi];
 
   // lower-triangle tiles of the (D+1) x (D+1) product, row-major
   const int Daug = D + 1;
@@ -270,143 +418,73 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
     for (int t = 0; t < MAXT; ++t) acc[t] = Acc{T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int t = 0; t < 4 * MAXT; ++t) sh[t] = 0.0;
-    __syncthreads();
 
-    for (int a = cd.a_lo; a < cd.a_hi; ++a) {
-      const int lo = ar[2 * a], hi = ar[2 * a + 1];
-      const int Ra = hi - lo + 1;
-      load_relposes<T>(poses, a, lo, hi, f_lo, rel);
-      for (int i = tid; i < NWAVES * Ra * TBL; i += WG) tbl[i] = T(0);
-      const int pb = acnt[a], pe = acnt[a + 1];
-      // nonzero column range of this anchor's u rows (plus the w column D)
-      const int nz_lo = 6 * (max(lo, lo_free) - lo_free);
-      const int nz_hi = (hi >= lo_free) ? 6 * (hi - lo_free + 1) : 0;
-      const bool a_free = a >= nfix;
-      T* mytbl = tbl + wv * Ra * TBL;
+    StageRegs<T> R;
+    int4 dcur = make_int4(0, 0, 0, 0), dnxt = dcur;
+    if (s_lo < s_hi) {
+      dcur = sbd[s_lo];
+      if (s_lo + 1 < s_hi) dnxt = sbd[s_lo + 1];
+      stage_issue<T>(P, W, w, we, dcur, R);
+    }
+    __syncthreads();   // previous pass done with the stage and the poses are in LDS
+    if (s_lo < s_hi) stage_store<T>(dcur, R, S);
 
-      for (int sb0 = pb; sb0 < pe; sb0 += SB) {
-        const int nsb = min(SB, pe - sb0);
-        for (int i = tid; i < 16 * T16 * LDK; i += WG) U[i] = T(0);
+    int a = -1, lo = 0, hi = -1, Ra = 0, nz_lo = 0, nz_hi = 0;
+    bool a_free = false;
+    for (int s = s_lo; s <= s_hi; ++s) {
+      const int an = (s < s_hi) ? (dcur.y >> 8) : -1;
+      if (an != a && a >= 0) {
+        // ---- pair blocks of the finished source frame a
         __syncthreads();
-
-        // ---- linearise this wave's patches, one lane segment per patch
-        for (int ps = 0; ps < npass; ++ps) {
-          const int slot_in_wave = ps * segs + sidx;
-          const int slot = wv * spw + slot_in_wave;
-          const bool pv = (slot_in_wave < spw) && (slot < nsb);
-          const int k = pv ? plist[sb0 + slot] : 0;
-          const int deg = pv ? cnt[k] : 0;
-          const int base = pv ? ptr[k] : 0;
-          const double* pt = P.patches_in + 3 * (W.patch_off + k);
-          const T xb = (T)((pt[0] - W.cx) / W.fx);
-          const T yb = (T)((pt[1] - W.cy) / W.fy);
-          const T dk = (T)state_depth(P, W, iter, k);
-
-          T s_cd = 0, s_wd = 0, s_ei[6] = {0, 0, 0, 0, 0, 0};
-          EdgeOut<T> eo;
-          for (int ch = 0; ch < nch; ++ch) {
-            const int es = ch * SEG + lseg;
-            const bool has = es < deg;
-            const int e = has ? csr[base + es] : 0;
-            const int j = has ? jjw[e] : a;
-            const T t0 = has ? tg[2 * e] : T(0), t1 = has ? tg[2 * e + 1] : T(0);
-            const T w0 = has ? wt[2 * e] : T(0), w1 = has ? wt[2 * e + 1] : T(0);
-            if (has && !(__builtin_isfinite(t0) && __builtin_isfinite(t1) &&
-                         __builtin_isfinite(w0) && __builtin_isfinite(w1)))
-              nonfinite = true;
-            linearize_edge<T>(rel + (j - f_lo) * RELW, xb, yb, dk, t0, t1, w0, w1, fx, fy, cx,
-                              cy, zmin, has && (j != a), eo);
-            eo.j = j;
-            s_cd += eo.cd;
-            s_wd += eo.wd;
+        for (int i = tid; i < Ra * TBL; i += WG) {
+          T sum = 0;
+          for (int x = 0; x < NWAVES; ++x) sum += tbl[x * Ra * TBL + i];
+          tbl[i] = sum;
+        }
+        __syncthreads();
+        // G_j = A_j^T Q_j
+        for (int i = tid; i < Ra * 36; i += WG) {
+          const int jr = i / 36, m = (i % 36) / 6, n = i % 6;
+          const T* rj = rel + (lo + jr - f_lo) * RELW;
+          const T* Q = tbl + jr * TBL;
+          T sum = 0;
 #pragma unroll
-            for (int m = 0; m < 6; ++m) s_ei[m] += eo.Ei[m];
-            // pair tables Q_aj (21) and V_aj (6); segments of a wave take turns,
-            // and duplicate (k, j) edges inside a segment are added one lane at a time
-            const int jprev = __shfl_up(j, 1, 64);
-            const bool dup = eo.active && lseg > 0 && es - 1 < deg && jprev == j;
-            const bool anydup = __any(dup);
-            T* tb = mytbl + (j - lo) * TBL;
-            for (int sgi = 0; sgi < segs; ++sgi) {
-              if (!anydup) {
-                if (sidx == sgi && eo.active) {
-                  int q = 0;
+          for (int p = 0; p < 6; ++p) sum += adj_at(rj, p, m) * Q[sym6(p, n)];
+          G[i] = sum;
+        }
+        __syncthreads();
+        // anchor block sum_j A^T Q A and anchor gradient -sum_j A^T V (targets in
+        // fixed frames included: J_i = -J_j Ad(T_ji) whatever frame j is)
+        T* AQA = G + Ra * 36;
+        if (a_free) {
+          for (int i = tid; i < 42; i += WG) {
+            T sum = 0;
+            if (i < 36) {
+              const int m = i / 6, n = i % 6;
+              for (int jr = 0; jr < Ra; ++jr) {
+                if (lo + jr == a) continue;
+                const T* rj = rel + (lo + jr - f_lo) * RELW;
 #pragma unroll
-                  for (int m = 0; m < 6; ++m)
-#pragma unroll
-                    for (int n = m; n < 6; ++n, ++q)
-                      tb[q] += eo.w0 * eo.J0[m] * eo.J0[n] + eo.w1 * eo.J1[m] * eo.J1[n];
-#pragma unroll
-                  for (int m = 0; m < 6; ++m)
-                    tb[21 + m] += eo.w0 * eo.r0 * eo.J0[m] + eo.w1 * eo.r1 * eo.J1[m];
-                }
-              } else {
-                for (int ln = 0; ln < SEG; ++ln) {
-                  if (sidx == sgi && lseg == ln && eo.active) {
-                    int q = 0;
-#pragma unroll
-                    for (int m = 0; m < 6; ++m)
-#pragma unroll
-                      for (int n = m; n < 6; ++n, ++q)
-                        tb[q] += eo.w0 * eo.J0[m] * eo.J0[n] + eo.w1 * eo.J1[m] * eo.J1[n];
-#pragma unroll
-                    for (int m = 0; m < 6; ++m)
-                      tb[21 + m] += eo.w0 * eo.r0 * eo.J0[m] + eo.w1 * eo.r1 * eo.J1[m];
-                  }
-                }
-              }
-            }
-          }
-          const T Ck = lam + seg_sum(s_cd, SEG);
-          const T Wk = seg_sum(s_wd, SEG);
-          T Eik[6];
-#pragma unroll
-          for (int m = 0; m < 6; ++m) Eik[m] = seg_sum(s_ei[m], SEG);
-          const T rs = T(1) / __builtin_sqrt(Ck);
-          // staged row u_k: E_jk / sqrt(C_k) at target columns, E_ik / sqrt(C_k) at
-          // the anchor's columns, w_k / sqrt(C_k) at column D
-          for (int ch = 0; ch < nch; ++ch) {
-            const int es = ch * SEG + lseg;
-            if (nch > 1) {   // degree above 64: recompute each lane chunk
-              const bool has = es < deg;
-              const int e = has ? csr[base + es] : 0;
-              const int j = has ? jjw[e] : a;
-              linearize_edge<T>(rel + (j - f_lo) * RELW, xb, yb, dk,
-                                has ? tg[2 * e] : T(0), has ? tg[2 * e + 1] : T(0),
-                                has ? wt[2 * e] : T(0), has ? wt[2 * e + 1] : T(0), fx, fy,
-                                cx, cy, zmin, has && (j != a), eo);
-              eo.j = has ? j : a;
-            }
-            const int j = eo.j;
-            const int jprev = __shfl_up(j, 1, 64);
-            const bool dup = eo.active && lseg > 0 && es - 1 < deg && jprev == j;
-            const bool anydup = __any(dup);
-            T* ucol = U + (6 * (j - lo_free)) * LDK + slot;
-            if (!anydup) {
-              if (pv && eo.active && j >= lo_free) {
-#pragma unroll
-                for (int m = 0; m < 6; ++m) ucol[m * LDK] += eo.Ej[m] * rs;
+                for (int q2 = 0; q2 < 6; ++q2) sum += G[jr * 36 + m * 6 + q2] * adj_at(rj, q2, n);
               }
             } else {
-              for (int ln = 0; ln < SEG; ++ln)
-                if (lseg == ln && pv && eo.active && j >= lo_free) {
+              const int m = i - 36;
+              for (int jr = 0; jr < Ra; ++jr) {
+                if (lo + jr == a) continue;
+                const T* rj = rel + (lo + jr - f_lo) * RELW;
+                const T* Q = tbl + jr * TBL;
 #pragma unroll
-                  for (int m = 0; m < 6; ++m) ucol[m * LDK] += eo.Ej[m] * rs;
-                }
+                for (int p = 0; p < 6; ++p) sum -= adj_at(rj, p, m) * Q[21 + p];
+              }
             }
-          }
-          if (pv && lseg == 0) {
-            if (a_free) {
-              T* ua = U + (6 * (a - lo_free)) * LDK + slot;
-#pragma unroll
-              for (int m = 0; m < 6; ++m) ua[m * LDK] = Eik[m] * rs;
-            }
-            U[D * LDK + slot] = Wk * rs;
+            AQA[i] = sum;
           }
         }
         __syncthreads();
-
-        // ---- matrix-core outer products of the staged rows
+        // Each lane folds this source frame's B / v entries of its tile
+        // elements and the staged outer products into its running sums:
+        //   (j,j) += Q_j, (a,j) -= A^T Q_j, (a,a) += sum A^T Q A, v_j += V_j,
+        //   v_a -= sum A^T V, and -= sum_k u_k u_k^T.
         {
           const int l16 = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -414,18 +492,32 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
             if (t < ntl) {
               const int code = tiles[t_beg + t];
               const int ti = code >> 16, tj = code & 0xffff;
-              const bool rows_nz = (16 * ti < nz_hi && 16 * ti + 16 > nz_lo) ||
-                                   (16 * ti <= D && D < 16 * ti + 16);
-              const bool cols_nz = (16 * tj < nz_hi && 16 * tj + 16 > nz_lo) ||
-                                   (16 * tj <= D && D < 16 * tj + 16);
-              if (rows_nz && cols_nz) {
-                const T* ua = U + (16 * ti + l16) * LDK + 4 * g;
-                const T* ub = U + (16 * tj + l16) * LDK + 4 * g;
 #pragma unroll
-                for (int kb = 0; kb < SB / 16; ++kb) {
-#pragma unroll
-                  for (int s = 0; s < 4; ++s)
-                    acc[t] = mfma16(ua[16 * kb + s], ub[16 * kb + s], acc[t]);
+              for (int r = 0; r < 4; ++r) {
+                const int row = 16 * ti + acc_row(T(0), g, r), col = 16 * tj + l16;
+                T val = 0;
+                if (col < D && (row < D ? col <= row : row == D)) {
+                  const int fc = lo_free + col / 6, n = col % 6;
+                  if (row == D) {
+                    if (fc == a) val = a_free ? AQA[36 + n] : T(0);
+                    else if (fc >= lo && fc <= hi) val = tbl[(fc - lo) * TBL + 21 + n];
+                  } else {
+                    const int fr = lo_free + row / 6, m = row % 6;
+                    if (fr == fc) {
+                      if (fr == a) val = a_free ? AQA[m * 6 + n] : T(0);
+                      else if (fr >= lo && fr <= hi) val = tbl[(fr - lo) * TBL + sym6(m, n)];
+                    } else if (fr == a && fc >= lo && fc <= hi) {
+                      val = -G[(fc - lo) * 36 + m * 6 + n];
+                    } else if (fc == a && fr >= lo && fr <= hi) {
+                      val = -G[(fr - lo) * 36 + n * 6 + m];
+                    }
+                  }
+                }
+                if constexpr (sizeof(T) == 4) {
+                  sh[t * 4 + r] += (double)val - (double)acc[t][r];
+                  acc[t][r] = T(0);
+                } else {
+                  acc[t][r] -= val;
                 }
               }
             }
@@ -433,96 +525,118 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
         }
         __syncthreads();
       }
+      if (s == s_hi) break;
+      if (an != a) {
+        // ---- start of source frame an: relative poses, empty pair tables
+        a = an;
+        lo = ar[2 * a];
+        hi = ar[2 * a + 1];
+        Ra = hi - lo + 1;
+        load_relposes<T>(lp, a, lo, hi, f_lo, rel);
+        for (int i = tid; i < NWAVES * Ra * TBL; i += WG) tbl[i] = T(0);
+        nz_lo = 6 * (max(lo, lo_free) - lo_free);
+        nz_hi = (hi >= lo_free) ? 6 * (hi - lo_free + 1) : 0;
+        a_free = a >= nfix;
+      }
+      const int nsb = dcur.y & 255;
+      // prefetch the next sub-batch
+      int4 dnn = dnxt;
+      if (s + 1 < s_hi) {
+        stage_issue<T>(P, W, w, we, dnxt, R);
+        if (s + 2 < s_hi) dnn = sbd[s + 2];
+      }
+      for (int i = tid; i < 16 * T16 * LDK; i += WG) U[i] = T(0);
+      __syncthreads();
 
-      // ---- pair blocks of this anchor
-      for (int i = tid; i < Ra * TBL; i += WG) {
-        T sum = 0;
-        for (int x = 0; x < NWAVES; ++x) sum += tbl[x * Ra * TBL + i];
-        tbl[i] = sum;
-      }
-      __syncthreads();
-      // G_j = A_j^T Q_j
-      for (int i = tid; i < Ra * 36; i += WG) {
-        const int jr = i / 36, m = (i % 36) / 6, n = i % 6;
-        const T* rj = rel + (lo + jr - f_lo) * RELW;
-        const T* Q = tbl + jr * TBL;
-        T sum = 0;
+      // ---- linearise this wave's patches, one lane segment per patch
+      T* mytbl = tbl + wv * Ra * TBL;
+      for (int ps = 0; ps < npass; ++ps) {
+        const int slot_in_wave = ps * segs + sidx;
+        const LaneEdge<T> le = lane_edge<T>(S, wv * spw + slot_in_wave, slot_in_wave < spw, nsb, lseg, a);
+        if (le.has && !(__builtin_isfinite(le.t0) && __builtin_isfinite(le.t1) &&
+                        __builtin_isfinite(le.w0) && __builtin_isfinite(le.w1)))
+          nonfinite = true;
+        EdgeOut<T> eo;
+        const int j = le.j;
+        linearize_edge<T>(rel + (j - f_lo) * RELW, le.xb, le.yb, (T)le.d, le.t0, le.t1, le.w0,
+                          le.w1, fx, fy, cx, cy, zmin, le.has && (j != a), eo);
+        // pair tables Q_aj (21) and V_aj (6); segments of a wave take turns,
+        // and duplicate (k, j) edges inside a segment are added one lane at a time
+        const int jprev = __shfl_up(j, 1, 64);
+        const bool dup = eo.active && lseg > 0 && jprev == j;
+        const bool anydup = __any(dup);
+        T* tb = mytbl + (j - lo) * TBL;
+        for (int sgi = 0; sgi < segs; ++sgi) {
+          for (int ln = 0; ln < (anydup ? SEG : 1); ++ln) {
+            if (sidx == sgi && eo.active && (!anydup || lseg == ln)) {
+              int q = 0;
 #pragma unroll
-        for (int p = 0; p < 6; ++p) sum += adj_at(rj, p, m) * Q[sym6(p, n)];
-        G[i] = sum;
-      }
-      __syncthreads();
-      // anchor block sum_j A^T Q A and anchor gradient -sum_j A^T V (targets in
-      // fixed frames included: J_i = -J_j Ad(T_ji) whatever frame j is)
-      T* AQA = G + Ra * 36;
-      if (a_free) {
-        for (int i = tid; i < 42; i += WG) {
-          T sum = 0;
-          if (i < 36) {
-            const int m = i / 6, n = i % 6;
-            for (int jr = 0; jr < Ra; ++jr) {
-              if (lo + jr == a) continue;
-              const T* rj = rel + (lo + jr - f_lo) * RELW;
+              for (int m = 0; m < 6; ++m)
 #pragma unroll
-              for (int q2 = 0; q2 < 6; ++q2) sum += G[jr * 36 + m * 6 + q2] * adj_at(rj, q2, n);
-            }
-          } else {
-            const int m = i - 36;
-            for (int jr = 0; jr < Ra; ++jr) {
-              if (lo + jr == a) continue;
-              const T* rj = rel + (lo + jr - f_lo) * RELW;
-              const T* Q = tbl + jr * TBL;
+                for (int n = m; n < 6; ++n, ++q)
+                  tb[q] += eo.w0 * eo.J0[m] * eo.J0[n] + eo.w1 * eo.J1[m] * eo.J1[n];
 #pragma unroll
-              for (int p = 0; p < 6; ++p) sum -= adj_at(rj, p, m) * Q[21 + p];
+              for (int m = 0; m < 6; ++m)
+                tb[21 + m] += eo.w0 * eo.r0 * eo.J0[m] + eo.w1 * eo.r1 * eo.J1[m];
             }
           }
-          AQA[i] = sum;
+        }
+        const T Ck = lam + seg_sum(eo.cd, SEG);
+        const T Wk = seg_sum(eo.wd, SEG);
+        T Eik[6];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) Eik[m] = seg_sum(eo.Ei[m], SEG);
+        const T rs = T(1) / __builtin_sqrt(Ck);
+        // staged row u_k: E_jk / sqrt(C_k) at target columns, E_ik / sqrt(C_k) at
+        // the source frame's columns, w_k / sqrt(C_k) at column D
+        const int slot = le.slot;
+        T* ucol = U + (6 * (j - lo_free)) * LDK + slot;
+        for (int ln = 0; ln < (anydup ? SEG : 1); ++ln) {
+          if (le.pv && eo.active && j >= lo_free && (!anydup || lseg == ln)) {
+#pragma unroll
+            for (int m = 0; m < 6; ++m) ucol[m * LDK] += eo.Ej[m] * rs;
+          }
+        }
+        if (le.pv && lseg == 0) {
+          if (a_free) {
+            T* ua = U + (6 * (a - lo_free)) * LDK + slot;
+#pragma unroll
+            for (int m = 0; m < 6; ++m) ua[m * LDK] = Eik[m] * rs;
+          }
+          U[D * LDK + slot] = Wk * rs;
         }
       }
       __syncthreads();
-      // Each lane folds this anchor's B / v entries of its tile elements and
-      // the staged outer products into its FP64 running sums:
-      //   (j,j) += Q_j, (a,j) -= A^T Q_j, (a,a) += sum A^T Q A, v_j += V_j,
-      //   v_a -= sum A^T V, and -= sum_k u_k u_k^T.
+
+      // ---- matrix-core outer products of the staged rows
       {
         const int l16 = lane & 15, g = lane >> 4;
+        const int nkb = (nsb + 15) >> 4;
 #pragma unroll
         for (int t = 0; t < MAXT; ++t) {
           if (t < ntl) {
             const int code = tiles[t_beg + t];
             const int ti = code >> 16, tj = code & 0xffff;
+            const bool rows_nz = (16 * ti < nz_hi && 16 * ti + 16 > nz_lo) ||
+                                 (16 * ti <= D && D < 16 * ti + 16);
+            const bool cols_nz = (16 * tj < nz_hi && 16 * tj + 16 > nz_lo) ||
+                                 (16 * tj <= D && D < 16 * tj + 16);
+            if (rows_nz && cols_nz) {
+              const T* ua = U + (16 * ti + l16) * LDK + 4 * g;
+              const T* ub = U + (16 * tj + l16) * LDK + 4 * g;
+              for (int kb = 0; kb < nkb; ++kb) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int row = 16 * ti + acc_row(T(0), g, r), col = 16 * tj + l16;
-              T val = 0;
-              if (col < D && (row < D ? col <= row : row == D)) {
-                const int fc = lo_free + col / 6, n = col % 6;
-                if (row == D) {
-                  if (fc == a) val = AQA[36 + n];
-                  else if (fc >= lo && fc <= hi) val = tbl[(fc - lo) * TBL + 21 + n];
-                } else {
-                  const int fr = lo_free + row / 6, m = row % 6;
-                  if (fr == fc) {
-                    if (fr == a) val = AQA[m * 6 + n];
-                    else if (fr >= lo && fr <= hi) val = tbl[(fr - lo) * TBL + sym6(m, n)];
-                  } else if (fr == a && fc >= lo && fc <= hi) {
-                    val = -G[(fc - lo) * 36 + m * 6 + n];
-                  } else if (fc == a && fr >= lo && fr <= hi) {
-                    val = -G[(fr - lo) * 36 + n * 6 + m];
-                  }
-                }
-              }
-              if constexpr (sizeof(T) == 4) {
-                sh[t * 4 + r] += (double)val - (double)acc[t][r];
-                acc[t][r] = T(0);
-              } else {
-                acc[t][r] -= val;
+                for (int s4 = 0; s4 < 4; ++s4)
+                  acc[t] = mfma16(ua[16 * kb + s4], ub[16 * kb + s4], acc[t]);
               }
             }
           }
         }
       }
+      if (s + 1 < s_hi) stage_store<T>(dnxt, R, S);
       __syncthreads();
+      dcur = dnxt;
+      dnxt = dnn;
     }
 
     // ---- chunk partial: lower triangle of S and s, FP64

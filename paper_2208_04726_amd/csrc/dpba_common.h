@@ -17,6 +17,7 @@ constexpr int TBL = 27;            // pair table entries: 21 (6x6 sym) + 6
 constexpr int W_NOT_SPD = 1;
 constexpr int W_NONFINITE = 2;
 constexpr int W_BAD_INDEX = 4;
+constexpr int W_DEGREE = 8;
 
 // ---------------------------------------------------------------------------
 // Descriptors, built on the host for every call and copied to the device.
@@ -27,6 +28,7 @@ struct WinDesc {
   int32_t chunk_off, n_chunks;    // chunks of this window in the chunk table
   int64_t part_off;               // first element of this window's partials
   int64_t part_stride;            // elements per chunk partial (D*D + D, D = 6*(N-nfix))
+  int64_t sb_off;                 // first sub-batch descriptor of this window
 };
 
 struct ChunkDesc {
@@ -57,14 +59,21 @@ struct Params {
   int32_t* fill;        // [P] scatter cursor
   int32_t* acnt;        // [F+W] patches per anchor -> offsets
   int32_t* afill;       // [F] scatter cursor
-  int32_t* plist;       // [P] patches sorted by (anchor, index), window-local
+  int32_t* plist;       // [P] patch at each position (positions sorted by (anchor, index))
   int32_t* csr;         // [E] edges sorted by (patch, target, index), window-local
+  int32_t* estart;      // [P+W] first edge (edge order) of each position
+  int32_t* sbstart;     // [F+W] first sub-batch of each source frame
+  int4* sbd;            // sub-batches: (first position, frame << 8 | count, e0, e1)
+  void* pxy;            // [P*2] T, normalised pixel of each position
+  int32_t* gj;          // [E] gathered target frames (edge order)
+  void* gt;             // [E*2] T gathered targets
+  void* gw;             // [E*2] T gathered weights
   int32_t* arange;      // [F*2] frame range touched by each anchor's patches
   int32_t* cstate;      // [C*2] chunk: first free frame of its range, D
   double* partial;      // chunk partials of S (lower, D x D) and s (D), FP64
   double* dxi;          // [F*6] pose steps
   double* pose_buf;     // [2][F*7] pose state double buffer
-  double* depth_buf;    // [P] depth state
+  double* depth_buf;    // [P] depth state, position order
   int64_t n_frames_total;
 };
 

@@ -1,20 +1,45 @@
 // Per-window graph preparation, one workgroup per window.
 //
 // The patch graph (Sec. 3 "Patch Graph") arrives as an unordered edge list
-// (k, j).  This pass validates indices, counts edges per patch and patches per
-// source frame, and builds two deterministic orderings used by every later
-// stage:
-//   plist: the window's patches sorted by (source frame, patch index);
-//   csr:   each patch's edges sorted by (target frame, edge index).
-// Both orders depend only on the graph, not on the input order of equal keys'
-// scheduling, so results are bitwise reproducible.  Inputs that already come
-// grouped (the usual case) are detected and take the identity orderings.
-// It also records, per source frame, the range of frames its patches touch.
+// (k, j).  This pass validates it and lays the window out in the order every
+// later stage consumes it:
+//   * positions: the window's patches sorted by (source frame, patch index);
+//     pk[pos] is the patch at a position, acnt[a] the first position of
+//     source frame a;
+//   * edge order: the edges of position 0, then of position 1, ...; inside a
+//     patch by (target frame, edge index).  estart[pos] is the first edge of a
+//     position.  When the input is already in this order (the usual case) the
+//     input arrays are used as they are; otherwise the target frame, target
+//     and weight of each edge are gathered into workspace arrays in this order;
+//   * per position: the normalised pixel ((x - cx) / fx, (y - cy) / fy) and
+//     the inverse depth of the state (position order);
+//   * sub-batches: runs of at most SB positions of one source frame, each with
+//     its position and edge ranges (sbd), and per source frame the index of
+//     its first sub-batch (sbstart);
+//   * per source frame, the range of frames its patches touch (arange).
+// Every order depends only on the graph, so results are bitwise reproducible
+// whatever the input order of the edges.
 #pragma once
 #include "dpba_common.h"
 
 namespace dpba {
 
+// Sub-batch width (patches) and lane segment width (edges per patch) for a
+// window's largest patch degree: one segment of lanes per patch, at most 1024
+// staged edges per sub-batch.
+__host__ __device__ inline int seg_width(int maxdeg) { return maxdeg <= 16 ? 16 : (maxdeg <= 32 ? 32 : 64); }
+__host__ __device__ inline int sb_width(int seg) { return seg == 64 ? 16 : 32; }
+
+__device__ inline int lower_bound_i32(const int32_t* a, int n, int v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+template <typename T>
 __device__ void wg_prep(const Params& P, int w, int* lds) {
   const WinDesc W = P.win[w];
   const int N = W.n_frames, M = W.n_patches, E = W.n_edges;
@@ -22,93 +47,97 @@ __device__ void wg_prep(const Params& P, int w, int* lds) {
   int32_t* cnt = P.cnt + W.patch_off;
   int32_t* ptr = P.ptr + W.patch_off;
   int32_t* fill = P.fill + W.patch_off;
-  int32_t* plist = P.plist + W.patch_off;
+  int32_t* pk = P.plist + W.patch_off;
   int32_t* acnt = P.acnt + W.frame_off + w;   // N + 1 entries
   int32_t* afill = P.afill + W.frame_off;
   int32_t* ar = P.arange + 2 * W.frame_off;
   int32_t* csr = P.csr + W.edge_off;
+  int32_t* est = P.estart + W.patch_off + w;  // M + 1 entries
+  int32_t* sbs = P.sbstart + W.frame_off + w; // N + 1 entries
+  int4* sbd = P.sbd + W.sb_off;
   const int32_t* anc = P.anchor + W.patch_off;
   const int32_t* kk = P.kk + W.edge_off;
   const int32_t* jj = P.jj + W.edge_off;
-  int* flags = lds + WG;  // [0] bad index, [1] edges unsorted, [2] patches unsorted, [3] max degree, [4] non-finite
+  // lds: [0, WG) scan scratch; flags at WG: [0] bad index, [1] edges unsorted,
+  // [2] patches unsorted, [3] max degree, [4] non-finite; per-frame range at WG+16
+  int* flags = lds + WG;
+  int* lr = lds + WG + 16;   // [2 * RMAX]
 
-  if (tid < 8) flags[tid] = 0;
-  for (int k = tid; k < M; k += WG) { cnt[k] = 0; fill[k] = 0; }
-  for (int a = tid; a <= N; a += WG) acnt[a] = 0;
-  for (int a = tid; a < N; a += WG) { afill[a] = 0; ar[2 * a] = a; ar[2 * a + 1] = a; }
+  if (tid < 16) flags[tid] = 0;
+  for (int a = tid; a < N; a += WG) { lr[2 * a] = a; lr[2 * a + 1] = a; }
   __syncthreads();
 
+  // ---- validation and order checks (coalesced, no atomics on the data path)
+  bool bad = false, uns_e = false, uns_p = false, nonfin = false;
   for (int a = tid; a < N; a += WG) {
     const double* p = P.poses_in + 7 * (W.frame_off + a);
-    bool fin = true;
-    for (int m = 0; m < 7; ++m) fin = fin && isfinite_d(p[m]);
-    if (!fin) atomicOr(&flags[4], 1);
+    for (int m = 0; m < 7; ++m) nonfin |= !isfinite_d(p[m]);
   }
   for (int k = tid; k < M; k += WG) {
     const int a = anc[k];
-    if (a < 0 || a >= N) {
-      atomicOr(&flags[0], 1);
-    } else {
-      atomicAdd(&acnt[a], 1);
-    }
-    if (k > 0 && anc[k - 1] > a) atomicOr(&flags[2], 1);
+    bad |= (a < 0 || a >= N);
+    if (k > 0) uns_p |= anc[k - 1] > a;
     const double* pt = P.patches_in + 3 * (W.patch_off + k);
-    if (!(isfinite_d(pt[0]) && isfinite_d(pt[1]) && isfinite_d(pt[2]))) atomicOr(&flags[4], 1);
+    nonfin |= !(isfinite_d(pt[0]) && isfinite_d(pt[1]) && isfinite_d(pt[2]));
   }
   for (int e = tid; e < E; e += WG) {
     const int k = kk[e], j = jj[e];
-    if (k < 0 || k >= M || j < 0 || j >= N) {
-      atomicOr(&flags[0], 1);
-    } else {
-      atomicAdd(&cnt[k], 1);
-    }
+    bad |= (k < 0 || k >= M || j < 0 || j >= N);
     if (e > 0) {
       const int kp = kk[e - 1], jp = jj[e - 1];
-      if (kp > k || (kp == k && jp > j)) atomicOr(&flags[1], 1);
+      uns_e |= (kp > k || (kp == k && jp > j));
     }
   }
+  if (__any(bad) && lane_id() == 0) atomicOr(&flags[0], 1);
+  if (__any(uns_e) && lane_id() == 0) atomicOr(&flags[1], 1);
+  if (__any(uns_p) && lane_id() == 0) atomicOr(&flags[2], 1);
+  if (__any(nonfin) && lane_id() == 0) atomicOr(&flags[4], 1);
   __syncthreads();
-  const int bad = flags[0];
-  if (bad) {
+  if (flags[0]) {
     if (tid == 0) {
       P.status[w] = W_BAD_INDEX | (flags[4] ? W_NONFINITE : 0);
       P.wmeta[4 * w] = 0;
     }
     return;
   }
-  for (int k = tid; k < M; k += WG) {
-    ptr[k] = cnt[k];
-    atomicMax(&flags[3], cnt[k]);
-  }
-  __syncthreads();
-  wg_exclusive_scan(ptr, M, lds);
-  wg_exclusive_scan(acnt, N + 1, lds);
   const int unsorted_e = flags[1], unsorted_p = flags[2];
 
-  if (unsorted_p) {
-    for (int k = tid; k < M; k += WG) {
-      const int a = anc[k];
-      const int slot = atomicAdd(&afill[a], 1);
-      plist[acnt[a] + slot] = k;
+  // ---- edges per patch and first CSR slot of each patch
+  for (int k = tid; k < M; k += WG) cnt[k] = 0;
+  __syncthreads();
+  if (!unsorted_e) {
+    // sorted by (patch, target): run boundaries give the counts
+    for (int e = tid; e < E; e += WG) {
+      const int k = kk[e];
+      if (e == E - 1 || kk[e + 1] != k) cnt[k] = e + 1;   // one past the run
+    }
+    __syncthreads();
+    for (int e = tid; e < E; e += WG) {
+      const int k = kk[e];
+      if (e == 0 || kk[e - 1] != k) cnt[k] -= e;          // minus the run start
     }
   } else {
-    for (int k = tid; k < M; k += WG) plist[k] = k;
+    for (int k = tid; k < M; k += WG) fill[k] = 0;
+    __syncthreads();
+    for (int e = tid; e < E; e += WG) atomicAdd(&cnt[kk[e]], 1);
   }
+  __syncthreads();
+  int mx = 0;
+  for (int k = tid; k < M; k += WG) {
+    ptr[k] = cnt[k];
+    mx = max(mx, cnt[k]);
+  }
+  atomicMax(&flags[3], mx);
+  __syncthreads();
+  wg_exclusive_scan(ptr, M, lds);
   if (unsorted_e) {
     for (int e = tid; e < E; e += WG) {
       const int k = kk[e];
-      const int slot = atomicAdd(&fill[k], 1);
-      csr[ptr[k] + slot] = e;
+      csr[ptr[k] + atomicAdd(&fill[k], 1)] = e;
     }
-  } else {
-    for (int e = tid; e < E; e += WG) csr[e] = e;
-  }
-  __syncthreads();
-
-  // per-patch ordering by (target frame, edge index) and anchor frame ranges
-  for (int k = tid; k < M; k += WG) {
-    const int b = ptr[k], n = cnt[k];
-    if (unsorted_e) {
+    __syncthreads();
+    for (int k = tid; k < M; k += WG) {   // order each patch's edges by (target, index)
+      const int b = ptr[k], n = cnt[k];
       for (int x = 1; x < n; ++x) {
         const int e = csr[b + x];
         const int je = jj[e];
@@ -123,35 +152,113 @@ __device__ void wg_prep(const Params& P, int w, int* lds) {
         csr[b + y + 1] = e;
       }
     }
-    const int a = anc[k];
-    int lo = a, hi = a;
-    for (int x = 0; x < n; ++x) {
-      const int j = jj[csr[b + x]];
-      lo = min(lo, j);
-      hi = max(hi, j);
-    }
-    atomicMin(&ar[2 * a], lo);
-    atomicMax(&ar[2 * a + 1], hi);
   }
-  if (unsorted_p) {
+
+  // ---- positions: patches by (source frame, index)
+  if (!unsorted_p) {
+    for (int a = tid; a <= N; a += WG) acnt[a] = a == N ? M : lower_bound_i32(anc, M, a);
+    for (int k = tid; k < M; k += WG) pk[k] = k;
+  } else {
+    for (int a = tid; a <= N; a += WG) acnt[a] = 0;
+    for (int a = tid; a < N; a += WG) afill[a] = 0;
+    __syncthreads();
+    for (int k = tid; k < M; k += WG) atomicAdd(&acnt[anc[k]], 1);
+    __syncthreads();
+    wg_exclusive_scan(acnt, N + 1, lds);
+    for (int k = tid; k < M; k += WG) {
+      const int a = anc[k];
+      pk[acnt[a] + atomicAdd(&afill[a], 1)] = k;
+    }
+    __syncthreads();
     for (int a = tid; a < N; a += WG) {
       const int b = acnt[a], n = acnt[a + 1] - b;
       for (int x = 1; x < n; ++x) {
-        const int v = plist[b + x];
+        const int v = pk[b + x];
         int y = x - 1;
-        while (y >= 0 && plist[b + y] > v) {
-          plist[b + y + 1] = plist[b + y];
-          --y;
-        }
-        plist[b + y + 1] = v;
+        while (y >= 0 && pk[b + y] > v) { pk[b + y + 1] = pk[b + y]; --y; }
+        pk[b + y + 1] = v;
       }
     }
   }
   __syncthreads();
+
+  // ---- edge order offsets per position
+  for (int q = tid; q < M; q += WG) est[q] = cnt[pk[q]];
+  __syncthreads();
+  wg_exclusive_scan(est, M, lds);
+  if (tid == 0) est[M] = E;
+  // per-position pixel rays, initial depths, frame ranges
+  T* pxy = (T*)P.pxy + 2 * W.patch_off;
+  double* dep = P.depth_buf + W.patch_off;
+  for (int q = tid; q < M; q += WG) {
+    const int k = pk[q];
+    const double* pt = P.patches_in + 3 * (W.patch_off + k);
+    pxy[2 * q] = (T)((pt[0] - W.cx) / W.fx);
+    pxy[2 * q + 1] = (T)((pt[1] - W.cy) / W.fy);
+    dep[q] = pt[2];
+    const int n = cnt[k];
+    if (n > 0) {
+      const int a = anc[k];
+      const int b = ptr[k];
+      const int j0 = unsorted_e ? jj[csr[b]] : jj[b];
+      const int j1 = unsorted_e ? jj[csr[b + n - 1]] : jj[b + n - 1];
+      atomicMin(&lr[2 * a], j0);
+      atomicMax(&lr[2 * a + 1], j1);
+    }
+  }
+  __syncthreads();
+  // gathered edge arrays when the input is not already in edge order
+  const bool gathered = unsorted_e || unsorted_p;
+  if (gathered) {
+    int32_t* gj = P.gj + W.edge_off;
+    T* gt = (T*)P.gt + 2 * W.edge_off;
+    T* gw = (T*)P.gw + 2 * W.edge_off;
+    const T* tg = (const T*)P.targets + 2 * W.edge_off;
+    const T* wt = (const T*)P.weights + 2 * W.edge_off;
+    for (int q = tid; q < M; q += WG) {
+      const int k = pk[q];
+      const int b = ptr[k], n = cnt[k], o = est[q];
+      for (int x = 0; x < n; ++x) {
+        const int e = unsorted_e ? csr[b + x] : b + x;
+        gj[o + x] = jj[e];
+        gt[2 * (o + x)] = tg[2 * e];
+        gt[2 * (o + x) + 1] = tg[2 * e + 1];
+        gw[2 * (o + x)] = wt[2 * e];
+        gw[2 * (o + x) + 1] = wt[2 * e + 1];
+      }
+    }
+  }
+  // sub-batches per source frame
+  const int maxdeg = flags[3];
+  const int SBw = sb_width(seg_width(maxdeg));
   if (tid == 0) {
-    P.status[w] = flags[4] ? W_NONFINITE : 0;
-    P.wmeta[4 * w + 0] = flags[3];
-    P.wmeta[4 * w + 1] = unsorted_e;
+    int s = 0;
+    for (int a = 0; a < N; ++a) {
+      sbs[a] = s;
+      s += (acnt[a + 1] - acnt[a] + SBw - 1) / SBw;
+    }
+    sbs[N] = s;
+  }
+  for (int a = tid; a < N; a += WG) {
+    ar[2 * a] = lr[2 * a];
+    ar[2 * a + 1] = lr[2 * a + 1];
+  }
+  __syncthreads();
+  for (int a = tid; a < N; a += WG) {
+    const int p0 = acnt[a], p1 = acnt[a + 1];
+    int s = sbs[a];
+    for (int q = p0; q < p1; q += SBw, ++s) {
+      const int n = min(SBw, p1 - q);
+      sbd[s] = make_int4(q, (a << 8) | n, est[q], est[q + n]);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int st = flags[4] ? W_NONFINITE : 0;
+    if (maxdeg > 64) st |= W_DEGREE;
+    P.status[w] = st;
+    P.wmeta[4 * w + 0] = maxdeg;
+    P.wmeta[4 * w + 1] = gathered ? 1 : 0;
     P.wmeta[4 * w + 2] = unsorted_p;
   }
 }

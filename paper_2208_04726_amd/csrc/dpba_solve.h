@@ -2,7 +2,7 @@
 //
 // With the depths eliminated (Sec. 3.1, Schur complement), the pose step of a
 // window solves S dxi = -s, S = B + lambda I - E C^{-1} E^T, by a Cholesky
-// factorisation held in LDS; then every depth is recovered from its own row,
+// factorisation; then every depth is recovered from its own row,
 //   dd_k = -(w_k + sum_a E_ak^T dxi_a) / C_k,
 // and the state is updated, T_a <- Exp(dxi_a) T_a for free frames and
 // d_k <- d_k + dd_k.  The chunk partials of S and s are summed here in chunk
@@ -12,13 +12,13 @@
 
 namespace dpba {
 
+// LDS of the solve: 64 B header, A (n x (n+1)), b, x, two column buffers.
 __host__ __device__ inline int chol_lds_bytes(int n) {
   const int lda = n + 1;
-  return (n * lda + 2 * n + 8) * 8 + 64;
+  return 64 + (n * lda + 2 * n + 8) * 8 + 2 * 128 * 8;
 }
 
 // Sum the chunk partials of window w into A (n x lda, lower) and b (n).
-template <typename T>
 __device__ inline void gather_partials(const Params& P, int w, const WinDesc& W, double* A,
                                        int lda, double* b, int n) {
   const int tid = threadIdx.x;
@@ -32,13 +32,111 @@ __device__ inline void gather_partials(const Params& P, int w, const WinDesc& W,
     if (Dc == 0) continue;
     const int off = 6 * (lo_free - nfix);
     const double* part = P.partial + W.part_off + (int64_t)cc * W.part_stride;
-    for (int i = tid; i < Dc * Dc; i += WG) {
-      const int r = i / Dc, col = i % Dc;
-      if (col <= r) A[(off + r) * lda + off + col] += part[i];
-    }
+    for (int r = tid >> 4; r < Dc; r += WG >> 4)
+      for (int col = tid & 15; col <= r; col += 16) A[(off + r) * lda + off + col] += part[r * Dc + col];
     for (int r = tid; r < Dc; r += WG) b[off + r] += part[Dc * Dc + r];
     __syncthreads();
   }
+}
+
+// Cholesky of the n x n lower triangle in A (LDS), n <= 128, in place.  The
+// matrix is spread over the workgroup's registers: thread (tr, tc) =
+// (tid % 32, tid / 32) owns rows tr + 32 a and columns tc + 16 b.  Column k is
+// published through an LDS buffer (two alternating buffers, one barrier per
+// column) and every thread applies the rank-one update to its own elements.
+// Writes BA_W_* bits (non-positive or non-finite pivot) to *flag (thread 0).
+__device__ inline void wg_cholesky(double* A, int lda, int n, double* colbuf, int* flag) {
+  const int tid = threadIdx.x;
+  const int tr = tid & 31, tc = tid >> 5;
+  double Ar[4][8];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int i = tr + 32 * a, j = tc + 16 * b;
+      Ar[a][b] = (i < n && j <= i) ? A[i * lda + j] : 0.0;
+    }
+  int bad = 0;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 16 * b + kk;
+      if (k >= n) break;
+      double* buf = colbuf + (k & 1) * 128;
+      if (tc == kk) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int i = tr + 32 * a;
+          if (i >= k && i < n) buf[i] = Ar[a][b];
+        }
+      }
+      __syncthreads();
+      double d = buf[k];
+      if (!(d > 0.0) || !isfinite_d(d)) {
+        bad |= isfinite_d(d) ? W_NOT_SPD : W_NONFINITE;
+        d = 1.0;
+      }
+      const double lkk = sqrt(d);
+      const double inv = 1.0 / lkk;
+      double li[4], lj[8];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int i = tr + 32 * a;
+        li[a] = (i > k && i < n) ? buf[i] * inv : 0.0;
+      }
+#pragma unroll
+      for (int bb = 0; bb < 8; ++bb) {
+        const int j = tc + 16 * bb;
+        lj[bb] = (j > k && j < n) ? buf[j] * inv : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 8; ++bb) Ar[a][bb] -= li[a] * lj[bb];
+      if (tc == kk) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const int i = tr + 32 * a;
+          if (i == k) Ar[a][b] = lkk;
+          else if (i > k && i < n) Ar[a][b] = li[a];
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int i = tr + 32 * a, j = tc + 16 * b;
+      if (i < n && j <= i) A[i * lda + j] = Ar[a][b];
+    }
+  if (tid == 0) *flag = bad;
+}
+
+// L L^T x = rhs by one wave (lanes hold entries l and l + 64); L in LDS.
+__device__ inline void wave_cholesky_solve(const double* A, int lda, int n, const double* rhs,
+                                           double* x) {
+  const int l = lane_id();
+  double y0 = l < n ? rhs[l] : 0.0, y1 = l + 64 < n ? rhs[l + 64] : 0.0;
+  for (int k = 0; k < n; ++k) {   // L y = rhs
+    const double v = __shfl(k < 64 ? y0 : y1, k & 63, 64);
+    const double yk = v / A[k * lda + k];
+    if (l > k && l < n) y0 -= A[l * lda + k] * yk;
+    if (l + 64 > k && l + 64 < n) y1 -= A[(l + 64) * lda + k] * yk;
+    if (l == k) y0 = yk;
+    if (l + 64 == k) y1 = yk;
+  }
+  for (int k = n - 1; k >= 0; --k) {   // L^T x = y
+    const double v = __shfl(k < 64 ? y0 : y1, k & 63, 64);
+    const double xk = v / A[k * lda + k];
+    if (l < k) y0 -= A[k * lda + l] * xk;
+    if (l + 64 < k) y1 -= A[k * lda + l + 64] * xk;
+    if (l == k) y0 = xk;
+    if (l + 64 == k) y1 = xk;
+  }
+  if (l < n) x[l] = y0;
+  if (l + 64 < n) x[l + 64] = y1;
 }
 
 template <typename T>
@@ -60,49 +158,18 @@ __device__ void wg_chol(const Params& P, int w, int iter, char* smem) {
   double* A = (double*)(smem + 64);
   double* b = A + n * lda;
   double* x = b + n;
+  double* colbuf = x + n + 8;
   if (n > 0) {
-    gather_partials<T>(P, w, W, A, lda, b, n);
-    for (int i = tid; i < n; i += WG) A[i * lda + i] += P.lambda;
-    if (tid == 0) misc[1] = 0;
+    gather_partials(P, w, W, A, lda, b, n);
+    for (int i = tid; i < n; i += WG) {
+      A[i * lda + i] += P.lambda;
+      b[i] = -b[i];
+    }
     __syncthreads();
-    // right-looking Cholesky, lower triangle in place
-    for (int k = 0; k < n; ++k) {
-      if (tid == 0) {
-        double d = A[k * lda + k];
-        if (!(d > 0.0) || !isfinite_d(d)) {
-          misc[1] |= isfinite_d(d) ? W_NOT_SPD : W_NONFINITE;
-          d = 1.0;
-        }
-        A[k * lda + k] = sqrt(d);
-      }
-      __syncthreads();
-      const double lkk = A[k * lda + k];
-      for (int i = k + 1 + tid; i < n; i += WG) A[i * lda + k] /= lkk;
-      __syncthreads();
-      const int m = n - k - 1;
-      for (int idx = tid; idx < m * m; idx += WG) {
-        const int ii = idx / m, jj = idx % m;
-        if (jj <= ii) A[(k + 1 + ii) * lda + k + 1 + jj] -= A[(k + 1 + ii) * lda + k] * A[(k + 1 + jj) * lda + k];
-      }
-      __syncthreads();
-    }
-    // L y = -s ; L^T dxi = y
-    for (int i = tid; i < n; i += WG) x[i] = -b[i];
+    wg_cholesky(A, lda, n, colbuf, misc + 1);
     __syncthreads();
-    for (int k = 0; k < n; ++k) {
-      if (tid == 0) x[k] /= A[k * lda + k];
-      __syncthreads();
-      const double xk = x[k];
-      for (int i = k + 1 + tid; i < n; i += WG) x[i] -= A[i * lda + k] * xk;
-      __syncthreads();
-    }
-    for (int k = n - 1; k >= 0; --k) {
-      if (tid == 0) x[k] /= A[k * lda + k];
-      __syncthreads();
-      const double xk = x[k];
-      for (int i = tid; i < k; i += WG) x[i] -= A[k * lda + i] * xk;
-      __syncthreads();
-    }
+    if (tid < 64) wave_cholesky_solve(A, lda, n, b, x);
+    __syncthreads();
     if (tid == 0) {
       int bad = misc[1];
       for (int i = 0; i < n; ++i)
@@ -110,7 +177,6 @@ __device__ void wg_chol(const Params& P, int w, int iter, char* smem) {
       misc[2] = bad;
       if (bad) atomicOr(&P.status[w], bad);
     }
-    __syncthreads();
   } else if (tid == 0) {
     misc[2] = 0;
   }
@@ -131,17 +197,18 @@ __device__ void wg_chol(const Params& P, int w, int iter, char* smem) {
   }
 }
 
-__host__ __device__ inline int backsub_lds_bytes(int Rcap, int esize) {
-  return RMAX * RELW * esize + Rcap * 6 * 8 + 64;
-}
-
-// dd_k for the chunk's patches; writes the depth state (or depth_out on the
-// last iteration).
+// dd_k for the chunk's patches, from the same staged sub-batches as the
+// assembly; writes the depth state (position order) or, on the last
+// iteration, depth_out (patch order).
 template <typename T>
 __device__ void wg_backsub(const Params& P, int c, int iter, char* smem, int Rcap) {
-  T* rel = (T*)smem;
-  double* dx = (double*)(smem + RMAX * RELW * sizeof(T));
-  int* misc = (int*)(smem + RMAX * RELW * sizeof(T) + Rcap * 6 * 8);
+  double* lp = (double*)smem;
+  T* rel = (T*)(smem + Rcap * 7 * 8);
+  double* dx = (double*)(smem + Rcap * 7 * 8 + Rcap * RELW * sizeof(T));
+  int o = Rcap * 7 * 8 + Rcap * RELW * (int)sizeof(T) + Rcap * 6 * 8;
+  o = (o + 15) & ~15;
+  Stage<T> S(smem + o);
+  int* misc = (int*)(smem + o + stage_bytes((int)sizeof(T)));
   const ChunkDesc cd = P.chunk[c];
   const int w = cd.window;
   const WinDesc W = P.win[w];
@@ -153,10 +220,8 @@ __device__ void wg_backsub(const Params& P, int c, int iter, char* smem, int Rca
   if (st != 0) {
     if (last) {
       // failed window: its outputs are its inputs
-      const int pb = (cd.a_lo < W.n_frames && !(st & W_BAD_INDEX)) ? acnt[cd.a_lo] : 0;
-      const int pe = (cd.a_lo < W.n_frames && !(st & W_BAD_INDEX)) ? acnt[cd.a_hi] : 0;
       if (!(st & W_BAD_INDEX)) {
-        for (int q = pb + tid; q < pe; q += WG) {
+        for (int q = acnt[cd.a_lo] + tid; q < acnt[cd.a_hi]; q += WG) {
           const int k = plist[q];
           P.depth_out[W.patch_off + k] = P.patches_in[3 * (W.patch_off + k) + 2];
         }
@@ -167,72 +232,71 @@ __device__ void wg_backsub(const Params& P, int c, int iter, char* smem, int Rca
     }
     return;
   }
-  const int nfix = W.n_fixed;
-  int f_lo, f_hi;
-  chunk_range(P, W, cd, f_lo, f_hi);
+  const int N = W.n_frames;
   const double* poses = state_poses<T>(P, W, iter);
-  const double* dxi = P.dxi + 6 * W.frame_off;
-  for (int i = tid; i < 6 * (f_hi - f_lo + 1); i += WG) dx[i] = dxi[6 * f_lo + i];
+  for (int i = tid; i < 7 * N; i += WG) lp[i] = poses[i];
+  for (int i = tid; i < 6 * N; i += WG) dx[i] = P.dxi[6 * W.frame_off + i];
   const int32_t* ar = P.arange + 2 * W.frame_off;
-  const int32_t* cnt = P.cnt + W.patch_off;
-  const int32_t* ptr = P.ptr + W.patch_off;
-  const int32_t* csr = P.csr + W.edge_off;
-  const int32_t* jjw = P.jj + W.edge_off;
-  const T* tg = (const T*)P.targets + 2 * W.edge_off;
-  const T* wt = (const T*)P.weights + 2 * W.edge_off;
+  const int32_t* sbs = P.sbstart + W.frame_off + w;
+  const int4* sbd = P.sbd + W.sb_off;
+  const WinEdges we = win_edges(P, W, P.wmeta[4 * w + 1], (int)sizeof(T));
   const T fx = (T)W.fx, fy = (T)W.fy, cx = (T)W.cx, cy = (T)W.cy;
   const T zmin = (T)P.z_min, lam = (T)P.lambda;
-  const int maxdeg = P.wmeta[4 * w];
-  const int SEG = seg_width(maxdeg);
+  const int SEG = seg_width(P.wmeta[4 * w]);
+  const int SBw = sb_width(SEG);
   const int segs = 64 / SEG;
+  const int spw = SBw / NWAVES;
+  const int npass = (spw + segs - 1) / segs;
   const int lseg = lane & (SEG - 1), sidx = lane / SEG;
-  const int nch = (maxdeg + SEG - 1) / SEG;
-  double* dout = last ? P.depth_out + W.patch_off : P.depth_buf + W.patch_off;
+  const int s_lo = sbs[cd.a_lo], s_hi = sbs[cd.a_hi];
+  if (s_lo >= s_hi) return;
 
-  for (int a = cd.a_lo; a < cd.a_hi; ++a) {
-    const int lo = ar[2 * a], hi = ar[2 * a + 1];
-    load_relposes<T>(poses, a, lo, hi, f_lo, rel);
-    __syncthreads();
-    const int pb = acnt[a], pe = acnt[a + 1];
-    const double* dxa = dx + 6 * (a - f_lo);
-    for (int q0 = pb + wv * segs; q0 < pe; q0 += NWAVES * segs) {
-      const int q = q0 + sidx;
-      const bool pv = q < pe;
-      const int k = pv ? plist[q] : 0;
-      const int deg = pv ? cnt[k] : 0;
-      const int base = pv ? ptr[k] : 0;
-      const double* pt = P.patches_in + 3 * (W.patch_off + k);
-      const double d0 = state_depth(P, W, iter, k);
-      const T xb = (T)((pt[0] - W.cx) / W.fx);
-      const T yb = (T)((pt[1] - W.cy) / W.fy);
-      const T dk = (T)d0;
-      T s_cd = 0, s_wd = 0;
-      double s_t = 0.0;
-      for (int ch = 0; ch < nch; ++ch) {
-        const int es = ch * SEG + lseg;
-        const bool has = es < deg;
-        const int e = has ? csr[base + es] : 0;
-        const int j = has ? jjw[e] : a;
-        EdgeOut<T> eo;
-        linearize_edge<T>(rel + (j - f_lo) * RELW, xb, yb, dk, has ? tg[2 * e] : T(0),
-                          has ? tg[2 * e + 1] : T(0), has ? wt[2 * e] : T(0),
-                          has ? wt[2 * e + 1] : T(0), fx, fy, cx, cy, zmin, has && (j != a), eo);
-        s_cd += eo.cd;
-        s_wd += eo.wd;
-        if (eo.active) {
-          const double* dxj = dx + 6 * (j - f_lo);
-          double t = 0.0;
-#pragma unroll
-          for (int m = 0; m < 6; ++m) t += (double)eo.Ej[m] * dxj[m] + (double)eo.Ei[m] * dxa[m];
-          s_t += t;
-        }
-      }
-      const T Ck = lam + seg_sum(s_cd, SEG);
-      const T Wk = seg_sum(s_wd, SEG);
-      const double tk = seg_sum(s_t, SEG);
-      if (pv && lseg == 0) dout[k] = d0 - ((double)Wk + tk) / (double)Ck;
+  StageRegs<T> R;
+  int4 dcur = sbd[s_lo], dnxt = dcur;
+  if (s_lo + 1 < s_hi) dnxt = sbd[s_lo + 1];
+  stage_issue<T>(P, W, w, we, dcur, R);
+  __syncthreads();
+  stage_store<T>(dcur, R, S);
+  int a = -1;
+  for (int s = s_lo; s < s_hi; ++s) {
+    const int an = dcur.y >> 8, nsb = dcur.y & 255, pos0 = dcur.x;
+    if (an != a) {
+      a = an;
+      load_relposes<T>(lp, a, ar[2 * a], ar[2 * a + 1], 0, rel);
+    }
+    int4 dnn = dnxt;
+    if (s + 1 < s_hi) {
+      stage_issue<T>(P, W, w, we, dnxt, R);
+      if (s + 2 < s_hi) dnn = sbd[s + 2];
     }
     __syncthreads();
+    const double* dxa = dx + 6 * a;
+    for (int ps = 0; ps < npass; ++ps) {
+      const int slot_in_wave = ps * segs + sidx;
+      const LaneEdge<T> le = lane_edge<T>(S, wv * spw + slot_in_wave, slot_in_wave < spw, nsb, lseg, a);
+      EdgeOut<T> eo;
+      const int j = le.j;
+      linearize_edge<T>(rel + j * RELW, le.xb, le.yb, (T)le.d, le.t0, le.t1, le.w0, le.w1, fx,
+                        fy, cx, cy, zmin, le.has && (j != a), eo);
+      double t = 0.0;
+      if (eo.active) {
+        const double* dxj = dx + 6 * j;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) t += (double)eo.Ej[m] * dxj[m] + (double)eo.Ei[m] * dxa[m];
+      }
+      const T Ck = lam + seg_sum(eo.cd, SEG);
+      const T Wk = seg_sum(eo.wd, SEG);
+      const double tk = seg_sum(t, SEG);
+      if (le.pv && lseg == 0) {
+        const double dnew = le.d - ((double)Wk + tk) / (double)Ck;
+        if (last) P.depth_out[W.patch_off + S.pk[le.slot]] = dnew;
+        else P.depth_buf[W.patch_off + pos0 + le.slot] = dnew;
+      }
+    }
+    __syncthreads();
+    if (s + 1 < s_hi) stage_store<T>(dnxt, R, S);
+    dcur = dnxt;
+    dnxt = dnn;
   }
 }
 

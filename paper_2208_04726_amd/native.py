@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libdpba.so")
 BA_OK, BA_E_INVAL, BA_E_CAPACITY, BA_E_HIP, BA_E_STATE = 0, -1, -2, -3, -4
 BA_PREC_FP64, BA_PREC_FP32 = 0, 1
 BA_SCHED_AUTO, BA_SCHED_SPLIT, BA_SCHED_FUSED = 0, 1, 2
-BA_W_OK, BA_W_NOT_SPD, BA_W_NONFINITE, BA_W_BAD_INDEX = 0, 1, 2, 4
+BA_W_OK, BA_W_NOT_SPD, BA_W_NONFINITE, BA_W_BAD_INDEX, BA_W_DEGREE = 0, 1, 2, 4, 8
 
 EXPORTED = ("ba_create", "ba_solve", "ba_backward", "ba_status", "ba_last_error",
             "ba_destroy", "ba_debug_reduced_system", "ba_debug_mfma")
