@@ -55,7 +55,7 @@ __device__ inline int acc_row(double, int g, int r) { return 4 * r + g; }
 constexpr int SBMAX = 32;       // patches per sub-batch (K block of the Schur product)
 constexpr int SBE = 1024;       // staged edges per sub-batch (SB x lane segment width)
 constexpr int LDK = SBMAX + 4;  // LDS row length of the staged u rows
-constexpr int RELW = 24;        // LDS words per relative pose: R(9) t(3) hat(t)R(9)
+constexpr int RELW = 25;        // LDS words per relative pose: R(9) t(3) hat(t)R(9); odd stride, no bank conflicts
 
 // LDS layout of the assembly and back-substitution stages, in bytes, for
 // windows of at most Rcap frames.  Shared with the host to size the launch.
@@ -66,29 +66,35 @@ struct AsmLayout {
 __host__ __device__ inline int stage_bytes(int esize) {
   return SBE * (4 + 4 * esize) + SBMAX * (4 + 2 * esize + 8) + (SBMAX + 1) * 4;
 }
+// Lane segments of a wave add their pair-table entries into separate copies
+// (two per wave when they fit), so they need not take turns.
+__host__ __device__ inline int table_slots(int Rcap) { return Rcap <= 32 ? 2 : 1; }
+__host__ __device__ inline int al16(int o) { return (o + 15) & ~15; }
 __host__ __device__ inline AsmLayout asm_layout(int Rcap, int esize) {
   AsmLayout L;
   const int Dcap = 6 * Rcap;
   L.Tcap = (Dcap + 1 + 15) / 16;
   int o = 0;
-  L.poses = o; o += Rcap * 7 * 8;
-  L.rel = o;   o += Rcap * RELW * esize;
-  L.tbl = o;   o += NWAVES * Rcap * TBL * esize;
-  L.G = o;     o += (Rcap * 36 + 42) * esize;
-  L.U = o;     o += 16 * L.Tcap * LDK * esize;
-  L.tiles = o; o += 4 * ((L.Tcap * (L.Tcap + 1)) / 2 + 4);
-  o = (o + 15) & ~15;
-  L.stage = o; o += stage_bytes(esize);
-  o = (o + 15) & ~15;
+  L.poses = o; o = al16(o + Rcap * 7 * 8);
+  L.rel = o;   o = al16(o + Rcap * RELW * esize);
+  L.tbl = o;   o = al16(o + NWAVES * table_slots(Rcap) * Rcap * TBL * esize);
+  L.G = o;     o = al16(o + (Rcap * 36 + 42) * esize);
+  L.U = o;     o = al16(o + 16 * L.Tcap * LDK * esize);
+  L.tiles = o; o = al16(o + 4 * ((L.Tcap * (L.Tcap + 1)) / 2 + 4));
+  L.stage = o; o = al16(o + stage_bytes(esize));
   L.misc = o;  o += 64;
   L.total = (o + 255) & ~255;
   return L;
 }
 // back-substitution: poses, relative poses, pose steps, stage
+__host__ __device__ inline int backsub_dx_offset(int Rcap, int esize) {
+  return al16(al16(Rcap * 7 * 8) + Rcap * RELW * esize);
+}
+__host__ __device__ inline int backsub_stage_offset(int Rcap, int esize) {
+  return al16(backsub_dx_offset(Rcap, esize) + Rcap * 6 * 8);
+}
 __host__ __device__ inline int backsub_lds_bytes(int Rcap, int esize) {
-  int o = Rcap * 7 * 8 + Rcap * RELW * esize + Rcap * 6 * 8;
-  o = (o + 15) & ~15;
-  return o + stage_bytes(esize) + 64;
+  return backsub_stage_offset(Rcap, esize) + stage_bytes(esize) + 64;
 }
 
 // packed index of (m, n), m <= n, in the 21-entry upper triangle of a 6x6
@@ -393,6 +399,7 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
   const int npass = (spw + segs - 1) / segs;
   const int lseg = lane & (SEG - 1), sidx = lane / SEG;
   const int s_lo = sbs[cd.a_lo], s_hi = sbs[cd.a_hi];
+  const int tslots = min(segs, table_slots(Rcap));   // pair-table copies per wave
 
   // lower-triangle tiles of the (D+1) x (D+1) product, row-major
   const int Daug = D + 1;
@@ -438,7 +445,7 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
         __syncthreads();
         for (int i = tid; i < Ra * TBL; i += WG) {
           T sum = 0;
-          for (int x = 0; x < NWAVES; ++x) sum += tbl[x * Ra * TBL + i];
+          for (int x = 0; x < NWAVES * tslots; ++x) sum += tbl[x * Ra * TBL + i];
           tbl[i] = sum;
         }
         __syncthreads();
@@ -447,9 +454,13 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
           const int jr = i / 36, m = (i % 36) / 6, n = i % 6;
           const T* rj = rel + (lo + jr - f_lo) * RELW;
           const T* Q = tbl + jr * TBL;
-          T sum = 0;
-#pragma unroll
-          for (int p = 0; p < 6; ++p) sum += adj_at(rj, p, m) * Q[sym6(p, n)];
+          const int mm = m < 3 ? m : m - 3;
+          // rows p = 0..2 of A carry R (m < 3) or hat(t)R (m >= 3); rows 3..5
+          // carry R for m >= 3 only
+          const T* top = m < 3 ? rj : rj + 12;
+          T sum = top[mm] * Q[sym6(0, n)] + top[3 + mm] * Q[sym6(1, n)] + top[6 + mm] * Q[sym6(2, n)];
+          if (m >= 3)
+            sum += rj[mm] * Q[sym6(3, n)] + rj[3 + mm] * Q[sym6(4, n)] + rj[6 + mm] * Q[sym6(5, n)];
           G[i] = sum;
         }
         __syncthreads();
@@ -533,7 +544,7 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
         hi = ar[2 * a + 1];
         Ra = hi - lo + 1;
         load_relposes<T>(lp, a, lo, hi, f_lo, rel);
-        for (int i = tid; i < NWAVES * Ra * TBL; i += WG) tbl[i] = T(0);
+        for (int i = tid; i < NWAVES * tslots * Ra * TBL; i += WG) tbl[i] = T(0);
         nz_lo = 6 * (max(lo, lo_free) - lo_free);
         nz_hi = (hi >= lo_free) ? 6 * (hi - lo_free + 1) : 0;
         a_free = a >= nfix;
@@ -549,7 +560,7 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
       __syncthreads();
 
       // ---- linearise this wave's patches, one lane segment per patch
-      T* mytbl = tbl + wv * Ra * TBL;
+      T* mytbl = tbl + wv * tslots * Ra * TBL;
       for (int ps = 0; ps < npass; ++ps) {
         const int slot_in_wave = ps * segs + sidx;
         const LaneEdge<T> le = lane_edge<T>(S, wv * spw + slot_in_wave, slot_in_wave < spw, nsb, lseg, a);
@@ -565,10 +576,10 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
         const int jprev = __shfl_up(j, 1, 64);
         const bool dup = eo.active && lseg > 0 && jprev == j;
         const bool anydup = __any(dup);
-        T* tb = mytbl + (j - lo) * TBL;
-        for (int sgi = 0; sgi < segs; ++sgi) {
+        T* tb = mytbl + ((sidx % tslots) * Ra + (j - lo)) * TBL;
+        for (int sgi = 0; sgi < segs; sgi += tslots) {
           for (int ln = 0; ln < (anydup ? SEG : 1); ++ln) {
-            if (sidx == sgi && eo.active && (!anydup || lseg == ln)) {
+            if (sidx - sidx % tslots == sgi && eo.active && (!anydup || lseg == ln)) {
               int q = 0;
 #pragma unroll
               for (int m = 0; m < 6; ++m)
@@ -581,11 +592,11 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
             }
           }
         }
-        const T Ck = lam + seg_sum(eo.cd, SEG);
-        const T Wk = seg_sum(eo.wd, SEG);
-        T Eik[6];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) Eik[m] = seg_sum(eo.Ei[m], SEG);
+        T red[8] = {eo.cd, eo.wd, eo.Ei[0], eo.Ei[1], eo.Ei[2], eo.Ei[3], eo.Ei[4], eo.Ei[5]};
+        seg_sum8(red, SEG);
+        const T Ck = lam + red[0];
+        const T Wk = red[1];
+        const T* Eik = red + 2;
         const T rs = T(1) / __builtin_sqrt(Ck);
         // staged row u_k: E_jk / sqrt(C_k) at target columns, E_ik / sqrt(C_k) at
         // the source frame's columns, w_k / sqrt(C_k) at column D

@@ -90,6 +90,19 @@ __device__ inline T seg_sum(T v, int seg) {
   return v;
 }
 
+// Eight butterfly all-reduces at once: the eight exchanges of each step are
+// issued back to back, so the lane exchanges of the step overlap.
+template <typename T>
+__device__ inline void seg_sum8(T* v, int seg) {
+  for (int o = seg >> 1; o > 0; o >>= 1) {
+    T x[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) x[m] = __shfl_xor(v[m], o, 64);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[m] += x[m];
+  }
+}
+
 __device__ inline bool isfinite_d(double x) { return __builtin_isfinite(x); }
 __device__ inline bool isfinite_f(float x) { return __builtin_isfinite(x); }
 

@@ -203,10 +203,9 @@ __device__ void wg_chol(const Params& P, int w, int iter, char* smem) {
 template <typename T>
 __device__ void wg_backsub(const Params& P, int c, int iter, char* smem, int Rcap) {
   double* lp = (double*)smem;
-  T* rel = (T*)(smem + Rcap * 7 * 8);
-  double* dx = (double*)(smem + Rcap * 7 * 8 + Rcap * RELW * sizeof(T));
-  int o = Rcap * 7 * 8 + Rcap * RELW * (int)sizeof(T) + Rcap * 6 * 8;
-  o = (o + 15) & ~15;
+  T* rel = (T*)(smem + al16(Rcap * 7 * 8));
+  double* dx = (double*)(smem + backsub_dx_offset(Rcap, (int)sizeof(T)));
+  const int o = backsub_stage_offset(Rcap, (int)sizeof(T));
   Stage<T> S(smem + o);
   int* misc = (int*)(smem + o + stage_bytes((int)sizeof(T)));
   const ChunkDesc cd = P.chunk[c];
@@ -284,9 +283,16 @@ __device__ void wg_backsub(const Params& P, int c, int iter, char* smem, int Rca
 #pragma unroll
         for (int m = 0; m < 6; ++m) t += (double)eo.Ej[m] * dxj[m] + (double)eo.Ei[m] * dxa[m];
       }
-      const T Ck = lam + seg_sum(eo.cd, SEG);
-      const T Wk = seg_sum(eo.wd, SEG);
-      const double tk = seg_sum(t, SEG);
+      T red[8] = {eo.cd, eo.wd, T(0), T(0), T(0), T(0), T(0), T(0)};
+      double dred[8] = {t, 0, 0, 0, 0, 0, 0, 0};
+      for (int o2 = SEG >> 1; o2 > 0; o2 >>= 1) {
+        const T x0 = __shfl_xor(red[0], o2, 64), x1 = __shfl_xor(red[1], o2, 64);
+        const double x2 = __shfl_xor(dred[0], o2, 64);
+        red[0] += x0; red[1] += x1; dred[0] += x2;
+      }
+      const T Ck = lam + red[0];
+      const T Wk = red[1];
+      const double tk = dred[0];
       if (le.pv && lseg == 0) {
         const double dnew = le.d - ((double)Wk + tk) / (double)Ck;
         if (last) P.depth_out[W.patch_off + S.pk[le.slot]] = dnew;
