@@ -13,6 +13,7 @@
 #include "dpba_prep.h"
 #include "dpba_assemble.h"
 #include "dpba_solve.h"
+#include "dpba_adjoint.h"
 
 using namespace dpba;
 
@@ -43,6 +44,23 @@ __global__ void __launch_bounds__(WG) k_backsub(Params P, int iter, int Rcap) {
 }
 
 __global__ void __launch_bounds__(WG) k_finalize(Params P) { wg_finalize(P, blockIdx.x); }
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_adj_init(Params P) { wg_adj_init<T>(P, blockIdx.x); }
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_chol_adj(Params P, int iter) {
+  extern __shared__ __align__(16) char smem[];
+  wg_chol_adj<T>(P, blockIdx.x, iter, smem);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_edge_adj(Params P, int iter, int Rcap) {
+  extern __shared__ __align__(16) char smem[];
+  wg_edge_adj<T>(P, blockIdx.x, iter, smem, Rcap);
+}
+
+__global__ void __launch_bounds__(WG) k_frame_adj(Params P) { wg_frame_adj(P, blockIdx.x); }
 
 // Persistent form: each workgroup takes whole windows (one chunk each) and
 // runs preparation and every stage of every iteration without leaving the
@@ -116,6 +134,8 @@ struct ba_handle {
   int4* sbd = nullptr;
   void *pxy = nullptr, *gt = nullptr, *gw = nullptr;
   int64_t cap_sb = 0;
+  int32_t* gidx = nullptr;
+  double *xib = nullptr, *xid = nullptr, *qxi = nullptr, *dbar = nullptr, *fcot = nullptr;
   double* partial = nullptr;
   double *dxi = nullptr, *pose_buf = nullptr, *depth_buf = nullptr;
   std::string err;
@@ -145,6 +165,8 @@ int set_kernel_attrs() {
   if (hipFuncSetAttribute((const void*)k_chol<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_backsub<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_debug_gather<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chol_adj<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_edge_adj<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   return 0;
 }
 
@@ -229,7 +251,7 @@ int build_descriptors(ba_handle* h, const ba_problem* p, Plan& pl) {
       const int nc = N == 0 ? 0 : (N + cw - 1) / cw;
       const int64_t D = 6LL * (N - p->n_fixed[w]);
       chunks += nc;
-      part += nc * (D * D + D);
+      part += nc * (D * D + 2 * D);
     }
     if (chunks <= h->cap_chunks && part <= h->cap_partial) break;
     if (pl.fused) return fail(h, BA_E_CAPACITY, "partial workspace too small");
@@ -262,7 +284,7 @@ int build_descriptors(ba_handle* h, const ba_problem* p, Plan& pl) {
     d.chunk_off = ci;
     d.n_chunks = nc;
     d.part_off = part_off;
-    d.part_stride = D * D + D;
+    d.part_stride = D * D + 2 * D;
     d.sb_off = sb_off;
     sb_off += (d.n_patches + 15) / 16 + N + 1;
     for (int q = 0; q < nc; ++q) {
@@ -279,9 +301,7 @@ int build_descriptors(ba_handle* h, const ba_problem* p, Plan& pl) {
   return BA_OK;
 }
 
-template <typename T>
-int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t s) {
-  Params P;
+void fill_params(ba_handle* h, const ba_problem* p, const Plan& pl, Params& P) {
   memset(&P, 0, sizeof(P));
   P.win = h->d_win;
   P.chunk = h->d_chunk;
@@ -315,6 +335,7 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
   P.pose_buf = h->pose_buf;
   P.depth_buf = h->depth_buf;
   P.n_frames_total = h->cfg.max_frames;
+  P.n_patches_total = std::max<int64_t>(h->cfg.max_patches, 1);
   P.estart = h->estart;
   P.sbstart = h->sbstart;
   P.sbd = h->sbd;
@@ -322,12 +343,31 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
   P.gj = h->gj;
   P.gt = h->gt;
   P.gw = h->gw;
+  P.gidx = h->gidx;
+  P.xib = h->xib;
+  P.xid = h->xid;
+  P.qxi = h->qxi;
+  P.dbar = h->dbar;
+  P.fcot = h->fcot;
+}
 
+int upload_descriptors(ba_handle* h, const Plan& pl, hipStream_t s) {
   HIPCHK(h, hipMemcpyAsync(h->d_win, h->h_win, sizeof(WinDesc) * pl.W, hipMemcpyHostToDevice, s));
   if (pl.C > 0)
     HIPCHK(h, hipMemcpyAsync(h->d_chunk, h->h_chunk, sizeof(ChunkDesc) * pl.C, hipMemcpyHostToDevice, s));
   HIPCHK(h, hipEventRecord(h->staging_ev, s));
   h->staging_pending = true;
+  return BA_OK;
+}
+
+template <typename T>
+int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t s) {
+  Params P;
+  fill_params(h, p, pl, P);
+  {
+    const int r = upload_descriptors(h, pl, s);
+    if (r != BA_OK) return r;
+  }
 
   const int Rcap = pl.Rcap;
   const int asm_lds = asm_layout(Rcap, (int)sizeof(T)).total;
@@ -356,6 +396,50 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
       }
     }
     hipLaunchKernelGGL(k_finalize, dim3(pl.W), dim3(WG), 0, s, P);
+    HIPCHK(h, hipGetLastError());
+  }
+  return BA_OK;
+}
+
+template <typename T>
+int launch_backward(ba_handle* h, const ba_problem* p, const Plan& pl, const double* grad_poses,
+                    const double* grad_depth, void* grad_targets, void* grad_weights,
+                    hipStream_t s) {
+  Params P;
+  fill_params(h, p, pl, P);
+  P.grad_poses = grad_poses;
+  P.grad_depth = grad_depth;
+  P.grad_targets = grad_targets;
+  P.grad_weights = grad_weights;
+  int r = upload_descriptors(h, pl, s);
+  if (r != BA_OK) return r;
+  const int Rcap = pl.Rcap, esz = (int)sizeof(T);
+  const int asm_lds = asm_layout(Rcap, esz).total;
+  const int bs_lds = backsub_lds_bytes(Rcap, esz);
+  const int chol_lds = chol_lds_bytes(pl.nmax);
+  const int chol_adj_lds = chol_lds + 2 * 8 * pl.nmax + 64;
+  const int adj_lds = edge_adj_lds_bytes(Rcap, esz);
+  const int K = P.iterations;
+  hipLaunchKernelGGL(k_prep<T>, dim3(pl.W), dim3(WG), 0, s, P);
+  HIPCHK(h, hipGetLastError());
+  // recompute the iterates x_1 .. x_{K-1}
+  for (int it = 0; it + 1 < K; ++it) {
+    if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<T, 4>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
+    else hipLaunchKernelGGL((k_assemble<T, 8>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
+    hipLaunchKernelGGL(k_chol<T>, dim3(pl.W), dim3(WG), chol_lds, s, P, it);
+    hipLaunchKernelGGL(k_backsub<T>, dim3(pl.C), dim3(WG), bs_lds, s, P, it, Rcap);
+    HIPCHK(h, hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_adj_init<T>, dim3(pl.W), dim3(WG), 0, s, P);
+  HIPCHK(h, hipGetLastError());
+  Params PA = P;
+  PA.adjoint = 1;
+  for (int it = K - 1; it >= 0; --it) {
+    if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<T, 4>), dim3(pl.C), dim3(WG), asm_lds, s, PA, it, Rcap);
+    else hipLaunchKernelGGL((k_assemble<T, 8>), dim3(pl.C), dim3(WG), asm_lds, s, PA, it, Rcap);
+    hipLaunchKernelGGL(k_chol_adj<T>, dim3(pl.W), dim3(WG), chol_adj_lds, s, PA, it);
+    hipLaunchKernelGGL(k_edge_adj<T>, dim3(pl.C), dim3(WG), adj_lds, s, PA, it, Rcap);
+    hipLaunchKernelGGL(k_frame_adj, dim3(pl.W), dim3(WG), 0, s, PA);
     HIPCHK(h, hipGetLastError());
   }
   return BA_OK;
@@ -395,7 +479,7 @@ int ba_create(const ba_config* cfg, ba_handle** out) {
   const int64_t Dmax = 6LL * cfg->max_frames_per_window;
   const size_t esz = cfg->precision == BA_PREC_FP32 ? 4 : 8;
   h->cap_chunks = std::max<int64_t>(F, W);
-  h->cap_partial = std::max<int64_t>(W, 32) * (Dmax * Dmax + Dmax);
+  h->cap_partial = std::max<int64_t>(W, 32) * (Dmax * Dmax + 2 * Dmax);
   bool ok = true;
   auto dmalloc = [&](void** ptr, size_t bytes) {
     if (!ok) return;
@@ -416,8 +500,15 @@ int ba_create(const ba_config* cfg, ba_handle** out) {
   dmalloc((void**)&h->cstate, 8 * h->cap_chunks);
   dmalloc((void**)&h->partial, 8 * h->cap_partial);
   dmalloc((void**)&h->dxi, 8 * 6 * F);
-  dmalloc((void**)&h->pose_buf, 8 * 2 * 7 * F);
-  dmalloc((void**)&h->depth_buf, 8 * Pn);
+  const int64_t slots = cfg->iterations + 1;
+  dmalloc((void**)&h->pose_buf, 8 * slots * 7 * F);
+  dmalloc((void**)&h->depth_buf, 8 * slots * Pn);
+  dmalloc((void**)&h->gidx, 4 * E);
+  dmalloc((void**)&h->xib, 8 * 6 * F);
+  dmalloc((void**)&h->xid, 8 * 6 * F);
+  dmalloc((void**)&h->qxi, 8 * 6 * F);
+  dmalloc((void**)&h->dbar, 8 * 2 * Pn);
+  dmalloc((void**)&h->fcot, 8 * RMAX * 6 * h->cap_chunks);
   h->cap_sb = Pn / 16 + F + 2 * W;
   dmalloc((void**)&h->estart, 4 * (Pn + W));
   dmalloc((void**)&h->sbstart, 4 * (F + W));
@@ -451,9 +542,29 @@ int ba_solve(ba_handle* h, const ba_problem* p, void* stream) {
                                           : launch_solve<double>(h, p, pl, s);
 }
 
-int ba_backward(ba_handle* h, const ba_problem*, const double*, const double*, void*, void*, void*) {
+int ba_backward(ba_handle* h, const ba_problem* p, const double* grad_poses,
+                const double* grad_depth, void* grad_targets, void* grad_weights, void* stream) {
   if (!h) return BA_E_INVAL;
-  return fail(h, BA_E_STATE, "ba_backward: not available in this build");
+  h->err.clear();
+  Plan pl;
+  int r = validate_and_plan(h, p, pl);
+  if (r != BA_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  h->last_W = pl.W;
+  if (pl.W == 0) return BA_OK;
+  if (h->cfg.iterations < 1) return fail(h, BA_E_STATE, "ba_backward needs at least one iteration");
+  if ((pl.F > 0 && !grad_poses) || (pl.Pn > 0 && !grad_depth) ||
+      (pl.E > 0 && (!grad_targets || !grad_weights)))
+    return fail(h, BA_E_INVAL, "gradient pointer is NULL");
+  const int saved = h->cfg.schedule;
+  h->cfg.schedule = BA_SCHED_SPLIT;
+  r = build_descriptors(h, p, pl);
+  h->cfg.schedule = saved;
+  if (r != BA_OK) return r;
+  return h->cfg.precision == BA_PREC_FP32
+             ? launch_backward<float>(h, p, pl, grad_poses, grad_depth, grad_targets, grad_weights, s)
+             : launch_backward<double>(h, p, pl, grad_poses, grad_depth, grad_targets, grad_weights, s);
 }
 
 int ba_status(ba_handle* h, int32_t* host_flags) {
@@ -493,6 +604,12 @@ void ba_destroy(ba_handle* h) {
   hipFree(h->gj);
   hipFree(h->gt);
   hipFree(h->gw);
+  hipFree(h->gidx);
+  hipFree(h->xib);
+  hipFree(h->xid);
+  hipFree(h->qxi);
+  hipFree(h->dbar);
+  hipFree(h->fcot);
   if (h->h_win) hipHostFree(h->h_win);
   if (h->h_chunk) hipHostFree(h->h_chunk);
   if (h->staging_ev) hipEventDestroy(h->staging_ev);
@@ -517,22 +634,10 @@ int ba_debug_reduced_system(ba_handle* h, const ba_problem* p, int32_t window, d
   h->last_stream = s;
   h->last_W = pl.W;
   Params P;
-  memset(&P, 0, sizeof(P));
-  P.win = h->d_win; P.chunk = h->d_chunk; P.n_windows = pl.W; P.n_chunks = pl.C;
-  P.iterations = 1; P.lambda = h->cfg.lambda; P.z_min = h->cfg.z_min;
-  P.poses_in = p->poses_in; P.patches_in = p->patches_in; P.anchor = p->anchor; P.kk = p->kk;
-  P.jj = p->jj; P.targets = p->targets; P.weights = p->weights;
-  P.status = h->status; P.wmeta = h->wmeta; P.cnt = h->cnt; P.ptr = h->ptr; P.fill = h->fill;
-  P.acnt = h->acnt; P.afill = h->afill; P.plist = h->plist; P.csr = h->csr; P.arange = h->arange;
-  P.cstate = h->cstate; P.partial = h->partial; P.dxi = h->dxi; P.pose_buf = h->pose_buf;
-  P.depth_buf = h->depth_buf; P.n_frames_total = h->cfg.max_frames;
-  P.estart = h->estart; P.sbstart = h->sbstart; P.sbd = h->sbd; P.pxy = h->pxy;
-  P.gj = h->gj; P.gt = h->gt; P.gw = h->gw;
-  HIPCHK(h, hipMemcpyAsync(h->d_win, h->h_win, sizeof(WinDesc) * pl.W, hipMemcpyHostToDevice, s));
-  if (pl.C > 0)
-    HIPCHK(h, hipMemcpyAsync(h->d_chunk, h->h_chunk, sizeof(ChunkDesc) * pl.C, hipMemcpyHostToDevice, s));
-  HIPCHK(h, hipEventRecord(h->staging_ev, s));
-  h->staging_pending = true;
+  fill_params(h, p, pl, P);
+  P.iterations = 1;
+  r = upload_descriptors(h, pl, s);
+  if (r != BA_OK) return r;
   const bool f32 = h->cfg.precision == BA_PREC_FP32;
   const int esz = f32 ? 4 : 8;
   if (f32) hipLaunchKernelGGL(k_prep<float>, dim3(pl.W), dim3(WG), 0, s, P);

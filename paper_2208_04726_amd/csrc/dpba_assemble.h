@@ -64,11 +64,11 @@ struct AsmLayout {
   int Tcap;
 };
 __host__ __device__ inline int stage_bytes(int esize) {
-  return SBE * (4 + 4 * esize) + SBMAX * (4 + 2 * esize + 8) + (SBMAX + 1) * 4;
+  return SBE * (4 + 4 * esize) + SBMAX * (4 + 2 * esize + 16) + (SBMAX + 1) * 4;
 }
 // Lane segments of a wave add their pair-table entries into separate copies
 // (two per wave when they fit), so they need not take turns.
-__host__ __device__ inline int table_slots(int Rcap) { return Rcap <= 32 ? 2 : 1; }
+__host__ __device__ inline int table_slots(int Rcap, int esize) { return (esize == 4 ? Rcap <= 32 : Rcap <= 16) ? 2 : 1; }
 __host__ __device__ inline int al16(int o) { return (o + 15) & ~15; }
 __host__ __device__ inline AsmLayout asm_layout(int Rcap, int esize) {
   AsmLayout L;
@@ -77,7 +77,7 @@ __host__ __device__ inline AsmLayout asm_layout(int Rcap, int esize) {
   int o = 0;
   L.poses = o; o = al16(o + Rcap * 7 * 8);
   L.rel = o;   o = al16(o + Rcap * RELW * esize);
-  L.tbl = o;   o = al16(o + NWAVES * table_slots(Rcap) * Rcap * TBL * esize);
+  L.tbl = o;   o = al16(o + NWAVES * table_slots(Rcap, esize) * Rcap * TBL * esize);
   L.G = o;     o = al16(o + (Rcap * 36 + 42) * esize);
   L.U = o;     o = al16(o + 16 * L.Tcap * LDK * esize);
   L.tiles = o; o = al16(o + 4 * ((L.Tcap * (L.Tcap + 1)) / 2 + 4));
@@ -110,6 +110,7 @@ struct EdgeOut {
   T Ei[6];         // J_i^T W J_d = -Ad^T Ej
   T J0[6], J1[6];  // rows of J_j
   T r0, r1, w0, w1;
+  T X, Y, Z, jd0, jd1;   // reprojected point, J_d
   bool active;
   int j;
 };
@@ -137,6 +138,7 @@ __device__ inline void linearize_edge(const T* rel, T xb, T yb, T d, T tx, T ty,
   o.J1[3] = Y * c1 - Z * b; o.J1[4] = -X * c1; o.J1[5] = X * b;
   const T jd0 = a * rel[9] + c0 * rel[11];
   const T jd1 = b * rel[10] + c1 * rel[11];
+  o.X = X; o.Y = Y; o.Z = Z; o.jd0 = jd0; o.jd1 = jd1;
   const T g0 = o.w0 * jd0, g1 = o.w1 * jd1;
   o.cd = g0 * jd0 + g1 * jd1;
   o.wd = g0 * o.r0 + g1 * o.r1;
@@ -189,10 +191,14 @@ __device__ inline T adj_at(const T* rel, int p, int q) {
   return q < 3 ? T(0) : rel[3 * (p - 3) + (q - 3)];
 }
 
+// State after `iter` iterations: poses (slot iter of pose_buf) and inverse
+// depths (slot iter of depth_buf, position order); slot 0 holds the inputs.
 template <typename T>
 __device__ inline const double* state_poses(const Params& P, const WinDesc& W, int iter) {
-  return iter == 0 ? P.poses_in + 7 * W.frame_off
-                   : P.pose_buf + (int64_t)(iter & 1) * 7 * P.n_frames_total + 7 * W.frame_off;
+  return P.pose_buf + (int64_t)iter * 7 * P.n_frames_total + 7 * W.frame_off;
+}
+__device__ inline double* state_depth(const Params& P, const WinDesc& W, int iter) {
+  return P.depth_buf + (int64_t)iter * P.n_patches_total + W.patch_off;
 }
 
 // ---------------------------------------------------------------------------
@@ -206,13 +212,14 @@ __device__ inline const double* state_poses(const Params& P, const WinDesc& W, i
 // latency overlaps the linearisation and the matrix-core work.
 template <typename T>
 struct Stage {
-  int32_t* j; T* t; T* w; int32_t* pk; int32_t* pe; T* px; T* py; double* pd;
+  int32_t* j; T* t; T* w; int32_t* pk; int32_t* pe; T* px; T* py; double* pd; double* pd2;
   __device__ Stage(char* base) {
     j = (int32_t*)base;
     t = (T*)(base + SBE * 4);
     w = (T*)(base + SBE * (4 + 2 * sizeof(T)));
     char* q = base + SBE * (4 + 4 * sizeof(T));
     pd = (double*)q; q += SBMAX * 8;
+    pd2 = (double*)q; q += SBMAX * 8;
     px = (T*)q; q += SBMAX * sizeof(T);
     py = (T*)q; q += SBMAX * sizeof(T);
     pk = (int32_t*)q; q += SBMAX * 4;
@@ -226,7 +233,7 @@ struct StageRegs {
   T t[4], w[4];
   int32_t pk, pe;
   T px, py;
-  double pd;
+  double pd, pd2;
 };
 
 struct WinEdges {   // edge arrays in edge order (inputs, or the gathered copies)
@@ -249,9 +256,11 @@ __device__ inline WinEdges win_edges(const Params& P, const WinDesc& W, int gath
   return e;
 }
 
+// `iter` selects the inverse-depth state; `extra` (optional, position order)
+// is staged alongside (the depth cotangents of the adjoint).
 template <typename T>
 __device__ inline void stage_issue(const Params& P, const WinDesc& W, int w, const WinEdges& we,
-                                   int4 d, StageRegs<T>& R) {
+                                   int4 d, int iter, const double* extra, StageRegs<T>& R) {
   const int tid = threadIdx.x;
   const int pos0 = d.x, n = d.y & 255, e0 = d.z, e1 = d.w;
   const T* tg = (const T*)we.t;
@@ -276,7 +285,8 @@ __device__ inline void stage_issue(const Params& P, const WinDesc& W, int w, con
     const T* pxy = (const T*)P.pxy + 2 * (W.patch_off + pos0 + tid);
     R.px = pxy[0];
     R.py = pxy[1];
-    R.pd = P.depth_buf[W.patch_off + pos0 + tid];
+    R.pd = state_depth(P, W, iter)[pos0 + tid];
+    R.pd2 = extra ? extra[W.patch_off + pos0 + tid] : 0.0;
   }
 }
 
@@ -301,6 +311,7 @@ __device__ inline void stage_store(int4 d, const StageRegs<T>& R, Stage<T>& S) {
     S.px[tid] = R.px;
     S.py[tid] = R.py;
     S.pd[tid] = R.pd;
+    S.pd2[tid] = R.pd2;
   }
 }
 
@@ -399,10 +410,14 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
   const int npass = (spw + segs - 1) / segs;
   const int lseg = lane & (SEG - 1), sidx = lane / SEG;
   const int s_lo = sbs[cd.a_lo], s_hi = sbs[cd.a_hi];
-  const int tslots = min(segs, table_slots(Rcap));   // pair-table copies per wave
+  const int tslots = min(segs, table_slots(Rcap, (int)sizeof(T)));   // pair-table copies per wave
+  // staged columns beyond the pose dofs: w_k / sqrt(C_k) (column D) and, for
+  // the adjoint, the depth cotangent / sqrt(C_k) (column D + 1)
+  const int nextra = P.adjoint ? 2 : 1;
+  const double* dbar_in = P.adjoint ? P.dbar + ((iter + 1) & 1) * P.n_patches_total : nullptr;
 
-  // lower-triangle tiles of the (D+1) x (D+1) product, row-major
-  const int Daug = D + 1;
+  // lower-triangle tiles of the (D+n_extra)^2 product, row-major
+  const int Daug = D + nextra;
   const int T16 = (Daug + 15) / 16;
   const int Ltot = (T16 * (T16 + 1)) / 2;
   for (int t = tid; t < Ltot; t += WG) {
@@ -431,7 +446,7 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
     if (s_lo < s_hi) {
       dcur = sbd[s_lo];
       if (s_lo + 1 < s_hi) dnxt = sbd[s_lo + 1];
-      stage_issue<T>(P, W, w, we, dcur, R);
+      stage_issue<T>(P, W, w, we, dcur, iter, dbar_in, R);
     }
     __syncthreads();   // previous pass done with the stage and the poses are in LDS
     if (s_lo < s_hi) stage_store<T>(dcur, R, S);
@@ -553,7 +568,7 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
       // prefetch the next sub-batch
       int4 dnn = dnxt;
       if (s + 1 < s_hi) {
-        stage_issue<T>(P, W, w, we, dnxt, R);
+        stage_issue<T>(P, W, w, we, dnxt, iter, dbar_in, R);
         if (s + 2 < s_hi) dnn = sbd[s + 2];
       }
       for (int i = tid; i < 16 * T16 * LDK; i += WG) U[i] = T(0);
@@ -615,6 +630,7 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
             for (int m = 0; m < 6; ++m) ua[m * LDK] = Eik[m] * rs;
           }
           U[D * LDK + slot] = Wk * rs;
+          if (nextra == 2) U[(D + 1) * LDK + slot] = (T)S.pd2[slot] * rs;
         }
       }
       __syncthreads();
@@ -629,9 +645,9 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
             const int code = tiles[t_beg + t];
             const int ti = code >> 16, tj = code & 0xffff;
             const bool rows_nz = (16 * ti < nz_hi && 16 * ti + 16 > nz_lo) ||
-                                 (16 * ti <= D && D < 16 * ti + 16);
+                                 (16 * ti < Daug && D < 16 * ti + 16);
             const bool cols_nz = (16 * tj < nz_hi && 16 * tj + 16 > nz_lo) ||
-                                 (16 * tj <= D && D < 16 * tj + 16);
+                                 (16 * tj < Daug && D < 16 * tj + 16);
             if (rows_nz && cols_nz) {
               const T* ua = U + (16 * ti + l16) * LDK + 4 * g;
               const T* ub = U + (16 * tj + l16) * LDK + 4 * g;
@@ -663,7 +679,7 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
             const int row = 16 * ti + acc_row(T(0), g, r), col = 16 * tj + l16;
             const double v = (sizeof(T) == 4) ? sh[t * 4 + r] : -(double)acc[t][r];
             if (row < D && col <= row) part[row * D + col] = v;
-            else if (row == D && col < D) part[D * D + col] = v;
+            else if (row >= D && row < Daug && col < D) part[D * D + (row - D) * D + col] = v;
           }
         }
       }

@@ -72,9 +72,22 @@ struct Params {
   int32_t* cstate;      // [C*2] chunk: first free frame of its range, D
   double* partial;      // chunk partials of S (lower, D x D) and s (D), FP64
   double* dxi;          // [F*6] pose steps
-  double* pose_buf;     // [2][F*7] pose state double buffer
-  double* depth_buf;    // [P] depth state, position order
-  int64_t n_frames_total;
+  double* pose_buf;     // [K+1][F*7] pose state after each iteration (slot 0: inputs)
+  double* depth_buf;    // [K+1][P] inverse-depth state after each iteration, position order
+  int64_t n_frames_total;   // slot strides
+  int64_t n_patches_total;
+  int32_t* gidx;        // [E] input index of each edge-order position (gathered layout)
+  // adjoint
+  int32_t adjoint;      // assembly adds the depth-cotangent column
+  const double* grad_poses;   // [F*7] cotangent of poses_out
+  const double* grad_depth;   // [P] cotangent of depth_out (patch order)
+  void* grad_targets;   // [E*2] T out
+  void* grad_weights;   // [E*2] T out
+  double* xib;          // [F*6] pose cotangent (left tangent) of the current state
+  double* xid;          // [F*6] direct part through the retraction
+  double* qxi;          // [F*6] adjoint solve, pose part
+  double* dbar;         // [2][P] depth cotangents, position order (ping-pong)
+  double* fcot;         // [C][RMAX*6] per-chunk pose cotangent partials
 };
 
 // ---------------------------------------------------------------------------

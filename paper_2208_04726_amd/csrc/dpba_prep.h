@@ -189,7 +189,8 @@ __device__ void wg_prep(const Params& P, int w, int* lds) {
   if (tid == 0) est[M] = E;
   // per-position pixel rays, initial depths, frame ranges
   T* pxy = (T*)P.pxy + 2 * W.patch_off;
-  double* dep = P.depth_buf + W.patch_off;
+  double* dep = P.depth_buf + W.patch_off;   // slot 0
+  for (int i = tid; i < 7 * N; i += WG) P.pose_buf[7 * W.frame_off + i] = P.poses_in[7 * W.frame_off + i];
   for (int q = tid; q < M; q += WG) {
     const int k = pk[q];
     const double* pt = P.patches_in + 3 * (W.patch_off + k);
@@ -221,6 +222,7 @@ __device__ void wg_prep(const Params& P, int w, int* lds) {
       for (int x = 0; x < n; ++x) {
         const int e = unsorted_e ? csr[b + x] : b + x;
         gj[o + x] = jj[e];
+        P.gidx[W.edge_off + o + x] = e;
         gt[2 * (o + x)] = tg[2 * e];
         gt[2 * (o + x) + 1] = tg[2 * e + 1];
         gw[2 * (o + x)] = wt[2 * e];

@@ -19,12 +19,15 @@ __host__ __device__ inline int chol_lds_bytes(int n) {
 }
 
 // Sum the chunk partials of window w into A (n x lda, lower) and b (n).
+// With b2 (adjoint), also the depth-cotangent row: b2 = -sum_k E_k dbar_k / C_k.
 __device__ inline void gather_partials(const Params& P, int w, const WinDesc& W, double* A,
-                                       int lda, double* b, int n) {
+                                       int lda, double* b, int n, double* b2 = nullptr) {
   const int tid = threadIdx.x;
   const int nfix = W.n_fixed;
   for (int i = tid; i < n * lda; i += WG) A[i] = 0.0;
   for (int i = tid; i < n; i += WG) b[i] = 0.0;
+  if (b2)
+    for (int i = tid; i < n; i += WG) b2[i] = 0.0;
   __syncthreads();
   for (int cc = 0; cc < W.n_chunks; ++cc) {
     const int c = W.chunk_off + cc;
@@ -35,6 +38,8 @@ __device__ inline void gather_partials(const Params& P, int w, const WinDesc& W,
     for (int r = tid >> 4; r < Dc; r += WG >> 4)
       for (int col = tid & 15; col <= r; col += 16) A[(off + r) * lda + off + col] += part[r * Dc + col];
     for (int r = tid; r < Dc; r += WG) b[off + r] += part[Dc * Dc + r];
+    if (b2)
+      for (int r = tid; r < Dc; r += WG) b2[off + r] += part[Dc * Dc + Dc + r];
     __syncthreads();
   }
 }
@@ -148,7 +153,7 @@ __device__ void wg_chol(const Params& P, int w, int iter, char* smem) {
   const int N = W.n_frames, nfix = W.n_fixed;
   const int n = 6 * (N - nfix);
   const double* poses = state_poses<T>(P, W, iter);
-  double* next = P.pose_buf + (int64_t)((iter + 1) & 1) * 7 * P.n_frames_total + 7 * W.frame_off;
+  double* next = P.pose_buf + (int64_t)(iter + 1) * 7 * P.n_frames_total + 7 * W.frame_off;
   double* dxi = P.dxi + 6 * W.frame_off;
   if (st != 0) {
     for (int i = tid; i < 6 * N; i += WG) dxi[i] = 0.0;
@@ -253,10 +258,11 @@ __device__ void wg_backsub(const Params& P, int c, int iter, char* smem, int Rca
   StageRegs<T> R;
   int4 dcur = sbd[s_lo], dnxt = dcur;
   if (s_lo + 1 < s_hi) dnxt = sbd[s_lo + 1];
-  stage_issue<T>(P, W, w, we, dcur, R);
+  stage_issue<T>(P, W, w, we, dcur, iter, nullptr, R);
   __syncthreads();
   stage_store<T>(dcur, R, S);
   int a = -1;
+  double* dnext = state_depth(P, W, iter + 1);
   for (int s = s_lo; s < s_hi; ++s) {
     const int an = dcur.y >> 8, nsb = dcur.y & 255, pos0 = dcur.x;
     if (an != a) {
@@ -265,7 +271,7 @@ __device__ void wg_backsub(const Params& P, int c, int iter, char* smem, int Rca
     }
     int4 dnn = dnxt;
     if (s + 1 < s_hi) {
-      stage_issue<T>(P, W, w, we, dnxt, R);
+      stage_issue<T>(P, W, w, we, dnxt, iter, nullptr, R);
       if (s + 2 < s_hi) dnn = sbd[s + 2];
     }
     __syncthreads();
@@ -296,7 +302,7 @@ __device__ void wg_backsub(const Params& P, int c, int iter, char* smem, int Rca
       if (le.pv && lseg == 0) {
         const double dnew = le.d - ((double)Wk + tk) / (double)Ck;
         if (last) P.depth_out[W.patch_off + S.pk[le.slot]] = dnew;
-        else P.depth_buf[W.patch_off + pos0 + le.slot] = dnew;
+        else dnext[pos0 + le.slot] = dnew;
       }
     }
     __syncthreads();
@@ -312,7 +318,7 @@ __device__ inline void wg_finalize(const Params& P, int w) {
   const int st = P.status[w];
   const double* src = (st != 0 || P.iterations == 0)
                           ? P.poses_in + 7 * W.frame_off
-                          : P.pose_buf + (int64_t)(P.iterations & 1) * 7 * P.n_frames_total + 7 * W.frame_off;
+                          : P.pose_buf + (int64_t)P.iterations * 7 * P.n_frames_total + 7 * W.frame_off;
   double* dst = P.poses_out + 7 * W.frame_off;
   for (int i = threadIdx.x; i < 7 * W.n_frames; i += WG) dst[i] = src[i];
   if (P.iterations == 0)

@@ -191,3 +191,49 @@ def capacities_for(windows: Sequence, slack: float = 1.0):
                 max_frames=max(1, sum(w.poses.shape[0] for w in windows)),
                 max_patches=max(1, int(slack * sum(w.patches.shape[0] for w in windows))),
                 max_edges=max(1, int(slack * sum(w.kk.shape[0] for w in windows))))
+
+
+def _backward(self, b: Batch, grad_poses: torch.Tensor, grad_depth: torch.Tensor, stream=None):
+    """Vector-Jacobian product of the solve with respect to targets and weights.
+    grad_poses: [F,7] f64 cotangent of poses_out; grad_depth: [P] f64 cotangent of
+    depth_out.  Returns (grad_targets, grad_weights), [E,2] in the dtype of targets."""
+    F, P, E = b.totals
+    dev = b.poses.device
+    gp = grad_poses.to(device=dev, dtype=torch.float64).contiguous()
+    gd = grad_depth.to(device=dev, dtype=torch.float64).contiguous()
+    gt = torch.empty((E, 2), dtype=b.targets.dtype, device=dev)
+    gw = torch.empty((E, 2), dtype=b.targets.dtype, device=dev)
+    scratch_p = torch.empty((max(F, 1), 7), dtype=torch.float64, device=dev)
+    scratch_d = torch.empty((max(P, 1),), dtype=torch.float64, device=dev)
+    p = self._problem(b, scratch_p, scratch_d)
+    st = (stream or torch.cuda.current_stream(dev)).cuda_stream
+    self._check(self.lib.ba_backward(self.h, ctypes.byref(p), _ptr(gp), _ptr(gd), _ptr(gt), _ptr(gw),
+                                     ctypes.c_void_p(st)))
+    self._last_w = b.n_windows
+    return gt, gw
+
+
+Solver.backward = _backward
+
+
+class BAFunction(torch.autograd.Function):
+    """(targets, weights) -> (poses_out, depth_out) through the GPU solve, with
+    the library's adjoint as backward.  The initial state and the graph are
+    constants (`batch` supplies them)."""
+
+    @staticmethod
+    def forward(ctx, targets, weights, solver: Solver, batch: Batch):
+        b = dataclasses.replace(batch, targets=targets.detach().contiguous(),
+                                weights=weights.detach().contiguous())
+        poses, depth = solver.solve(b)
+        ctx.solver, ctx.batch = solver, b
+        return poses, depth
+
+    @staticmethod
+    def backward(ctx, grad_poses, grad_depth):
+        if grad_poses is None:
+            grad_poses = torch.zeros((ctx.batch.totals[0], 7), dtype=torch.float64, device=ctx.batch.poses.device)
+        if grad_depth is None:
+            grad_depth = torch.zeros((ctx.batch.totals[1],), dtype=torch.float64, device=ctx.batch.poses.device)
+        gt, gw = ctx.solver.backward(ctx.batch, grad_poses, grad_depth)
+        return gt, gw, None, None
