@@ -94,7 +94,12 @@ typedef struct {
   int32_t schedule;               /* BA_SCHED_*                                   */
   int32_t max_windows;            /* windows per call                             */
   int32_t max_frames_per_window;  /* 1..64 (1..24 for BA_PREC_FP64)               */
-  int32_t reserved;
+  int32_t chunk_frames;           /* split schedule: source frames per assembly
+                                     workgroup.  0 = chosen per call from the
+                                     batch size (about two workgroups per CU);
+                                     > 0 = fixed, so that each window's result
+                                     is bitwise independent of the other windows
+                                     of the batch (the fused schedule always is) */
   int64_t max_frames;             /* total frames per call                        */
   int64_t max_patches;            /* total patches per call                       */
   int64_t max_edges;              /* total edges per call                         */
@@ -146,8 +151,52 @@ int ba_backward(ba_handle* h, const ba_problem* p, const double* grad_poses,
                 const double* grad_depth, void* grad_targets, void* grad_weights,
                 void* stream);
 
+/* Two-phase form of ba_solve for callers that replay the device work as a
+ * graph: batched serving of many odometry streams, each of which runs two
+ * BA iterations after every update of its window (Sec. 3.3 "Optimization").
+ *
+ * ba_prepare runs the host-side checks and window / chunk bookkeeping of
+ * ba_solve for *p and enqueues the upload of the resulting descriptor table
+ * (and the window and chunk counts) on `stream`.  It keeps a copy of *p.
+ *
+ * ba_launch enqueues the solve of the last prepared problem on `stream`.  It
+ * issues kernel launches only, sized for the handle's capacities rather than
+ * for the prepared batch (workgroups beyond the batch exit at once), so the
+ * launches may be captured into a HIP graph.  A captured graph holds the
+ * device pointers of the problem prepared before the capture: before every
+ * replay, call ba_prepare with a problem over the same device buffers (sizes
+ * and contents may change within the capacities) on the replay stream.
+ * The schedule is fixed per handle: BA_SCHED_AUTO resolves to the fused
+ * schedule when max_windows is at least a quarter of the compute units.
+ * Returns BA_E_STATE if nothing was prepared. */
+int ba_prepare(ba_handle* h, const ba_problem* p, void* stream);
+int ba_launch(ba_handle* h, void* stream);
+
+/* Kernel stages, for ba_kernel_times. */
+enum {
+  BA_STAGE_PREP = 0,      /* graph validation and ordering                       */
+  BA_STAGE_ASSEMBLE = 1,  /* edge linearisation, block assembly, Schur complement */
+  BA_STAGE_CHOL = 2,      /* reduced pose Cholesky, pose solve and retraction     */
+  BA_STAGE_BACKSUB = 3,   /* depth back-substitution                              */
+  BA_STAGE_FINALIZE = 4,  /* output poses                                         */
+  BA_STAGE_FUSED = 5,     /* the persistent launch of the fused schedule          */
+  BA_STAGE_COUNT = 6
+};
+
+/* Measurement aid: with timing enabled, every kernel that ba_solve or
+ * ba_launch enqueues (not while the stream is being captured) is bracketed by
+ * a pair of HIP events on its stream.  ba_kernel_times waits for the
+ * bracketed launches, writes per stage the summed kernel time in ms
+ * (ms_out[BA_STAGE_COUNT]) and the number of launches
+ * (launches_out[BA_STAGE_COUNT]) since the previous ba_kernel_times, and
+ * recycles the events.  Timing creates events on first use and keeps one pair
+ * per launch until ba_kernel_times is called. */
+int ba_set_timing(ba_handle* h, int32_t enable);
+int ba_kernel_times(ba_handle* h, double* ms_out, int32_t* launches_out);
+
 /* Waits for the last stream used with the handle and copies the per-window
- * BA_W_* bits of the last ba_solve / ba_backward into host_flags[W]. */
+ * BA_W_* bits of the last ba_solve / ba_prepare / ba_backward into
+ * host_flags[W]. */
 int ba_status(ba_handle* h, int32_t* host_flags);
 
 /* Message of the last error on this handle ("" if none).  Valid until the

@@ -22,45 +22,60 @@ using namespace dpba;
 template <typename T>
 __global__ void __launch_bounds__(WG) k_prep(Params P) {
   __shared__ int lds[WG + 16 + 2 * RMAX];
+  if ((int)blockIdx.x >= P.counts[0]) return;
   wg_prep<T>(P, blockIdx.x, lds);
 }
 
 template <typename T, int MAXT>
 __global__ void __launch_bounds__(WG) k_assemble(Params P, int iter, int Rcap) {
   extern __shared__ __align__(16) char smem[];
+  if ((int)blockIdx.x >= P.counts[1]) return;
   wg_assemble<T, MAXT>(P, blockIdx.x, iter, smem, Rcap);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(WG) k_chol(Params P, int iter) {
   extern __shared__ __align__(16) char smem[];
+  if ((int)blockIdx.x >= P.counts[0]) return;
   wg_chol<T>(P, blockIdx.x, iter, smem);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(WG) k_backsub(Params P, int iter, int Rcap) {
   extern __shared__ __align__(16) char smem[];
+  if ((int)blockIdx.x >= P.counts[1]) return;
   wg_backsub<T>(P, blockIdx.x, iter, smem, Rcap);
 }
 
-__global__ void __launch_bounds__(WG) k_finalize(Params P) { wg_finalize(P, blockIdx.x); }
+__global__ void __launch_bounds__(WG) k_finalize(Params P) {
+  if ((int)blockIdx.x >= P.counts[0]) return;
+  wg_finalize(P, blockIdx.x);
+}
 
 template <typename T>
-__global__ void __launch_bounds__(WG) k_adj_init(Params P) { wg_adj_init<T>(P, blockIdx.x); }
+__global__ void __launch_bounds__(WG) k_adj_init(Params P) {
+  if ((int)blockIdx.x >= P.counts[0]) return;
+  wg_adj_init<T>(P, blockIdx.x);
+}
 
 template <typename T>
 __global__ void __launch_bounds__(WG) k_chol_adj(Params P, int iter) {
   extern __shared__ __align__(16) char smem[];
+  if ((int)blockIdx.x >= P.counts[0]) return;
   wg_chol_adj<T>(P, blockIdx.x, iter, smem);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(WG) k_edge_adj(Params P, int iter, int Rcap) {
   extern __shared__ __align__(16) char smem[];
+  if ((int)blockIdx.x >= P.counts[1]) return;
   wg_edge_adj<T>(P, blockIdx.x, iter, smem, Rcap);
 }
 
-__global__ void __launch_bounds__(WG) k_frame_adj(Params P) { wg_frame_adj(P, blockIdx.x); }
+__global__ void __launch_bounds__(WG) k_frame_adj(Params P) {
+  if ((int)blockIdx.x >= P.counts[0]) return;
+  wg_frame_adj(P, blockIdx.x);
+}
 
 // Persistent form: each workgroup takes whole windows (one chunk each) and
 // runs preparation and every stage of every iteration without leaving the
@@ -68,7 +83,8 @@ __global__ void __launch_bounds__(WG) k_frame_adj(Params P) { wg_frame_adj(P, bl
 template <typename T, int MAXT>
 __global__ void __launch_bounds__(WG) k_fused(Params P, int Rcap) {
   extern __shared__ __align__(16) char smem[];
-  for (int w = blockIdx.x; w < P.n_windows; w += gridDim.x) {
+  const int nw = P.counts[0];
+  for (int w = blockIdx.x; w < nw; w += gridDim.x) {
     wg_prep<T>(P, w, (int*)smem);
     __syncthreads();
     const int c = P.win[w].chunk_off;
@@ -135,9 +151,19 @@ struct ba_handle {
   void *pxy = nullptr, *gt = nullptr, *gw = nullptr;
   int64_t cap_sb = 0;
   int32_t* gidx = nullptr;
+  int32_t* d_counts = nullptr;
+  int32_t* h_counts = nullptr;
+  bool prepared = false;
+  bool launch_fused = false;  // schedule of ba_prepare / ba_launch, fixed per handle
+  ba_problem prep_problem;
   double *xib = nullptr, *xid = nullptr, *qxi = nullptr, *dbar = nullptr, *fcot = nullptr;
   double* partial = nullptr;
   double *dxi = nullptr, *pose_buf = nullptr, *depth_buf = nullptr;
+  // per-kernel timing (ba_set_timing): event pairs around each launch
+  struct TimedLaunch { int stage; hipEvent_t a, b; };
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<TimedLaunch> timed;
   std::string err;
 };
 
@@ -170,9 +196,50 @@ int set_kernel_attrs() {
   return 0;
 }
 
+hipEvent_t take_event(ba_handle* h) {
+  if (!h->ev_pool.empty()) {
+    hipEvent_t e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one kernel launch with events on its stream when timing is on and
+// the stream is not being captured into a graph.
+struct KernelTimer {
+  ba_handle* h;
+  hipStream_t s;
+  int stage;
+  hipEvent_t a = nullptr;
+  KernelTimer(ba_handle* h_, hipStream_t s_, int stage_) : h(h_), s(s_), stage(stage_) {
+    if (!h->timing) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    a = take_event(h);
+    if (a && hipEventRecord(a, s) != hipSuccess) {
+      h->ev_pool.push_back(a);
+      a = nullptr;
+    }
+  }
+  ~KernelTimer() {
+    if (!a) return;
+    hipEvent_t b = take_event(h);
+    if (b && hipEventRecord(b, s) == hipSuccess) {
+      h->timed.push_back({stage, a, b});
+    } else {
+      h->ev_pool.push_back(a);
+      if (b) h->ev_pool.push_back(b);
+    }
+  }
+};
+
 struct Plan {
   int W = 0, C = 0, Rcap = 1, nmax = 0, maxt = 4;
   bool fused = false;
+  bool capacity = false;   // grids sized for the handle's capacities (ba_launch)
   int64_t F = 0, Pn = 0, E = 0;
 };
 
@@ -228,20 +295,24 @@ int validate_and_plan(ba_handle* h, const ba_problem* p, Plan& pl) {
 }
 
 // Chunking: split each window into runs of `c` consecutive source frames.
-// The fused schedule uses one chunk per window.
-int build_descriptors(ba_handle* h, const ba_problem* p, Plan& pl) {
+// The fused schedule uses one chunk per window.  `sched` is BA_SCHED_*.
+int build_descriptors(ba_handle* h, const ba_problem* p, Plan& pl, int sched) {
   const ba_config& cfg = h->cfg;
   const int W = pl.W;
   int64_t total_anchor = 0;
   for (int w = 0; w < W; ++w) total_anchor += p->frame_off[w + 1] - p->frame_off[w];
-  if (cfg.schedule == BA_SCHED_FUSED) pl.fused = true;
-  else if (cfg.schedule == BA_SCHED_SPLIT) pl.fused = false;
+  if (sched == BA_SCHED_FUSED) pl.fused = true;
+  else if (sched == BA_SCHED_SPLIT) pl.fused = false;
   else pl.fused = W >= h->n_cu / 4;
-  // anchors per chunk for the split schedule: aim for ~2 workgroups per CU
+  // anchors per chunk for the split schedule: fixed, or aim for ~2 workgroups per CU
   int c = 1;
   if (!pl.fused) {
-    const int64_t target = 2LL * h->n_cu;
-    c = (int)std::max<int64_t>(1, (total_anchor + target - 1) / target);
+    if (cfg.chunk_frames > 0) {
+      c = cfg.chunk_frames;
+    } else {
+      const int64_t target = 2LL * h->n_cu;
+      c = (int)std::max<int64_t>(1, (total_anchor + target - 1) / target);
+    }
   }
   for (;;) {
     int64_t chunks = 0, part = 0;
@@ -254,8 +325,9 @@ int build_descriptors(ba_handle* h, const ba_problem* p, Plan& pl) {
       part += nc * (D * D + 2 * D);
     }
     if (chunks <= h->cap_chunks && part <= h->cap_partial) break;
-    if (pl.fused) return fail(h, BA_E_CAPACITY, "partial workspace too small");
-    if (c >= cfg.max_frames_per_window) { pl.fused = true; continue; }
+    // one chunk per window always fits the workspace ba_create sizes
+    if (pl.fused || cfg.chunk_frames > 0 || c >= cfg.max_frames_per_window)
+      return fail(h, BA_E_CAPACITY, "partial workspace too small");
     c *= 2;
   }
   if (h->staging_pending) {
@@ -305,8 +377,7 @@ void fill_params(ba_handle* h, const ba_problem* p, const Plan& pl, Params& P) {
   memset(&P, 0, sizeof(P));
   P.win = h->d_win;
   P.chunk = h->d_chunk;
-  P.n_windows = pl.W;
-  P.n_chunks = pl.C;
+  P.counts = h->d_counts;
   P.iterations = h->cfg.iterations;
   P.lambda = h->cfg.lambda;
   P.z_min = h->cfg.z_min;
@@ -351,8 +422,13 @@ void fill_params(ba_handle* h, const ba_problem* p, const Plan& pl, Params& P) {
   P.fcot = h->fcot;
 }
 
+// Copies the staged descriptors and the window / chunk counts of `pl`.
 int upload_descriptors(ba_handle* h, const Plan& pl, hipStream_t s) {
-  HIPCHK(h, hipMemcpyAsync(h->d_win, h->h_win, sizeof(WinDesc) * pl.W, hipMemcpyHostToDevice, s));
+  h->h_counts[0] = pl.W;
+  h->h_counts[1] = pl.C;
+  HIPCHK(h, hipMemcpyAsync(h->d_counts, h->h_counts, 8, hipMemcpyHostToDevice, s));
+  if (pl.W > 0)
+    HIPCHK(h, hipMemcpyAsync(h->d_win, h->h_win, sizeof(WinDesc) * pl.W, hipMemcpyHostToDevice, s));
   if (pl.C > 0)
     HIPCHK(h, hipMemcpyAsync(h->d_chunk, h->h_chunk, sizeof(ChunkDesc) * pl.C, hipMemcpyHostToDevice, s));
   HIPCHK(h, hipEventRecord(h->staging_ev, s));
@@ -360,42 +436,56 @@ int upload_descriptors(ba_handle* h, const Plan& pl, hipStream_t s) {
   return BA_OK;
 }
 
+// Enqueues the forward solve.  The descriptors of `pl` must have been
+// uploaded on `s` before.  With pl.capacity the grids and LDS sizes are those
+// of the handle's capacities and the kernels read the batch size from the
+// device counts; otherwise they are sized for the batch.
 template <typename T>
 int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t s) {
   Params P;
   fill_params(h, p, pl, P);
-  {
-    const int r = upload_descriptors(h, pl, s);
-    if (r != BA_OK) return r;
-  }
-
+  const int gW = pl.capacity ? h->cfg.max_windows : pl.W;
+  const int gC = pl.capacity ? (int)h->cap_chunks : pl.C;
   const int Rcap = pl.Rcap;
   const int asm_lds = asm_layout(Rcap, (int)sizeof(T)).total;
   const int chol_lds = chol_lds_bytes(pl.nmax);
   const int bs_lds = backsub_lds_bytes(Rcap, (int)sizeof(T));
+  if (gW == 0) return BA_OK;
   if (pl.fused) {
     const int lds = std::max(std::max(asm_lds, chol_lds), std::max(bs_lds, (WG + 16 + 2 * RMAX) * 4));
-    const int grid = std::min(pl.W, 4 * h->n_cu);
+    const int grid = std::min(gW, 4 * h->n_cu);
+    KernelTimer kt(h, s, BA_STAGE_FUSED);
     if (pl.maxt == 4) hipLaunchKernelGGL((k_fused<T, 4>), dim3(grid), dim3(WG), lds, s, P, Rcap);
     else hipLaunchKernelGGL((k_fused<T, 8>), dim3(grid), dim3(WG), lds, s, P, Rcap);
     HIPCHK(h, hipGetLastError());
   } else {
-    hipLaunchKernelGGL(k_prep<T>, dim3(pl.W), dim3(WG), 0, s, P);
+    {
+      KernelTimer kt(h, s, BA_STAGE_PREP);
+      hipLaunchKernelGGL(k_prep<T>, dim3(gW), dim3(WG), 0, s, P);
+    }
     HIPCHK(h, hipGetLastError());
     for (int it = 0; it < P.iterations; ++it) {
-      if (pl.C > 0) {
-        if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<T, 4>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
-        else hipLaunchKernelGGL((k_assemble<T, 8>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
-        HIPCHK(h, hipGetLastError());
+      if (gC > 0) {
+        KernelTimer kt(h, s, BA_STAGE_ASSEMBLE);
+        if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<T, 4>), dim3(gC), dim3(WG), asm_lds, s, P, it, Rcap);
+        else hipLaunchKernelGGL((k_assemble<T, 8>), dim3(gC), dim3(WG), asm_lds, s, P, it, Rcap);
       }
-      hipLaunchKernelGGL(k_chol<T>, dim3(pl.W), dim3(WG), chol_lds, s, P, it);
       HIPCHK(h, hipGetLastError());
-      if (pl.C > 0) {
-        hipLaunchKernelGGL(k_backsub<T>, dim3(pl.C), dim3(WG), bs_lds, s, P, it, Rcap);
-        HIPCHK(h, hipGetLastError());
+      {
+        KernelTimer kt(h, s, BA_STAGE_CHOL);
+        hipLaunchKernelGGL(k_chol<T>, dim3(gW), dim3(WG), chol_lds, s, P, it);
       }
+      HIPCHK(h, hipGetLastError());
+      if (gC > 0) {
+        KernelTimer kt(h, s, BA_STAGE_BACKSUB);
+        hipLaunchKernelGGL(k_backsub<T>, dim3(gC), dim3(WG), bs_lds, s, P, it, Rcap);
+      }
+      HIPCHK(h, hipGetLastError());
     }
-    hipLaunchKernelGGL(k_finalize, dim3(pl.W), dim3(WG), 0, s, P);
+    {
+      KernelTimer kt(h, s, BA_STAGE_FINALIZE);
+      hipLaunchKernelGGL(k_finalize, dim3(gW), dim3(WG), 0, s, P);
+    }
     HIPCHK(h, hipGetLastError());
   }
   return BA_OK;
@@ -463,6 +553,7 @@ int ba_create(const ba_config* cfg, ba_handle** out) {
     return BA_E_INVAL;
   if (cfg->precision == BA_PREC_FP64 && cfg->max_frames_per_window > 24) return BA_E_INVAL;
   if (cfg->max_frames < 1 || cfg->max_patches < 0 || cfg->max_edges < 0) return BA_E_INVAL;
+  if (cfg->chunk_frames < 0) return BA_E_INVAL;
 
   ba_handle* h = new ba_handle();
   h->cfg = *cfg;
@@ -479,7 +570,16 @@ int ba_create(const ba_config* cfg, ba_handle** out) {
   const int64_t Dmax = 6LL * cfg->max_frames_per_window;
   const size_t esz = cfg->precision == BA_PREC_FP32 ? 4 : 8;
   h->cap_chunks = std::max<int64_t>(F, W);
-  h->cap_partial = std::max<int64_t>(W, 32) * (Dmax * Dmax + 2 * Dmax);
+  {
+    // partial blocks: enough for one chunk per window, or for the fixed chunking
+    int64_t blocks = std::max<int64_t>(W, 32);
+    if (cfg->chunk_frames > 0)
+      blocks = std::max(blocks, std::min<int64_t>(F, W * ((cfg->max_frames_per_window + cfg->chunk_frames - 1) /
+                                                            cfg->chunk_frames)));
+    h->cap_partial = blocks * (Dmax * Dmax + 2 * Dmax);
+  }
+  h->launch_fused = cfg->schedule == BA_SCHED_FUSED ||
+                    (cfg->schedule == BA_SCHED_AUTO && cfg->max_windows >= h->n_cu / 4);
   bool ok = true;
   auto dmalloc = [&](void** ptr, size_t bytes) {
     if (!ok) return;
@@ -487,6 +587,7 @@ int ba_create(const ba_config* cfg, ba_handle** out) {
   };
   dmalloc((void**)&h->d_win, sizeof(WinDesc) * W);
   dmalloc((void**)&h->d_chunk, sizeof(ChunkDesc) * h->cap_chunks);
+  dmalloc((void**)&h->d_counts, 16);
   dmalloc((void**)&h->status, 4 * W);
   dmalloc((void**)&h->wmeta, 16 * W);
   dmalloc((void**)&h->cnt, 4 * Pn);
@@ -520,6 +621,7 @@ int ba_create(const ba_config* cfg, ba_handle** out) {
   if (!ok) return cleanup(BA_E_HIP);
   if (hipHostMalloc((void**)&h->h_win, sizeof(WinDesc) * W) != hipSuccess) return cleanup(BA_E_HIP);
   if (hipHostMalloc((void**)&h->h_chunk, sizeof(ChunkDesc) * h->cap_chunks) != hipSuccess) return cleanup(BA_E_HIP);
+  if (hipHostMalloc((void**)&h->h_counts, 16) != hipSuccess) return cleanup(BA_E_HIP);
   if (hipEventCreateWithFlags(&h->staging_ev, hipEventDisableTiming) != hipSuccess) return cleanup(BA_E_HIP);
   if (hipMemset(h->status, 0, 4 * W) != hipSuccess) return cleanup(BA_E_HIP);
   *out = h;
@@ -536,7 +638,9 @@ int ba_solve(ba_handle* h, const ba_problem* p, void* stream) {
   h->last_stream = s;
   h->last_W = pl.W;
   if (pl.W == 0) return BA_OK;
-  r = build_descriptors(h, p, pl);
+  r = build_descriptors(h, p, pl, h->cfg.schedule);
+  if (r != BA_OK) return r;
+  r = upload_descriptors(h, pl, s);
   if (r != BA_OK) return r;
   return h->cfg.precision == BA_PREC_FP32 ? launch_solve<float>(h, p, pl, s)
                                           : launch_solve<double>(h, p, pl, s);
@@ -557,21 +661,89 @@ int ba_backward(ba_handle* h, const ba_problem* p, const double* grad_poses,
   if ((pl.F > 0 && !grad_poses) || (pl.Pn > 0 && !grad_depth) ||
       (pl.E > 0 && (!grad_targets || !grad_weights)))
     return fail(h, BA_E_INVAL, "gradient pointer is NULL");
-  const int saved = h->cfg.schedule;
-  h->cfg.schedule = BA_SCHED_SPLIT;
-  r = build_descriptors(h, p, pl);
-  h->cfg.schedule = saved;
+  r = build_descriptors(h, p, pl, BA_SCHED_SPLIT);
   if (r != BA_OK) return r;
   return h->cfg.precision == BA_PREC_FP32
              ? launch_backward<float>(h, p, pl, grad_poses, grad_depth, grad_targets, grad_weights, s)
              : launch_backward<double>(h, p, pl, grad_poses, grad_depth, grad_targets, grad_weights, s);
 }
 
+int ba_prepare(ba_handle* h, const ba_problem* p, void* stream) {
+  if (!h) return BA_E_INVAL;
+  h->err.clear();
+  h->prepared = false;
+  Plan pl;
+  int r = validate_and_plan(h, p, pl);
+  if (r != BA_OK) return r;
+  r = build_descriptors(h, p, pl, h->launch_fused ? BA_SCHED_FUSED : BA_SCHED_SPLIT);
+  if (r != BA_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  r = upload_descriptors(h, pl, s);
+  if (r != BA_OK) return r;
+  h->prep_problem = *p;
+  h->last_stream = s;
+  h->last_W = pl.W;
+  h->prepared = true;
+  return BA_OK;
+}
+
+int ba_launch(ba_handle* h, void* stream) {
+  if (!h) return BA_E_INVAL;
+  if (!h->prepared) return fail(h, BA_E_STATE, "ba_launch without ba_prepare");
+  h->err.clear();
+  hipStream_t s = (hipStream_t)stream;
+  h->last_stream = s;
+  Plan pl;
+  pl.capacity = true;
+  pl.fused = h->launch_fused;
+  pl.Rcap = h->cfg.max_frames_per_window;
+  pl.nmax = std::min(NCHOL_MAX, 6 * pl.Rcap);
+  {
+    const int T16 = (pl.nmax + 1 + 15) / 16;
+    pl.maxt = T16 * (T16 + 1) / 2 > NWAVES * 4 ? 8 : 4;
+  }
+  const ba_problem* p = &h->prep_problem;
+  return h->cfg.precision == BA_PREC_FP32 ? launch_solve<float>(h, p, pl, s)
+                                          : launch_solve<double>(h, p, pl, s);
+}
+
+int ba_set_timing(ba_handle* h, int32_t enable) {
+  if (!h) return BA_E_INVAL;
+  h->timing = enable != 0;
+  return BA_OK;
+}
+
+int ba_kernel_times(ba_handle* h, double* ms_out, int32_t* launches_out) {
+  if (!h || !ms_out || !launches_out) return BA_E_INVAL;
+  for (int i = 0; i < BA_STAGE_COUNT; ++i) {
+    ms_out[i] = 0.0;
+    launches_out[i] = 0;
+  }
+  int rc = BA_OK;
+  for (const auto& t : h->timed) {
+    float ms = 0.f;
+    if (rc == BA_OK) {
+      hipError_t e = hipEventSynchronize(t.b);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.a, t.b);
+      if (e != hipSuccess) rc = fail(h, BA_E_HIP, std::string("kernel timing: ") + hipGetErrorString(e));
+    }
+    if (rc == BA_OK && t.stage >= 0 && t.stage < BA_STAGE_COUNT) {
+      ms_out[t.stage] += ms;
+      launches_out[t.stage] += 1;
+    }
+    h->ev_pool.push_back(t.a);
+    h->ev_pool.push_back(t.b);
+  }
+  h->timed.clear();
+  return rc;
+}
+
 int ba_status(ba_handle* h, int32_t* host_flags) {
   if (!h || !host_flags) return BA_E_INVAL;
-  HIPCHK(h, hipStreamSynchronize(h->last_stream));
+  // copy on the handle's own stream, so that other streams are not waited for
   if (h->last_W > 0)
-    HIPCHK(h, hipMemcpy(host_flags, h->status, 4 * h->last_W, hipMemcpyDeviceToHost));
+    HIPCHK(h, hipMemcpyAsync(host_flags, h->status, 4 * h->last_W, hipMemcpyDeviceToHost, h->last_stream));
+  HIPCHK(h, hipStreamSynchronize(h->last_stream));
   return BA_OK;
 }
 
@@ -612,7 +784,14 @@ void ba_destroy(ba_handle* h) {
   hipFree(h->fcot);
   if (h->h_win) hipHostFree(h->h_win);
   if (h->h_chunk) hipHostFree(h->h_chunk);
+  if (h->h_counts) hipHostFree(h->h_counts);
+  hipFree(h->d_counts);
   if (h->staging_ev) hipEventDestroy(h->staging_ev);
+  for (auto& t : h->timed) {
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  for (auto e : h->ev_pool) hipEventDestroy(e);
   delete h;
 }
 
@@ -625,10 +804,7 @@ int ba_debug_reduced_system(ba_handle* h, const ba_problem* p, int32_t window, d
   if (r != BA_OK) return r;
   if (window < 0 || window >= pl.W) return fail(h, BA_E_INVAL, "window index out of range");
   if (!S_out || !s_out) return fail(h, BA_E_INVAL, "output pointer is NULL");
-  const int saved = h->cfg.schedule;
-  h->cfg.schedule = BA_SCHED_SPLIT;
-  r = build_descriptors(h, p, pl);
-  h->cfg.schedule = saved;
+  r = build_descriptors(h, p, pl, BA_SCHED_SPLIT);
   if (r != BA_OK) return r;
   hipStream_t s = (hipStream_t)stream;
   h->last_stream = s;

@@ -38,7 +38,7 @@ struct ChunkDesc {
 struct Params {
   const WinDesc* win;
   const ChunkDesc* chunk;
-  int32_t n_windows, n_chunks;
+  const int32_t* counts;  // device [2]: windows, chunks of this call (grids may be larger)
   int32_t iterations;
   double lambda, z_min;
   // problem (caller buffers)

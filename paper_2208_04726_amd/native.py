@@ -17,15 +17,17 @@ BA_PREC_FP64, BA_PREC_FP32 = 0, 1
 BA_SCHED_AUTO, BA_SCHED_SPLIT, BA_SCHED_FUSED = 0, 1, 2
 BA_W_OK, BA_W_NOT_SPD, BA_W_NONFINITE, BA_W_BAD_INDEX, BA_W_DEGREE = 0, 1, 2, 4, 8
 
-EXPORTED = ("ba_create", "ba_solve", "ba_backward", "ba_status", "ba_last_error",
-            "ba_destroy", "ba_debug_reduced_system", "ba_debug_mfma")
+EXPORTED = ("ba_create", "ba_solve", "ba_backward", "ba_prepare", "ba_launch", "ba_set_timing",
+            "ba_kernel_times", "ba_status", "ba_last_error", "ba_destroy",
+            "ba_debug_reduced_system", "ba_debug_mfma")
+STAGES = ("prep", "assemble", "chol", "backsub", "finalize", "fused")
 
 
 class BAConfig(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("lambda_", ctypes.c_double), ("z_min", ctypes.c_double),
                 ("schedule", ctypes.c_int32), ("max_windows", ctypes.c_int32),
-                ("max_frames_per_window", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_frames_per_window", ctypes.c_int32), ("chunk_frames", ctypes.c_int32),
                 ("max_frames", ctypes.c_int64), ("max_patches", ctypes.c_int64),
                 ("max_edges", ctypes.c_int64)]
 
@@ -59,6 +61,14 @@ def lib() -> ctypes.CDLL:
         L.ba_solve.restype = ctypes.c_int
         L.ba_backward.argtypes = [vp, ctypes.POINTER(BAProblem), vp, vp, vp, vp, vp]
         L.ba_backward.restype = ctypes.c_int
+        L.ba_prepare.argtypes = [vp, ctypes.POINTER(BAProblem), vp]
+        L.ba_prepare.restype = ctypes.c_int
+        L.ba_launch.argtypes = [vp, vp]
+        L.ba_launch.restype = ctypes.c_int
+        L.ba_set_timing.argtypes = [vp, i32]
+        L.ba_set_timing.restype = ctypes.c_int
+        L.ba_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32p]
+        L.ba_kernel_times.restype = ctypes.c_int
         L.ba_status.argtypes = [vp, i32p]
         L.ba_status.restype = ctypes.c_int
         L.ba_last_error.argtypes = [vp]

@@ -91,12 +91,13 @@ class Solver:
 
     precision: "fp32" (FP32 linearisation and assembly, FP64 Cholesky and
     back-substitution) or "fp64".  schedule: "auto", "split" (one launch per
-    stage) or "fused" (one persistent launch)."""
+    stage) or "fused" (one persistent launch).  chunk_frames: source frames
+    per assembly workgroup of the split schedule, 0 = chosen per call."""
 
     def __init__(self, precision: str = "fp32", iterations: int = 2, lam: float = 1e-4,
                  z_min: float = 0.1, schedule: str = "auto", max_windows: int = 1,
                  max_frames_per_window: int = 22, max_frames: Optional[int] = None,
-                 max_patches: int = 4096, max_edges: int = 65536):
+                 max_patches: int = 4096, max_edges: int = 65536, chunk_frames: int = 0):
         self.lib = native.lib()
         self.precision = precision
         cfg = BAConfig()
@@ -110,6 +111,7 @@ class Solver:
         cfg.max_frames = max_frames if max_frames is not None else max_windows * max_frames_per_window
         cfg.max_patches = max_patches
         cfg.max_edges = max_edges
+        cfg.chunk_frames = chunk_frames
         self.cfg = cfg
         h = ctypes.c_void_p()
         r = self.lib.ba_create(ctypes.byref(cfg), ctypes.byref(h))
@@ -160,6 +162,28 @@ class Solver:
         self._check(self.lib.ba_solve(self.h, ctypes.byref(p), ctypes.c_void_p(s)))
         self._last_w = b.n_windows
         return poses_out, depth_out
+
+    def prepare(self, p: BAProblem, stream: torch.cuda.Stream, n_windows: int):
+        """ba_prepare: host checks and descriptor upload on `stream` for the
+        problem struct `p` (whose host arrays the caller keeps alive)."""
+        self._check(self.lib.ba_prepare(self.h, ctypes.byref(p), ctypes.c_void_p(stream.cuda_stream)))
+        self._last_w = n_windows
+
+    def launch(self, stream: torch.cuda.Stream):
+        """ba_launch: the capacity-sized, capturable kernel sequence of the
+        last prepared problem."""
+        self._check(self.lib.ba_launch(self.h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def set_timing(self, enable: bool = True):
+        """Bracket every kernel launch with events (ba_set_timing)."""
+        self._check(self.lib.ba_set_timing(self.h, 1 if enable else 0))
+
+    def kernel_times(self):
+        """{stage: (total ms, launches)} since the previous call (waits for them)."""
+        ms = (ctypes.c_double * len(native.STAGES))()
+        n = (ctypes.c_int32 * len(native.STAGES))()
+        self._check(self.lib.ba_kernel_times(self.h, ms, n))
+        return {st: (float(ms[i]), int(n[i])) for i, st in enumerate(native.STAGES)}
 
     def status(self) -> np.ndarray:
         """Per-window BA_W_* bits of the last call (waits for its stream)."""
