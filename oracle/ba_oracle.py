@@ -322,3 +322,80 @@ def reduced_system(w, poses=None, depth=None, lam: float = 1e-4, z_min: float = 
         S = Hpp - Hpd @ Hdd_inv @ Hpd.T
         s = gp - Hpd @ Hdd_inv @ gd
     return S.numpy(), s.numpy()
+
+
+# --------------------------------------------------------------- large windows
+def normal_blocks(poses, depth, P: Dict, lam: float, z_min: float = 0.1):
+    """The damped normal equations of `normal_equations`, kept in three blocks
+    so that windows with tens of thousands of depths fit in memory:
+      Hpp [n_pose, n_pose] dense,  Hpd [n_pose, M] dense,  hdd [M] (the depth
+      block is diagonal: every edge involves exactly one depth),  gp, gd.
+    Each block is the same sum over edges of J_e^T W_e J_e (and J_e^T W_e r_e)
+    restricted to its unknowns; lam is added to every free diagonal."""
+    lin = edge_linearization(poses, depth, P["patches_xy"], P["anchor"], P["kk"],
+                             P["jj"], P["targets"], P["intr"], z_min)
+    N, M = poses.shape[0], depth.shape[0]
+    nf = P["n_fixed"]
+    kk, jj = P["kk"], P["jj"]
+    ii = P["anchor"][kk]
+    W = P["weights"]
+    Ji, Jj, Jd, r = lin["Ji"], lin["Jj"], lin["Jd"], lin["r"]
+    JiW = Ji.transpose(-1, -2) * W[:, None, :]        # [E,6,2]
+    JjW = Jj.transpose(-1, -2) * W[:, None, :]
+    # pose-pose: blocks (i,i), (i,j), (j,i), (j,j) of every edge, summed per frame pair
+    Bpair = torch.zeros((N * N, 6, 6), dtype=DT)
+    Bpair.index_add_(0, ii * N + ii, JiW @ Ji)
+    Bpair.index_add_(0, ii * N + jj, JiW @ Jj)
+    Bpair.index_add_(0, jj * N + ii, JjW @ Ji)
+    Bpair.index_add_(0, jj * N + jj, JjW @ Jj)
+    Bfull = Bpair.reshape(N, N, 6, 6).permute(0, 2, 1, 3).reshape(6 * N, 6 * N)
+    gfull = torch.zeros(6 * N, dtype=DT)
+    gfull.index_add_(0, (6 * ii[:, None] + torch.arange(6)).reshape(-1), (JiW @ r[..., None]).reshape(-1))
+    gfull.index_add_(0, (6 * jj[:, None] + torch.arange(6)).reshape(-1), (JjW @ r[..., None]).reshape(-1))
+    # pose-depth: J_a^T W J_d into (pose a, patch k)
+    Hpd_full = torch.zeros((6 * N, M), dtype=DT)
+    rows_i = (6 * ii[:, None] + torch.arange(6)).reshape(-1)
+    rows_j = (6 * jj[:, None] + torch.arange(6)).reshape(-1)
+    colk = kk[:, None].expand(-1, 6).reshape(-1)
+    Hpd_full.index_put_((rows_i, colk), (JiW @ Jd[..., None]).reshape(-1), accumulate=True)
+    Hpd_full.index_put_((rows_j, colk), (JjW @ Jd[..., None]).reshape(-1), accumulate=True)
+    # depth diagonal and depth gradient
+    hdd = torch.zeros(M, dtype=DT).index_add_(0, kk, (W * Jd * Jd).sum(-1)) + lam
+    gd = torch.zeros(M, dtype=DT).index_add_(0, kk, (W * Jd * r).sum(-1))
+    fr = slice(6 * nf, 6 * N)
+    n_pose = 6 * (N - nf)
+    Hpp = Bfull[fr, fr] + lam * torch.eye(n_pose, dtype=DT)
+    return Hpp, Hpd_full[fr], hdd, gfull[fr], gd, lin
+
+
+def gn_step_schur(poses, depth, P: Dict, lam: float = 1e-4, z_min: float = 0.1):
+    """The Gauss-Newton step of `gn_step`, with the depths eliminated first
+    (the Schur complement of Sec. 3.1, an exact identity since the depth block
+    is diagonal):
+      S = Hpp - Hpd diag(hdd)^-1 Hpd^T,   s = gp - Hpd (gd / hdd),
+      dxi = -S^-1 s (library Cholesky),   dd = -(gd + Hpd^T dxi) / hdd."""
+    Hpp, Hpd, hdd, gp, gd, lin = normal_blocks(poses, depth, P, lam, z_min)
+    S = Hpp - (Hpd / hdd) @ Hpd.T
+    s = gp - Hpd @ (gd / hdd)
+    nf = P["n_fixed"]
+    N = poses.shape[0]
+    if S.shape[0] > 0:
+        L = torch.linalg.cholesky(S)
+        dxi = -torch.cholesky_solve(s[:, None], L)[:, 0]
+    else:
+        dxi = torch.zeros(0, dtype=DT)
+    dd = -(gd + Hpd.T @ dxi) / hdd
+    if N > nf:
+        poses = torch.cat([poses[:nf], retract(poses[nf:], dxi.reshape(N - nf, 6))], 0)
+    return poses, depth + dd, dict(S=S, s=s)
+
+
+def solve_schur(w, iterations: int = 2, lam: float = 1e-4, z_min: float = 0.1):
+    """K steps of `gn_step_schur` (for windows too large for the dense H).
+    Returns (poses [N,7] numpy, inverse depths [M] numpy)."""
+    P = to_problem(w)
+    with torch.no_grad():
+        poses, depth = P["poses"], P["depth"]
+        for _ in range(iterations):
+            poses, depth, _ = gn_step_schur(poses, depth, P, lam, z_min)
+    return poses.numpy(), depth.numpy()

@@ -377,3 +377,42 @@ def test_gradient_directional_at_method_scale():
     fd = (loss(h) - loss(-h)) / (2 * h)
     an = float((gy * uy).sum() + (gw * uw).sum())
     assert abs(fd - an) < 1e-5 * abs(an), (fd, an)
+
+
+# ---------------------------------------------------------------- block-eliminated form
+@pytest.mark.parametrize("shape", [(4, 3, 2, 2), (5, 4, 3, 2), (6, 3, 5, 3)])
+def test_schur_step_matches_bruteforce(shape):
+    """The block-eliminated step (used for windows too large for the dense H)
+    against the brute-force finite-difference normal equations."""
+    N, ppf, r, nf = shape
+    w = synth.make_window(N, ppf, r, seed=[12, N], n_fixed=nf, outlier_frac=0.2)
+    delta_bf, _, _ = _bruteforce_step(w)
+    P = O.to_problem(w)
+    poses1, depth1, _ = O.gn_step_schur(P["poses"], P["depth"], P)
+    n_pose = 6 * (N - nf)
+    dd = depth1.numpy() - w.patches[:, 2]
+    assert np.abs(dd - delta_bf[n_pose:]).max() < 1e-6 * np.abs(delta_bf).max()
+    # pose step: the retraction of the brute-force step
+    for a in range(nf, N):
+        ref = perturb_left(w.poses[a], delta_bf[6 * (a - nf):6 * (a - nf) + 6])
+        got = poses1[a].numpy()
+        q_err = min(np.abs(got[3:] - ref[3:]).max(), np.abs(got[3:] + ref[3:]).max())
+        assert np.abs(got[:3] - ref[:3]).max() < 1e-6 * max(1.0, np.abs(delta_bf).max()) and q_err < 1e-6
+
+
+@pytest.mark.parametrize("which", ["small", "method", "wide"])
+def test_schur_solve_equals_dense_solve(which):
+    w = {"small": lambda: synth.plain_fp64_window(3),
+         "method": lambda: synth.method_scale_window(2),
+         "wide": lambda: synth.make_window(30, 10, 16, seed=[14], outlier_frac=0.1)}[which]()
+    pd, dd = O.solve(w)
+    ps, ds = O.solve_schur(w)
+    assert np.abs(pd - ps).max() < 1e-10
+    assert np.abs(dd - ds).max() < 1e-10 * np.abs(dd).max()
+
+
+def test_schur_depth_only_equals_dense():
+    w = synth.make_window(5, 6, 4, seed=[13], outlier_frac=0.1, n_fixed=5)
+    pd, dd = O.solve(w)
+    ps, ds = O.solve_schur(w)
+    assert np.array_equal(pd, ps) and np.abs(dd - ds).max() < 1e-12
