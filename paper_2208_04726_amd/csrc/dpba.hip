@@ -13,6 +13,7 @@
 #include "dpba_prep.h"
 #include "dpba_assemble.h"
 #include "dpba_solve.h"
+#include "dpba_chol_big.h"
 #include "dpba_adjoint.h"
 
 using namespace dpba;
@@ -36,8 +37,28 @@ __global__ void __launch_bounds__(WG) k_assemble(Params P, int iter, int Rcap) {
 template <typename T>
 __global__ void __launch_bounds__(WG) k_chol(Params P, int iter) {
   extern __shared__ __align__(16) char smem[];
-  if ((int)blockIdx.x >= P.counts[0]) return;
-  wg_chol<T>(P, blockIdx.x, iter, smem);
+  const int w = blockIdx.x;
+  if (w >= P.counts[0]) return;
+  const WinDesc& W = P.win[w];
+  if (6 * (W.n_frames - W.n_fixed) > NCHOL_MAX) return;   // k_chol_big
+  wg_chol<T>(P, w, iter, smem);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_chol_big(Params P, int iter) {
+  extern __shared__ __align__(16) char smem[];
+  const int w = blockIdx.x;
+  if (w >= P.counts[0]) return;
+  const WinDesc& W = P.win[w];
+  if (6 * (W.n_frames - W.n_fixed) <= NCHOL_MAX) return;  // k_chol
+  wg_chol_big<T>(P, w, iter, smem);
+}
+
+// Reduced systems of the windows with n > 126: blockIdx.x = window * tiles + tile.
+__global__ void __launch_bounds__(WG) k_gather_big(Params P, int tiles) {
+  const int w = blockIdx.x / tiles;
+  if (w >= P.counts[0]) return;
+  wg_gather_big(P, w, blockIdx.x % tiles);
 }
 
 template <typename T>
@@ -119,6 +140,19 @@ __global__ void __launch_bounds__(WG) k_debug_gather(Params P, int w, double* S,
   for (int i = threadIdx.x; i < n; i += WG) s[i] = b[i];
 }
 
+// Dense S, s of a window with n > 126 from its gathered augmented system.
+__global__ void __launch_bounds__(WG) k_debug_copy_big(Params P, int w, double* S, double* s) {
+  const WinDesc W = P.win[w];
+  const int n = 6 * (W.n_frames - W.n_fixed);
+  const int ld = P.ld_big;
+  const double* A = P.s_big + (int64_t)w * ld * ld;
+  for (int i = threadIdx.x; i < n * n; i += WG) {
+    const int r = i / n, c = i % n;
+    S[i] = c <= r ? A[(int64_t)r * ld + c] : A[(int64_t)c * ld + r];
+  }
+  for (int i = threadIdx.x; i < n; i += WG) s[i] = -A[(int64_t)n * ld + i];
+}
+
 template <typename T>
 __global__ void k_debug_mfma(const T* A, const T* B, T* D) {
   typedef typename AccT<T>::type Acc;
@@ -158,6 +192,8 @@ struct ba_handle {
   ba_problem prep_problem;
   double *xib = nullptr, *xid = nullptr, *qxi = nullptr, *dbar = nullptr, *fcot = nullptr;
   double* partial = nullptr;
+  double* s_big = nullptr;   // augmented reduced systems, windows with n > 126
+  int ld_big = 0;
   double *dxi = nullptr, *pose_buf = nullptr, *depth_buf = nullptr;
   // per-kernel timing (ba_set_timing): event pairs around each launch
   struct TimedLaunch { int stage; hipEvent_t a, b; };
@@ -189,6 +225,7 @@ int set_kernel_attrs() {
   if (hipFuncSetAttribute((const void*)k_fused<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_fused<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_chol<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chol_big<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_backsub<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_debug_gather<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_chol_adj<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
@@ -240,6 +277,7 @@ struct Plan {
   int W = 0, C = 0, Rcap = 1, nmax = 0, maxt = 4;
   bool fused = false;
   bool capacity = false;   // grids sized for the handle's capacities (ba_launch)
+  bool big = false;        // some window has more than 21 free frames
   int64_t F = 0, Pn = 0, E = 0;
 };
 
@@ -266,8 +304,11 @@ int validate_and_plan(ba_handle* h, const ba_problem* p, Plan& pl) {
     const int nf = p->n_fixed[w];
     if (nf < 0 || nf > N) return fail(h, BA_E_INVAL, "n_fixed outside [0, frames] in window " + std::to_string(w));
     const int n = 6 * (int)(N - nf);
-    if (n > NCHOL_MAX)
-      return fail(h, BA_E_CAPACITY, "window " + std::to_string(w) + ": more than 21 free frames");
+    if (n > NCHOL_MAX) {
+      if (!h->s_big)
+        return fail(h, BA_E_CAPACITY, "window " + std::to_string(w) + ": more than 21 free frames");
+      pl.big = true;
+    }
     pl.nmax = std::max(pl.nmax, n);
     {
       // accumulator tiles per wave: lower-triangle 16x16 tiles of (n+1)^2 over 8 waves
@@ -402,6 +443,8 @@ void fill_params(ba_handle* h, const ba_problem* p, const Plan& pl, Params& P) {
   P.arange = h->arange;
   P.cstate = h->cstate;
   P.partial = h->partial;
+  P.s_big = h->s_big;
+  P.ld_big = h->ld_big;
   P.dxi = h->dxi;
   P.pose_buf = h->pose_buf;
   P.depth_buf = h->depth_buf;
@@ -448,9 +491,11 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
   const int gC = pl.capacity ? (int)h->cap_chunks : pl.C;
   const int Rcap = pl.Rcap;
   const int asm_lds = asm_layout(Rcap, (int)sizeof(T)).total;
-  const int chol_lds = chol_lds_bytes(pl.nmax);
+  const int chol_lds = chol_lds_bytes(std::min(pl.nmax, NCHOL_MAX));
+  const int big_lds = chol_big_lds_bytes(pl.nmax);
   const int bs_lds = backsub_lds_bytes(Rcap, (int)sizeof(T));
   if (gW == 0) return BA_OK;
+  if (pl.fused && pl.big) return fail(h, BA_E_CAPACITY, "the fused schedule holds at most 21 free frames per window");
   if (pl.fused) {
     const int lds = std::max(std::max(asm_lds, chol_lds), std::max(bs_lds, (WG + 16 + 2 * RMAX) * 4));
     const int grid = std::min(gW, 4 * h->n_cu);
@@ -474,6 +519,11 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
       {
         KernelTimer kt(h, s, BA_STAGE_CHOL);
         hipLaunchKernelGGL(k_chol<T>, dim3(gW), dim3(WG), chol_lds, s, P, it);
+        if (pl.big) {
+          const int tiles = gather_tiles(pl.nmax);
+          hipLaunchKernelGGL(k_gather_big, dim3(gW * tiles), dim3(WG), 0, s, P, tiles);
+          hipLaunchKernelGGL(k_chol_big<T>, dim3(gW), dim3(WG), big_lds, s, P, it);
+        }
       }
       HIPCHK(h, hipGetLastError());
       if (gC > 0) {
@@ -571,8 +621,9 @@ int ba_create(const ba_config* cfg, ba_handle** out) {
   const size_t esz = cfg->precision == BA_PREC_FP32 ? 4 : 8;
   h->cap_chunks = std::max<int64_t>(F, W);
   {
-    // partial blocks: enough for one chunk per window, or for the fixed chunking
-    int64_t blocks = std::max<int64_t>(W, 32);
+    // partial blocks: one chunk per window, and about two chunks per CU
+    // across the batch (or the fixed chunking)
+    int64_t blocks = std::max<int64_t>(W, std::min<int64_t>(F, 2LL * h->n_cu));
     if (cfg->chunk_frames > 0)
       blocks = std::max(blocks, std::min<int64_t>(F, W * ((cfg->max_frames_per_window + cfg->chunk_frames - 1) /
                                                             cfg->chunk_frames)));
@@ -600,6 +651,10 @@ int ba_create(const ba_config* cfg, ba_handle** out) {
   dmalloc((void**)&h->arange, 8 * F);
   dmalloc((void**)&h->cstate, 8 * h->cap_chunks);
   dmalloc((void**)&h->partial, 8 * h->cap_partial);
+  if (6 * cfg->max_frames_per_window > NCHOL_MAX) {
+    h->ld_big = big_ld(cfg->max_frames_per_window);
+    dmalloc((void**)&h->s_big, 8 * (size_t)W * h->ld_big * h->ld_big);
+  }
   dmalloc((void**)&h->dxi, 8 * 6 * F);
   const int64_t slots = cfg->iterations + 1;
   dmalloc((void**)&h->pose_buf, 8 * slots * 7 * F);
@@ -638,7 +693,13 @@ int ba_solve(ba_handle* h, const ba_problem* p, void* stream) {
   h->last_stream = s;
   h->last_W = pl.W;
   if (pl.W == 0) return BA_OK;
-  r = build_descriptors(h, p, pl, h->cfg.schedule);
+  int sched = h->cfg.schedule;
+  if (pl.big) {
+    if (sched == BA_SCHED_FUSED)
+      return fail(h, BA_E_CAPACITY, "the fused schedule holds at most 21 free frames per window");
+    sched = BA_SCHED_SPLIT;
+  }
+  r = build_descriptors(h, p, pl, sched);
   if (r != BA_OK) return r;
   r = upload_descriptors(h, pl, s);
   if (r != BA_OK) return r;
@@ -658,6 +719,7 @@ int ba_backward(ba_handle* h, const ba_problem* p, const double* grad_poses,
   h->last_W = pl.W;
   if (pl.W == 0) return BA_OK;
   if (h->cfg.iterations < 1) return fail(h, BA_E_STATE, "ba_backward needs at least one iteration");
+  if (pl.big) return fail(h, BA_E_CAPACITY, "ba_backward holds at most 21 free frames per window");
   if ((pl.F > 0 && !grad_poses) || (pl.Pn > 0 && !grad_depth) ||
       (pl.E > 0 && (!grad_targets || !grad_weights)))
     return fail(h, BA_E_INVAL, "gradient pointer is NULL");
@@ -675,6 +737,8 @@ int ba_prepare(ba_handle* h, const ba_problem* p, void* stream) {
   Plan pl;
   int r = validate_and_plan(h, p, pl);
   if (r != BA_OK) return r;
+  if (pl.big && h->launch_fused)
+    return fail(h, BA_E_CAPACITY, "the fused schedule holds at most 21 free frames per window");
   r = build_descriptors(h, p, pl, h->launch_fused ? BA_SCHED_FUSED : BA_SCHED_SPLIT);
   if (r != BA_OK) return r;
   hipStream_t s = (hipStream_t)stream;
@@ -697,7 +761,9 @@ int ba_launch(ba_handle* h, void* stream) {
   pl.capacity = true;
   pl.fused = h->launch_fused;
   pl.Rcap = h->cfg.max_frames_per_window;
-  pl.nmax = std::min(NCHOL_MAX, 6 * pl.Rcap);
+  pl.nmax = 6 * pl.Rcap;
+  pl.big = !pl.fused && pl.nmax > NCHOL_MAX;
+  if (pl.fused) pl.nmax = std::min(NCHOL_MAX, pl.nmax);
   {
     const int T16 = (pl.nmax + 1 + 15) / 16;
     pl.maxt = T16 * (T16 + 1) / 2 > NWAVES * 4 ? 8 : 4;
@@ -766,6 +832,7 @@ void ba_destroy(ba_handle* h) {
   hipFree(h->arange);
   hipFree(h->cstate);
   hipFree(h->partial);
+  hipFree(h->s_big);
   hipFree(h->dxi);
   hipFree(h->pose_buf);
   hipFree(h->depth_buf);
@@ -825,7 +892,15 @@ int ba_debug_reduced_system(ba_handle* h, const ba_problem* p, int32_t window, d
     else hipLaunchKernelGGL((k_assemble<double, 8>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
     HIPCHK(h, hipGetLastError());
   }
-  const int lds = chol_lds_bytes(pl.nmax);
+  const int nw = 6 * (int)(p->frame_off[window + 1] - p->frame_off[window] - p->n_fixed[window]);
+  if (nw > NCHOL_MAX) {
+    const int tiles = gather_tiles(pl.nmax);
+    hipLaunchKernelGGL(k_gather_big, dim3(pl.W * tiles), dim3(WG), 0, s, P, tiles);
+    hipLaunchKernelGGL(k_debug_copy_big, dim3(1), dim3(WG), 0, s, P, window, S_out, s_out);
+    HIPCHK(h, hipGetLastError());
+    return BA_OK;
+  }
+  const int lds = chol_lds_bytes(std::min(pl.nmax, NCHOL_MAX));
   if (f32) hipLaunchKernelGGL(k_debug_gather<float>, dim3(1), dim3(WG), lds, s, P, window, S_out, s_out);
   else hipLaunchKernelGGL(k_debug_gather<double>, dim3(1), dim3(WG), lds, s, P, window, S_out, s_out);
   HIPCHK(h, hipGetLastError());

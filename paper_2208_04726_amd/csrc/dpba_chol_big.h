@@ -1,0 +1,269 @@
+// Reduced pose solve for windows with more than 21 free frames (n > 126):
+// the depth-eliminated system (Sec. 3.1, Schur complement) no longer fits in
+// the LDS of one workgroup, so it is summed into an (n+1) x (n+1) FP64 matrix
+// in device memory (row n carries the right-hand side -s) by many
+// workgroups, then factorised in place by one workgroup per window with a
+// blocked right-looking Cholesky:
+//   * the 32 x 32 diagonal block is factorised by one wave in registers;
+//   * the rows below it (the right-hand-side row included, which folds the
+//     forward substitution L y = -s into the factorisation) are solved
+//     against it, one row per thread;
+//   * the trailing lower triangle is updated with 16x16x4 FP64 matrix-core
+//     products from the panel held in LDS.
+// The back substitution L^T dxi = y runs by 32-row blocks from the bottom,
+// then the free poses are retracted as in the small-window solve.
+#pragma once
+#include "dpba_solve.h"
+
+namespace dpba {
+
+constexpr int NBIG_MAX = 6 * RMAX;   // reduced system size of a 64-frame window
+constexpr int CB = 32;               // panel width
+constexpr int PLD = CB + 1;          // LDS row stride of the panel
+constexpr int GT = 64;               // gather tile
+
+// 64 x 64 lower tiles of the augmented (n+1) square.
+__host__ __device__ inline int gather_tiles(int n) {
+  const int t = (n + 1 + GT - 1) / GT;
+  return t * (t + 1) / 2;
+}
+__host__ __device__ inline int big_ld(int rcap) { return 6 * rcap + 1; }
+
+// LDS: panel ((n+1) rows padded to 16, CB columns), the factorised diagonal
+// block, its inverse diagonal, the right-hand side / solution, flags.
+__host__ __device__ inline int chol_big_lds_bytes(int n) {
+  const int rows = ((n + 1 + 15) / 16) * 16;
+  return 64 + (rows * PLD + CB * PLD + CB + 2 * (n + 8)) * 8;
+}
+
+__device__ inline double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One 64 x 64 tile of the augmented system of window w, summed from the chunk
+// partials in chunk order (the order of the small-window gather):
+// rows < n hold S + lambda I (lower triangle), row n holds -s.
+__device__ void wg_gather_big(const Params& P, int w, int tile) {
+  const WinDesc W = P.win[w];
+  const int nfix = W.n_fixed;
+  const int n = 6 * (W.n_frames - nfix);
+  if (n <= NCHOL_MAX || P.status[w] != 0) return;
+  if (tile >= gather_tiles(n)) return;
+  int bi = 0;
+  while (((bi + 1) * (bi + 2)) / 2 <= tile) ++bi;
+  const int bj = tile - (bi * (bi + 1)) / 2;
+  const int ld = P.ld_big;
+  double* A = P.s_big + (int64_t)w * ld * ld;
+  for (int e = threadIdx.x; e < GT * GT; e += WG) {
+    const int r = GT * bi + e / GT, c = GT * bj + e % GT;
+    if (r > n || c > r || c >= n) continue;
+    double v = 0.0;
+    for (int cc = 0; cc < W.n_chunks; ++cc) {
+      const int ci = W.chunk_off + cc;
+      const int lo_free = P.cstate[2 * ci], Dc = P.cstate[2 * ci + 1];
+      if (Dc == 0) continue;
+      const int off = 6 * (lo_free - nfix);
+      const double* part = P.partial + W.part_off + (int64_t)cc * W.part_stride;
+      if (c < off || c >= off + Dc) continue;
+      if (r == n) v += part[Dc * Dc + (c - off)];
+      else if (r < off + Dc) v += part[(r - off) * Dc + (c - off)];
+    }
+    A[(int64_t)r * ld + c] = (r == n) ? -v : (r == c ? v + P.lambda : v);
+  }
+}
+
+// Blocked Cholesky of the augmented matrix A (lower, ld) in place; on return
+// rows < n hold L and row n holds y = L^{-1} b.  Returns BA_W_* bits of the
+// pivots (thread 0 of the workgroup holds the result in *flag).
+__device__ inline void wg_cholesky_big(double* A, int ld, int n, char* smem, int* flag) {
+  const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  const int rows_pad = ((n + 1 + 15) / 16) * 16;
+  double* Pn = (double*)(smem + 64);           // panel rows below the diagonal block
+  double* Ld = Pn + rows_pad * PLD;            // factorised diagonal block
+  double* inv = Ld + CB * PLD;                 // 1 / L_tt
+  if (tid == 0) *flag = 0;
+  int bad = 0;
+  for (int k0 = 0; k0 < n; k0 += CB) {
+    const int kb = min(CB, n - k0);
+    const int r0 = k0 + kb;             // first row below the block
+    const int m = n + 1 - r0;           // rows below, the right-hand-side row included
+    // ---- diagonal block, one wave: lane l holds row l
+    if (wv == 0) {
+      double Lr[CB];
+#pragma unroll
+      for (int t = 0; t < CB; ++t)
+        Lr[t] = (lane < kb && t <= lane) ? A[(int64_t)(k0 + lane) * ld + k0 + t] : 0.0;
+#pragma unroll
+      for (int kk = 0; kk < CB; ++kk) {
+        if (kk < kb) {
+          double piv = readlane_d(Lr[kk], kk);
+          if (!(piv > 0.0) || !isfinite_d(piv)) {
+            bad |= isfinite_d(piv) ? W_NOT_SPD : W_NONFINITE;
+            piv = 1.0;
+          }
+          const double lkk = sqrt(piv);
+          const double il = 1.0 / lkk;
+          if (lane == kk) Lr[kk] = lkk;
+          else if (lane > kk) Lr[kk] *= il;
+#pragma unroll
+          for (int jj = kk + 1; jj < CB; ++jj) {
+            if (jj < kb) {
+              const double ljk = readlane_d(Lr[kk], jj);
+              if (lane >= jj) Lr[jj] -= Lr[kk] * ljk;
+            }
+          }
+          if (lane == kk) inv[kk] = il;
+        }
+      }
+      if (lane < CB) {
+#pragma unroll
+        for (int t = 0; t < CB; ++t) {
+          Ld[lane * PLD + t] = Lr[t];
+          if (lane < kb && t <= lane) A[(int64_t)(k0 + lane) * ld + k0 + t] = Lr[t];
+        }
+      }
+    }
+    __syncthreads();
+    // ---- rows below: x L^T = a, one row per thread
+    for (int i = tid; i < rows_pad - r0; i += WG) {
+      double* prow = Pn + i * PLD;
+      if (i < m) {
+        double* arow = A + (int64_t)(r0 + i) * ld + k0;
+        double x[CB];
+#pragma unroll
+        for (int t = 0; t < CB; ++t) x[t] = t < kb ? arow[t] : 0.0;
+#pragma unroll
+        for (int t = 0; t < CB; ++t) {
+          double v = x[t];
+#pragma unroll
+          for (int s = 0; s < t; ++s) v -= x[s] * Ld[t * PLD + s];
+          x[t] = t < kb ? v * inv[t] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < CB; ++t) {
+          prow[t] = x[t];
+          if (t < kb) arow[t] = x[t];
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < CB; ++t) prow[t] = 0.0;
+      }
+    }
+    __syncthreads();
+    // ---- trailing update A[r][c] -= sum_t P[r][t] P[c][t], c <= r, c < n
+    if (m > 1) {
+      const int T = (m + 15) / 16;
+      const int ntile = T * (T + 1) / 2;
+      const int l16 = lane & 15, g = lane >> 4;
+      for (int t = wv; t < ntile; t += NWAVES) {
+        int ti = 0;
+        while (((ti + 1) * (ti + 2)) / 2 <= t) ++ti;
+        const int tj = t - (ti * (ti + 1)) / 2;
+        f64x4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * ti + acc_row(0.0, g, r), col = 16 * tj + l16;
+          const bool ok = row < m && col <= row && r0 + col < n;
+          acc[r] = ok ? A[(int64_t)(r0 + row) * ld + r0 + col] : 0.0;
+        }
+        const double* pa = Pn + (16 * ti + l16) * PLD + g;
+        const double* pb = Pn + (16 * tj + l16) * PLD + g;
+#pragma unroll
+        for (int kq = 0; kq < CB / 4; ++kq) acc = mfma16(-pa[4 * kq], pb[4 * kq], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * ti + acc_row(0.0, g, r), col = 16 * tj + l16;
+          if (row < m && col <= row && r0 + col < n) A[(int64_t)(r0 + row) * ld + r0 + col] = acc[r];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (wv == 0 && bad) atomicOr(flag, bad);
+  __syncthreads();
+}
+
+// L^T x = y, L in A (lower, ld), y = row n of A; x into LDS `x` (n entries).
+__device__ inline void wg_backsolve_big(const double* A, int ld, int n, double* x, double* z) {
+  const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  for (int j = tid; j < n; j += WG) z[j] = A[(int64_t)n * ld + j];
+  __syncthreads();
+  const int nb = (n + CB - 1) / CB;
+  for (int b = nb - 1; b >= 0; --b) {
+    const int b0 = b * CB, bs = min(CB, n - b0);
+    if (wv == 0) {
+      // lane t holds column t of the diagonal block and z_t
+      double Lc[CB];
+#pragma unroll
+      for (int s = 0; s < CB; ++s) Lc[s] = (lane < bs && s < bs && s >= lane) ? A[(int64_t)(b0 + s) * ld + b0 + lane] : 0.0;
+      double zz = lane < bs ? z[b0 + lane] : 0.0;
+#pragma unroll
+      for (int s = CB - 1; s >= 0; --s) {
+        if (s < bs) {
+          const double xs = readlane_d(zz, s) / readlane_d(Lc[s], s);
+          if (lane == s) zz = xs;
+          else if (lane < s) zz -= Lc[s] * xs;
+        }
+      }
+      if (lane < bs) x[b0 + lane] = zz;
+    }
+    __syncthreads();
+    for (int j = tid; j < b0; j += WG) {
+      double v = z[j];
+      for (int s = 0; s < bs; ++s) v -= A[(int64_t)(b0 + s) * ld + j] * x[b0 + s];
+      z[j] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// Solve and retraction of a window with n > 126 (the system was gathered by
+// wg_gather_big).
+template <typename T>
+__device__ void wg_chol_big(const Params& P, int w, int iter, char* smem) {
+  const WinDesc W = P.win[w];
+  const int tid = threadIdx.x;
+  int* misc = (int*)smem;
+  const int st = wg_bcast_status(P.status, w, misc);
+  const int N = W.n_frames, nfix = W.n_fixed;
+  const int n = 6 * (N - nfix);
+  const double* poses = state_poses<T>(P, W, iter);
+  double* next = P.pose_buf + (int64_t)(iter + 1) * 7 * P.n_frames_total + 7 * W.frame_off;
+  double* dxi = P.dxi + 6 * W.frame_off;
+  if (st != 0) {
+    for (int i = tid; i < 6 * N; i += WG) dxi[i] = 0.0;
+    return;
+  }
+  const int ld = P.ld_big;
+  double* A = P.s_big + (int64_t)w * ld * ld;
+  const int rows_pad = ((n + 1 + 15) / 16) * 16;
+  double* x = (double*)(smem + 64) + rows_pad * PLD + CB * PLD + CB;
+  double* z = x + n + 8;
+  wg_cholesky_big(A, ld, n, smem, misc + 1);
+  wg_backsolve_big(A, ld, n, x, z);
+  if (tid == 0) {
+    int bad = misc[1];
+    for (int i = 0; i < n; ++i)
+      if (!isfinite_d(x[i])) bad |= W_NONFINITE;
+    misc[2] = bad;
+    if (bad) atomicOr(&P.status[w], bad);
+  }
+  __syncthreads();
+  const int bad = misc[2];
+  for (int i = tid; i < 6 * N; i += WG) {
+    const int a = i / 6;
+    dxi[i] = (a >= nfix && !bad) ? x[6 * (a - nfix) + i % 6] : 0.0;
+  }
+  for (int a = tid; a < N; a += WG) {
+    const double* p = poses + 7 * a;
+    double* q = next + 7 * a;
+    if (a >= nfix && !bad) retract_left(x + 6 * (a - nfix), p, q);
+    else
+      for (int m = 0; m < 7; ++m) q[m] = p[m];
+  }
+}
+
+}  // namespace dpba

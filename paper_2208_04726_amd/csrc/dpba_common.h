@@ -71,6 +71,8 @@ struct Params {
   int32_t* arange;      // [F*2] frame range touched by each anchor's patches
   int32_t* cstate;      // [C*2] chunk: first free frame of its range, D
   double* partial;      // chunk partials of S (lower, D x D) and s (D), FP64
+  double* s_big;        // [W][ld_big^2] augmented reduced systems of windows with n > 126
+  int32_t ld_big;
   double* dxi;          // [F*6] pose steps
   double* pose_buf;     // [K+1][F*7] pose state after each iteration (slot 0: inputs)
   double* depth_buf;    // [K+1][P] inverse-depth state after each iteration, position order

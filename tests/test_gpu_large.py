@@ -1,0 +1,95 @@
+"""Windows with more than 21 free frames: the reduced system is gathered in
+device memory and factorised by the blocked FP64 Cholesky.  Parity with the
+dense oracle where it fits, with the block-eliminated oracle at 64 x 256."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ba_oracle as O
+from paper_2208_04726_amd import synth
+from tests.gpu_util import compare, need_gpu, solve_gpu
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = (1e-6, 1e-4, 1e-6)
+FP32_TOL = (1e-4, 1e-2, 1e-3)
+
+
+def _wide(n_frames, ppf, r, seed, fp32=True, n_fixed=2):
+    return synth.make_window(n_frames, ppf, r, seed=[2208, 9, seed], outlier_frac=0.1, fp32=fp32,
+                             n_fixed=n_fixed)
+
+
+def test_reduced_system_372_matches_oracle():
+    need_gpu()
+    from paper_2208_04726_amd.solver import Solver, make_batch, capacities_for
+    w = _wide(64, 16, 16, 0)
+    s = Solver(precision="fp32", **capacities_for([w]))
+    S, sv = s.reduced_system(make_batch([w], "fp32"))
+    torch.cuda.synchronize()
+    S_ref, s_ref = O.reduced_system(w)
+    S, sv = S.cpu().numpy(), sv.cpu().numpy()
+    assert S.shape == (372, 372)
+    rel_S = np.abs(S - S_ref).max() / np.abs(S_ref).max()
+    rel_s = np.abs(sv - s_ref).max() / np.abs(s_ref).max()
+    print(f"S rel {rel_S:.2e} s rel {rel_s:.2e}")
+    assert rel_S < 2e-4 and rel_s < 2e-4
+
+
+@pytest.mark.parametrize("shape", [(64, 16, 16), (30, 24, 16), (24, 40, 13)])
+def test_fp32_wide_window_matches_dense_oracle(shape):
+    need_gpu()
+    N, ppf, r = shape
+    w = _wide(N, ppf, r, 1)
+    out, st = solve_gpu([w], "fp32", "auto")
+    assert (st == 0).all()
+    pr, dr = O.solve(w)
+    dc, drot, dd = compare(out[0][0], out[0][1], pr, dr)
+    print(f"{shape}: {dc:.2e} m {drot:.2e} deg depth {dd:.2e}")
+    assert dc < FP32_TOL[0] and drot < FP32_TOL[1] and dd < FP32_TOL[2]
+
+
+def test_fp64_24_frames_matches_oracle():
+    """n = 132 in FP64: the blocked Cholesky at FP64 parity."""
+    need_gpu()
+    w = _wide(24, 12, 8, 2, fp32=False)
+    for sched in ("split", "auto"):
+        out, st = solve_gpu([w], "fp64", sched)
+        assert (st == 0).all()
+        pr, dr = O.solve(w)
+        dc, drot, dd = compare(out[0][0], out[0][1], pr, dr)
+        print(f"fp64 {sched}: {dc:.2e} m {drot:.2e} deg depth {dd:.2e}")
+        assert dc < FP64_TOL[0] and drot < FP64_TOL[1] and dd < FP64_TOL[2]
+
+
+def test_mixed_small_and_wide_windows_alone_equals_batch():
+    need_gpu()
+    wins = [synth.method_scale_window(3), _wide(40, 16, 16, 3), synth.serving_window(5), _wide(64, 8, 16, 4)]
+    batch, st = solve_gpu(wins, "fp32", "split", chunk_frames=2, max_frames_per_window=64)
+    assert (st == 0).all()
+    for i, w in enumerate(wins):
+        alone, st1 = solve_gpu([w], "fp32", "split", chunk_frames=2, max_frames_per_window=64)
+        assert (st1 == 0).all()
+        assert np.array_equal(alone[0][0], batch[i][0]) and np.array_equal(alone[0][1], batch[i][1]), i
+
+
+def test_fused_schedule_rejects_wide_windows():
+    need_gpu()
+    from paper_2208_04726_amd import native
+    with pytest.raises(native.BAError) as e:
+        solve_gpu([_wide(30, 8, 16, 5)], "fp32", "fused")
+    assert e.value.code == native.BA_E_CAPACITY
+
+
+def test_large_windows_64x256_k4_batch_of_8():
+    """Eight 64-frame x 256-patch windows (radius 16, 4 iterations) in one call;
+    two of them checked against the block-eliminated FP64 oracle."""
+    need_gpu()
+    wins = [synth.large_window(i) for i in range(8)]
+    out, st = solve_gpu(wins, "fp32", "auto", iterations=4)
+    assert (st == 0).all(), st
+    for i in (0, 5):
+        pr, dr = O.solve_schur(wins[i], iterations=4)
+        dc, drot, dd = compare(out[i][0], out[i][1], pr, dr)
+        print(f"large window {i}: {dc:.2e} m {drot:.2e} deg depth {dd:.2e}")
+        assert dc < FP32_TOL[0] and drot < FP32_TOL[1] and dd < FP32_TOL[2]
