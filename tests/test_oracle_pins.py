@@ -416,3 +416,15 @@ def test_schur_depth_only_equals_dense():
     pd, dd = O.solve(w)
     ps, ds = O.solve_schur(w)
     assert np.array_equal(pd, ps) and np.abs(dd - ds).max() < 1e-12
+
+
+def test_schur_rounded_system_is_a_perturbation():
+    """Rounding the reduced system to FP32 moves a well-conditioned solve by
+    little, and leaves FP64 rounding an identity."""
+    w = synth.method_scale_window(1)
+    p0, d0 = O.solve_schur(w)
+    p1, d1 = O.solve_schur(w, round_system=torch.float64)
+    assert np.array_equal(p0, p1) and np.array_equal(d0, d1)
+    p2, d2 = O.solve_schur(w, round_system=torch.float32)
+    dc, dr = synth.pose_errors(p2, p0)
+    assert 0 < dc < 1e-4 and dr < 1e-2
