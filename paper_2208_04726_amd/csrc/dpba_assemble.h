@@ -67,8 +67,20 @@ __host__ __device__ inline int stage_bytes(int esize) {
   return SBE * (4 + 4 * esize) + SBMAX * (4 + 2 * esize + 16) + (SBMAX + 1) * 4;
 }
 // Lane segments of a wave add their pair-table entries into separate copies
-// (two per wave when they fit), so they need not take turns.
-__host__ __device__ inline int table_slots(int Rcap, int esize) { return (esize == 4 ? Rcap <= 32 : Rcap <= 16) ? 2 : 1; }
+// (two per wave for windows of at most 32 frames, 16 in FP64), so they need
+// not take turns.  The count depends on the window alone, so a window's sums
+// are the same whatever else is in the batch.
+__host__ __device__ inline int table_slots(int n_frames, int esize) {
+  return (esize == 4 ? n_frames <= 32 : n_frames <= 16) ? 2 : 1;
+}
+// Rows of pair tables per wave the LDS must hold for windows of up to Rcap
+// frames: the larger of one copy of Rcap rows and two copies of the largest
+// two-copy window.
+__host__ __device__ inline int table_rows(int Rcap, int esize) {
+  const int two = esize == 4 ? 32 : 16;
+  const int a = table_slots(Rcap, esize) * Rcap, b = 2 * (Rcap < two ? Rcap : two);
+  return a > b ? a : b;
+}
 __host__ __device__ inline int al16(int o) { return (o + 15) & ~15; }
 __host__ __device__ inline AsmLayout asm_layout(int Rcap, int esize) {
   AsmLayout L;
@@ -77,7 +89,7 @@ __host__ __device__ inline AsmLayout asm_layout(int Rcap, int esize) {
   int o = 0;
   L.poses = o; o = al16(o + Rcap * 7 * 8);
   L.rel = o;   o = al16(o + Rcap * RELW * esize);
-  L.tbl = o;   o = al16(o + NWAVES * table_slots(Rcap, esize) * Rcap * TBL * esize);
+  L.tbl = o;   o = al16(o + NWAVES * table_rows(Rcap, esize) * TBL * esize);
   L.G = o;     o = al16(o + (Rcap * 36 + 42) * esize);
   L.U = o;     o = al16(o + 16 * L.Tcap * LDK * esize);
   L.tiles = o; o = al16(o + 4 * ((L.Tcap * (L.Tcap + 1)) / 2 + 4));
@@ -410,7 +422,7 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
   const int npass = (spw + segs - 1) / segs;
   const int lseg = lane & (SEG - 1), sidx = lane / SEG;
   const int s_lo = sbs[cd.a_lo], s_hi = sbs[cd.a_hi];
-  const int tslots = min(segs, table_slots(Rcap, (int)sizeof(T)));   // pair-table copies per wave
+  const int tslots = min(segs, table_slots(N, (int)sizeof(T)));   // pair-table copies per wave
   // staged columns beyond the pose dofs: w_k / sqrt(C_k) (column D) and, for
   // the adjoint, the depth cotangent / sqrt(C_k) (column D + 1)
   const int nextra = P.adjoint ? 2 : 1;
