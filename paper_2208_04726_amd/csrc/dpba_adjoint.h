@@ -383,13 +383,12 @@ __device__ void wg_edge_adj(const Params& P, int c, int it, char* smem, int Rcap
           tQ += (double)eo.Ej[m] * qxj[m] + (double)eo.Ei[m] * qxa[m];
         }
       }
-      T rc0 = eo.cd, rc1 = eo.wd;
-      double r2 = tD, r3 = tQ;
-      for (int o2 = SEG >> 1; o2 > 0; o2 >>= 1) {
-        const T x0 = __shfl_xor(rc0, o2, 64), x1 = __shfl_xor(rc1, o2, 64);
-        const double x2 = __shfl_xor(r2, o2, 64), x3 = __shfl_xor(r3, o2, 64);
-        rc0 += x0; rc1 += x1; r2 += x2; r3 += x3;
-      }
+      T rc[2] = {eo.cd, eo.wd};
+      double rr[2] = {tD, tQ};
+      seg_sum_n<2>(rc, SEG);
+      seg_sum_n<2>(rr, SEG);
+      const T rc0 = rc[0], rc1 = rc[1];
+      const double r2 = rr[0], r3 = rr[1];
       const double Ck = (double)(lam + rc0);
       const double ddk = -((double)rc1 + r2) / Ck;
       const double dbk = le.pv ? S.pd2[le.slot] : 0.0;
@@ -447,13 +446,7 @@ __device__ void wg_edge_adj(const Params& P, int c, int it, char* smem, int Rcap
       rel_adj_T<T>(rj, gv, ga);
       for (int m = 0; m < 6; ++m) ga[m] = -ga[m];
       ga[6] = gv[6];
-      for (int o2 = SEG >> 1; o2 > 0; o2 >>= 1) {
-        double xs[7];
-#pragma unroll
-        for (int m = 0; m < 7; ++m) xs[m] = __shfl_xor(ga[m], o2, 64);
-#pragma unroll
-        for (int m = 0; m < 7; ++m) ga[m] += xs[m];
-      }
+      seg_sum_n<7>(ga, SEG);
       if (le.pv && lseg == 0) {
         dbar_out[pos0 + le.slot] = dbk + ga[6];
         double* acc = gA + (wv * 4 + sidx) * 6;

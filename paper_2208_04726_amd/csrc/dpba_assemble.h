@@ -136,7 +136,7 @@ __device__ inline void linearize_edge(const T* rel, T xb, T yb, T d, T tx, T ty,
   const T Y = rel[3] * xb + rel[4] * yb + rel[5] + rel[10] * d;
   const T Z = rel[6] * xb + rel[7] * yb + rel[8] + rel[11] * d;
   o.active = valid && (Z > zmin);
-  const T iz = o.active ? T(1) / Z : T(0);
+  const T iz = o.active ? recip(Z) : T(0);
   const T a = fx * iz, b = fy * iz;
   const T c0 = -fx * X * iz * iz, c1 = -fy * Y * iz * iz;
   o.w0 = o.active ? w0 : T(0);
@@ -624,7 +624,7 @@ __device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rc
         const T Ck = lam + red[0];
         const T Wk = red[1];
         const T* Eik = red + 2;
-        const T rs = T(1) / __builtin_sqrt(Ck);
+        const T rs = rsqrt_(Ck);
         // staged row u_k: E_jk / sqrt(C_k) at target columns, E_ik / sqrt(C_k) at
         // the source frame's columns, w_k / sqrt(C_k) at column D
         const int slot = le.slot;

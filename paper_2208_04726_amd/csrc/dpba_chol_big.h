@@ -4,13 +4,13 @@
 // in device memory (row n carries the right-hand side -s) by many
 // workgroups, then factorised in place by one workgroup per window with a
 // blocked right-looking Cholesky:
-//   * the 32 x 32 diagonal block is factorised by one wave in registers;
+//   * each 16 x 16 diagonal block is factorised and inverted by one wave;
 //   * the rows below it (the right-hand-side row included, which folds the
-//     forward substitution L y = -s into the factorisation) are solved
-//     against it, one row per thread;
+//     forward substitution L y = -s into the factorisation) are multiplied by
+//     the inverse with matrix-core products;
 //   * the trailing lower triangle is updated with 16x16x4 FP64 matrix-core
 //     products from the panel held in LDS.
-// The back substitution L^T dxi = y runs by 32-row blocks from the bottom,
+// The back substitution L^T dxi = y runs by 16-row blocks from the bottom,
 // then the free poses are retracted as in the small-window solve.
 #pragma once
 #include "dpba_solve.h"
@@ -18,7 +18,7 @@
 namespace dpba {
 
 constexpr int NBIG_MAX = 6 * RMAX;   // reduced system size of a 64-frame window
-constexpr int CB = 32;               // panel width
+constexpr int CB = CBS;              // panel width
 constexpr int PLD = CB + 1;          // LDS row stride of the panel
 constexpr int GT = 64;               // gather tile
 
@@ -29,18 +29,11 @@ __host__ __device__ inline int gather_tiles(int n) {
 }
 __host__ __device__ inline int big_ld(int rcap) { return 6 * rcap + 1; }
 
-// LDS: panel ((n+1) rows padded to 16, CB columns), the factorised diagonal
-// block, its inverse diagonal, the right-hand side / solution, flags.
+// LDS: panel ((n+1) rows padded to 16, CB columns), the diagonal block's
+// factor and its inverse, the right-hand side / solution, flags.
 __host__ __device__ inline int chol_big_lds_bytes(int n) {
   const int rows = ((n + 1 + 15) / 16) * 16;
-  return 64 + (rows * PLD + CB * PLD + CB + 2 * (n + 8)) * 8;
-}
-
-__device__ inline double readlane_d(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  return 64 + (rows * PLD + 2 * CB * PLD + 2 * (n + 8)) * 8;
 }
 
 // One 64 x 64 tile of the augmented system of window w, summed from the chunk
@@ -76,81 +69,44 @@ __device__ void wg_gather_big(const Params& P, int w, int tile) {
 }
 
 // Blocked Cholesky of the augmented matrix A (lower, ld) in place; on return
-// rows < n hold L and row n holds y = L^{-1} b.  Returns BA_W_* bits of the
-// pivots (thread 0 of the workgroup holds the result in *flag).
+// rows < n hold L and row n holds y = L^{-1} b.  Pivot problems set BA_W_*
+// bits in *flag.  Per 16-column panel: wave 0 factorises and inverts the
+// diagonal block; the rows below become A L^{-T} (matrix-core products, kept
+// in the LDS panel and written back); the trailing lower triangle is updated
+// from the LDS panel, two 16x16 tiles per wave in flight.
 __device__ inline void wg_cholesky_big(double* A, int ld, int n, char* smem, int* flag) {
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   const int rows_pad = ((n + 1 + 15) / 16) * 16;
   double* Pn = (double*)(smem + 64);           // panel rows below the diagonal block
-  double* Ld = Pn + rows_pad * PLD;            // factorised diagonal block
-  double* inv = Ld + CB * PLD;                 // 1 / L_tt
-  if (tid == 0) *flag = 0;
+  double* Linv = Pn + rows_pad * PLD;          // inverse of the diagonal block
+  double* Ld = Linv + CB * PLD;                // the diagonal block's factor
   int bad = 0;
   for (int k0 = 0; k0 < n; k0 += CB) {
     const int kb = min(CB, n - k0);
     const int r0 = k0 + kb;             // first row below the block
     const int m = n + 1 - r0;           // rows below, the right-hand-side row included
-    // ---- diagonal block, one wave: lane l holds row l
     if (wv == 0) {
       double Lr[CB];
 #pragma unroll
       for (int t = 0; t < CB; ++t)
         Lr[t] = (lane < kb && t <= lane) ? A[(int64_t)(k0 + lane) * ld + k0 + t] : 0.0;
+      wave_factor_invert(Lr, kb, Ld, PLD, Linv, bad);
+      if (lane < kb) {
 #pragma unroll
-      for (int kk = 0; kk < CB; ++kk) {
-        if (kk < kb) {
-          double piv = readlane_d(Lr[kk], kk);
-          if (!(piv > 0.0) || !isfinite_d(piv)) {
-            bad |= isfinite_d(piv) ? W_NOT_SPD : W_NONFINITE;
-            piv = 1.0;
-          }
-          const double lkk = sqrt(piv);
-          const double il = 1.0 / lkk;
-          if (lane == kk) Lr[kk] = lkk;
-          else if (lane > kk) Lr[kk] *= il;
-#pragma unroll
-          for (int jj = kk + 1; jj < CB; ++jj) {
-            if (jj < kb) {
-              const double ljk = readlane_d(Lr[kk], jj);
-              if (lane >= jj) Lr[jj] -= Lr[kk] * ljk;
-            }
-          }
-          if (lane == kk) inv[kk] = il;
-        }
-      }
-      if (lane < CB) {
-#pragma unroll
-        for (int t = 0; t < CB; ++t) {
-          Ld[lane * PLD + t] = Lr[t];
-          if (lane < kb && t <= lane) A[(int64_t)(k0 + lane) * ld + k0 + t] = Lr[t];
-        }
+        for (int t = 0; t < CB; ++t)
+          if (t <= lane) A[(int64_t)(k0 + lane) * ld + k0 + t] = Lr[t];
       }
     }
+    // zero the panel rows past the matrix (operands of the last tiles)
+    for (int i = m + tid; i < rows_pad - r0; i += WG)
+#pragma unroll
+      for (int t = 0; t < CB; ++t) Pn[i * PLD + t] = 0.0;
     __syncthreads();
-    // ---- rows below: x L^T = a, one row per thread
-    for (int i = tid; i < rows_pad - r0; i += WG) {
-      double* prow = Pn + i * PLD;
-      if (i < m) {
-        double* arow = A + (int64_t)(r0 + i) * ld + k0;
-        double x[CB];
-#pragma unroll
-        for (int t = 0; t < CB; ++t) x[t] = t < kb ? arow[t] : 0.0;
-#pragma unroll
-        for (int t = 0; t < CB; ++t) {
-          double v = x[t];
-#pragma unroll
-          for (int s = 0; s < t; ++s) v -= x[s] * Ld[t * PLD + s];
-          x[t] = t < kb ? v * inv[t] : 0.0;
-        }
-#pragma unroll
-        for (int t = 0; t < CB; ++t) {
-          prow[t] = x[t];
-          if (t < kb) arow[t] = x[t];
-        }
-      } else {
-#pragma unroll
-        for (int t = 0; t < CB; ++t) prow[t] = 0.0;
-      }
+    {
+      auto rows = [&](int r) { return (const double*)(A + (int64_t)(r0 + r) * ld + k0); };
+      auto dst = [&](int r) { return Pn + r * PLD; };
+      auto dst2 = [&](int r, int c, double v) { A[(int64_t)(r0 + r) * ld + k0 + c] = v; };
+      panel_trsm_mfma(m, kb, Linv, rows, dst, dst2);
     }
     __syncthreads();
     // ---- trailing update A[r][c] -= sum_t P[r][t] P[c][t], c <= r, c < n
@@ -158,31 +114,48 @@ __device__ inline void wg_cholesky_big(double* A, int ld, int n, char* smem, int
       const int T = (m + 15) / 16;
       const int ntile = T * (T + 1) / 2;
       const int l16 = lane & 15, g = lane >> 4;
-      for (int t = wv; t < ntile; t += NWAVES) {
-        int ti = 0;
-        while (((ti + 1) * (ti + 2)) / 2 <= t) ++ti;
-        const int tj = t - (ti * (ti + 1)) / 2;
-        f64x4 acc;
+      for (int t0 = wv; t0 < ntile; t0 += 2 * NWAVES) {
+        f64x4 acc[2];
+        int ti[2], tj[2];
+        bool has[2];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * ti + acc_row(0.0, g, r), col = 16 * tj + l16;
-          const bool ok = row < m && col <= row && r0 + col < n;
-          acc[r] = ok ? A[(int64_t)(r0 + row) * ld + r0 + col] : 0.0;
+        for (int u = 0; u < 2; ++u) {
+          const int t = t0 + u * NWAVES;
+          has[u] = t < ntile;
+          int a = 0;
+          while (((a + 1) * (a + 2)) / 2 <= t) ++a;
+          ti[u] = a;
+          tj[u] = t - (a * (a + 1)) / 2;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * ti[u] + acc_row(0.0, g, r), col = 16 * tj[u] + l16;
+            const bool ok = has[u] && row < m && col <= row && r0 + col < n;
+            acc[u][r] = ok ? A[(int64_t)(r0 + row) * ld + r0 + col] : 0.0;
+          }
         }
-        const double* pa = Pn + (16 * ti + l16) * PLD + g;
-        const double* pb = Pn + (16 * tj + l16) * PLD + g;
 #pragma unroll
-        for (int kq = 0; kq < CB / 4; ++kq) acc = mfma16(-pa[4 * kq], pb[4 * kq], acc);
+        for (int u = 0; u < 2; ++u) {
+          if (has[u]) {
+            const double* pa = Pn + (16 * ti[u] + l16) * PLD + g;
+            const double* pb = Pn + (16 * tj[u] + l16) * PLD + g;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * ti + acc_row(0.0, g, r), col = 16 * tj + l16;
-          if (row < m && col <= row && r0 + col < n) A[(int64_t)(r0 + row) * ld + r0 + col] = acc[r];
+            for (int kq = 0; kq < CB / 4; ++kq) acc[u] = mfma16(-pa[4 * kq], pb[4 * kq], acc[u]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * ti[u] + acc_row(0.0, g, r), col = 16 * tj[u] + l16;
+            if (has[u] && row < m && col <= row && r0 + col < n)
+              A[(int64_t)(r0 + row) * ld + r0 + col] = acc[u][r];
+          }
         }
       }
     }
     __syncthreads();
   }
-  if (wv == 0 && bad) atomicOr(flag, bad);
+  if (wv == 0 && lane == 0) *flag = bad;
   __syncthreads();
 }
 
@@ -203,7 +176,7 @@ __device__ inline void wg_backsolve_big(const double* A, int ld, int n, double* 
 #pragma unroll
       for (int s = CB - 1; s >= 0; --s) {
         if (s < bs) {
-          const double xs = readlane_d(zz, s) / readlane_d(Lc[s], s);
+          const double xs = readlane_f64(zz, s) / readlane_f64(Lc[s], s);
           if (lane == s) zz = xs;
           else if (lane < s) zz -= Lc[s] * xs;
         }
@@ -240,7 +213,7 @@ __device__ void wg_chol_big(const Params& P, int w, int iter, char* smem) {
   const int ld = P.ld_big;
   double* A = P.s_big + (int64_t)w * ld * ld;
   const int rows_pad = ((n + 1 + 15) / 16) * 16;
-  double* x = (double*)(smem + 64) + rows_pad * PLD + CB * PLD + CB;
+  double* x = (double*)(smem + 64) + rows_pad * PLD + 2 * CB * PLD;
   double* z = x + n + 8;
   wg_cholesky_big(A, ld, n, smem, misc + 1);
   wg_backsolve_big(A, ld, n, x, z);

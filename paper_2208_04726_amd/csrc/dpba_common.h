@@ -97,26 +97,92 @@ struct Params {
 __device__ inline int lane_id() { return threadIdx.x & 63; }
 __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
+// Lane exchanges of the segment sums, done in the vector ALU: DPP quad
+// permutations (the lane 1 and 2 apart), the half-row and row mirrors (the
+// other half of each 8- and 16-lane group) and the row swaps of gfx950 (the
+// other 16-lane row of each 32, the other 32-lane half of the wave).  Every
+// step adds two lane groups that already hold equal partial sums, so all
+// lanes of a segment end with the bitwise-identical total, and the order of
+// the additions depends only on the segment width.  All 64 lanes must be
+// active.
+template <int CTRL>
+__device__ inline float dpp_get(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ inline double dpp_get(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// v plus the same lane of the other 16-lane row (ROW = 16) or 32-lane half (32)
+template <int ROW>
+__device__ inline float swap_add(float v) {
+  const int b = __float_as_int(v);
+  const auto r = ROW == 16 ? __builtin_amdgcn_permlane16_swap(b, b, false, false)
+                           : __builtin_amdgcn_permlane32_swap(b, b, false, false);
+  return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+template <int ROW>
+__device__ inline double swap_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const int l = (int)(b & 0xffffffffLL), h = (int)(b >> 32);
+  const auto lo = ROW == 16 ? __builtin_amdgcn_permlane16_swap(l, l, false, false)
+                            : __builtin_amdgcn_permlane32_swap(l, l, false, false);
+  const auto hi = ROW == 16 ? __builtin_amdgcn_permlane16_swap(h, h, false, false)
+                            : __builtin_amdgcn_permlane32_swap(h, h, false, false);
+  const double x = __longlong_as_double(((long long)hi[0] << 32) | (unsigned int)lo[0]);
+  const double y = __longlong_as_double(((long long)hi[1] << 32) | (unsigned int)lo[1]);
+  return x + y;
+}
+
+// Sums of v[0..N) over aligned power-of-two lane segments of width seg.
+template <int N, typename T>
+__device__ inline void seg_sum_n(T* v, int seg) {
+  if (seg > 1) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] += dpp_get<0xB1>(v[m]);   // quad_perm [1,0,3,2]
+  }
+  if (seg > 2) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] += dpp_get<0x4E>(v[m]);   // quad_perm [2,3,0,1]
+  }
+  if (seg > 4) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] += dpp_get<0x141>(v[m]);  // row_half_mirror
+  }
+  if (seg > 8) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] += dpp_get<0x140>(v[m]);  // row_mirror
+  }
+  if (seg > 16) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = swap_add<16>(v[m]);
+  }
+  if (seg > 32) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = swap_add<32>(v[m]);
+  }
+}
+
 template <typename T>
 __device__ inline T seg_sum(T v, int seg) {
-  // butterfly all-reduce inside aligned power-of-two lane groups; every lane
-  // of a group ends with the bitwise-identical sum
-  for (int o = seg >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  seg_sum_n<1>(&v, seg);
   return v;
 }
 
-// Eight butterfly all-reduces at once: the eight exchanges of each step are
-// issued back to back, so the lane exchanges of the step overlap.
 template <typename T>
 __device__ inline void seg_sum8(T* v, int seg) {
-  for (int o = seg >> 1; o > 0; o >>= 1) {
-    T x[8];
-#pragma unroll
-    for (int m = 0; m < 8; ++m) x[m] = __shfl_xor(v[m], o, 64);
-#pragma unroll
-    for (int m = 0; m < 8; ++m) v[m] += x[m];
-  }
+  seg_sum_n<8>(v, seg);
 }
+
+// Reciprocal and reciprocal square root: the hardware approximations (about
+// 1 ulp) in FP32, correctly rounded division in FP64.
+__device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double recip(double x) { return 1.0 / x; }
+__device__ inline float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double rsqrt_(double x) { return 1.0 / sqrt(x); }
 
 __device__ inline bool isfinite_d(double x) { return __builtin_isfinite(x); }
 __device__ inline bool isfinite_f(float x) { return __builtin_isfinite(x); }

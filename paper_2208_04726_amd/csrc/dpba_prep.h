@@ -27,6 +27,8 @@ namespace dpba {
 // Sub-batch width (patches) and lane segment width (edges per patch) for a
 // window's largest patch degree: one segment of lanes per patch, at most 1024
 // staged edges per sub-batch.
+constexpr int PU = 8;   // edges per thread in flight in the preparation loops
+
 __host__ __device__ inline int seg_width(int maxdeg) { return maxdeg <= 16 ? 16 : (maxdeg <= 32 ? 32 : 64); }
 __host__ __device__ inline int sb_width(int seg) { return seg == 64 ? 16 : 32; }
 
@@ -73,19 +75,48 @@ __device__ void wg_prep(const Params& P, int w, int* lds) {
     const double* p = P.poses_in + 7 * (W.frame_off + a);
     for (int m = 0; m < 7; ++m) nonfin |= !isfinite_d(p[m]);
   }
-  for (int k = tid; k < M; k += WG) {
-    const int a = anc[k];
-    bad |= (a < 0 || a >= N);
-    if (k > 0) uns_p |= anc[k - 1] > a;
-    const double* pt = P.patches_in + 3 * (W.patch_off + k);
-    nonfin |= !(isfinite_d(pt[0]) && isfinite_d(pt[1]) && isfinite_d(pt[2]));
+  for (int k0 = tid; k0 < M; k0 += PU * WG) {
+    int a[PU], ap[PU];
+    double x[PU], y[PU], d[PU];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int k = k0 + u * WG;
+      const bool in = k < M;
+      a[u] = in ? anc[k] : 0;
+      ap[u] = (in && k > 0) ? anc[k - 1] : -1;
+      const double* pt = P.patches_in + 3 * (W.patch_off + (in ? k : 0));
+      x[u] = in ? pt[0] : 0.0;
+      y[u] = in ? pt[1] : 0.0;
+      d[u] = in ? pt[2] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      if (k0 + u * WG < M) {
+        bad |= (a[u] < 0 || a[u] >= N);
+        uns_p |= ap[u] > a[u];
+        nonfin |= !(isfinite_d(x[u]) && isfinite_d(y[u]) && isfinite_d(d[u]));
+      }
+    }
   }
-  for (int e = tid; e < E; e += WG) {
-    const int k = kk[e], j = jj[e];
-    bad |= (k < 0 || k >= M || j < 0 || j >= N);
-    if (e > 0) {
-      const int kp = kk[e - 1], jp = jj[e - 1];
-      uns_e |= (kp > k || (kp == k && jp > j));
+  // edges in batches of PU per thread, so that the loads of a batch are in
+  // flight together
+  for (int e0 = tid; e0 < E; e0 += PU * WG) {
+    int k[PU], j[PU], kp[PU], jp[PU];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int e = e0 + u * WG;
+      const bool in = e < E;
+      k[u] = in ? kk[e] : 0;
+      j[u] = in ? jj[e] : 0;
+      kp[u] = (in && e > 0) ? kk[e - 1] : -1;
+      jp[u] = (in && e > 0) ? jj[e - 1] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      if (e0 + u * WG < E) {
+        bad |= (k[u] < 0 || k[u] >= M || j[u] < 0 || j[u] >= N);
+        uns_e |= (kp[u] > k[u] || (kp[u] == k[u] && jp[u] > j[u]));
+      }
     }
   }
   if (__any(bad) && lane_id() == 0) atomicOr(&flags[0], 1);
@@ -107,14 +138,30 @@ __device__ void wg_prep(const Params& P, int w, int* lds) {
   __syncthreads();
   if (!unsorted_e) {
     // sorted by (patch, target): run boundaries give the counts
-    for (int e = tid; e < E; e += WG) {
-      const int k = kk[e];
-      if (e == E - 1 || kk[e + 1] != k) cnt[k] = e + 1;   // one past the run
+    for (int e0 = tid; e0 < E; e0 += PU * WG) {
+      int k[PU], kn[PU];
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        const int e = e0 + u * WG;
+        k[u] = e < E ? kk[e] : -1;
+        kn[u] = e + 1 < E ? kk[e + 1] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < PU; ++u)
+        if (e0 + u * WG < E && kn[u] != k[u]) cnt[k[u]] = e0 + u * WG + 1;   // one past the run
     }
     __syncthreads();
-    for (int e = tid; e < E; e += WG) {
-      const int k = kk[e];
-      if (e == 0 || kk[e - 1] != k) cnt[k] -= e;          // minus the run start
+    for (int e0 = tid; e0 < E; e0 += PU * WG) {
+      int k[PU], kq[PU];
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        const int e = e0 + u * WG;
+        k[u] = e < E ? kk[e] : -1;
+        kq[u] = (e < E && e > 0) ? kk[e - 1] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < PU; ++u)
+        if (e0 + u * WG < E && kq[u] != k[u]) cnt[k[u]] -= e0 + u * WG;     // minus the run start
     }
   } else {
     for (int k = tid; k < M; k += WG) fill[k] = 0;
@@ -191,20 +238,45 @@ __device__ void wg_prep(const Params& P, int w, int* lds) {
   T* pxy = (T*)P.pxy + 2 * W.patch_off;
   double* dep = P.depth_buf + W.patch_off;   // slot 0
   for (int i = tid; i < 7 * N; i += WG) P.pose_buf[7 * W.frame_off + i] = P.poses_in[7 * W.frame_off + i];
-  for (int q = tid; q < M; q += WG) {
-    const int k = pk[q];
-    const double* pt = P.patches_in + 3 * (W.patch_off + k);
-    pxy[2 * q] = (T)((pt[0] - W.cx) / W.fx);
-    pxy[2 * q + 1] = (T)((pt[1] - W.cy) / W.fy);
-    dep[q] = pt[2];
-    const int n = cnt[k];
-    if (n > 0) {
-      const int a = anc[k];
-      const int b = ptr[k];
-      const int j0 = unsorted_e ? jj[csr[b]] : jj[b];
-      const int j1 = unsorted_e ? jj[csr[b + n - 1]] : jj[b + n - 1];
-      atomicMin(&lr[2 * a], j0);
-      atomicMax(&lr[2 * a + 1], j1);
+  for (int q0 = tid; q0 < M; q0 += PU * WG) {
+    int k[PU], n[PU], a[PU], b[PU], j0[PU], j1[PU];
+    double x[PU], y[PU], d[PU];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int q = q0 + u * WG;
+      k[u] = q < M ? (unsorted_p ? pk[q] : q) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const bool in = q0 + u * WG < M;
+      const double* pt = P.patches_in + 3 * (W.patch_off + k[u]);
+      x[u] = in ? pt[0] : 0.0;
+      y[u] = in ? pt[1] : 0.0;
+      d[u] = in ? pt[2] : 0.0;
+      n[u] = in ? cnt[k[u]] : 0;
+      a[u] = in ? anc[k[u]] : 0;
+      b[u] = in ? ptr[k[u]] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      j0[u] = j1[u] = 0;
+      if (n[u] > 0) {
+        j0[u] = unsorted_e ? jj[csr[b[u]]] : jj[b[u]];
+        j1[u] = unsorted_e ? jj[csr[b[u] + n[u] - 1]] : jj[b[u] + n[u] - 1];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int q = q0 + u * WG;
+      if (q < M) {
+        pxy[2 * q] = (T)((x[u] - W.cx) / W.fx);
+        pxy[2 * q + 1] = (T)((y[u] - W.cy) / W.fy);
+        dep[q] = d[u];
+        if (n[u] > 0) {
+          atomicMin(&lr[2 * a[u]], j0[u]);
+          atomicMax(&lr[2 * a[u] + 1], j1[u]);
+        }
+      }
     }
   }
   __syncthreads();

@@ -12,10 +12,12 @@
 
 namespace dpba {
 
-// LDS of the solve: 64 B header, A (n x (n+1)), b, x, two column buffers.
+constexpr int CBS_LDS = 32 * 33;   // inverse diagonal block of the blocked factorisation (and spare)
+// LDS of the solve: 64 B header, A (n x (n+1)), b, x, the inverse diagonal
+// block and solve scratch (the adjoint's column buffers fit in the same space).
 __host__ __device__ inline int chol_lds_bytes(int n) {
   const int lda = n + 1;
-  return 64 + (n * lda + 2 * n + 8) * 8 + 2 * 128 * 8;
+  return 64 + (n * lda + 2 * n + 8) * 8 + (CBS_LDS + 128) * 8;
 }
 
 // Sum the chunk partials of window w into A (n x lda, lower) and b (n).
@@ -144,6 +146,216 @@ __device__ inline void wave_cholesky_solve(const double* A, int lda, int n, cons
   if (l + 64 < n) x[l + 64] = y1;
 }
 
+constexpr int CBS = 16;   // panel width of the blocked factorisation
+
+__device__ inline double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Factorisation of one diagonal block by wave 0 (lane l < kb holds row l,
+// loaded by the caller into Lr), followed by the inverse of the factor.  The
+// factor's rows are written to Ld (LDS, row stride ldd); Linv (LDS, CBS x
+// CBS, row stride CBS + 1) receives L^{-1} (lower, zeros elsewhere).  Lane
+// values are exchanged through LDS (in issue order within the wave).  Pivot
+// problems accumulate BA_W_* bits into bad.
+__device__ inline void wave_factor_invert(double (&Lr)[CBS], int kb, double* Ld, int ldd,
+                                          double* Linv, int& bad) {
+  const int lane = lane_id();
+  double* col = Linv;   // column exchange buffer until the inverse is written
+#pragma unroll
+  for (int kk = 0; kk < CBS; ++kk) {
+    if (kk < kb) {
+      if (lane < CBS) col[lane] = Lr[kk];
+      double piv = col[kk];
+      if (!(piv > 0.0) || !isfinite_d(piv)) {
+        bad |= isfinite_d(piv) ? W_NOT_SPD : W_NONFINITE;
+        piv = 1.0;
+      }
+      const double lkk = sqrt(piv);
+      const double il = 1.0 / lkk;
+      if (lane == kk) Lr[kk] = lkk;
+      else if (lane > kk) Lr[kk] *= il;
+#pragma unroll
+      for (int jj = kk + 1; jj < CBS; ++jj) {
+        if (jj < kb) {
+          const double ljk = col[jj] * il;
+          if (lane >= jj) Lr[jj] -= Lr[kk] * ljk;
+        }
+      }
+    }
+  }
+  if (lane < kb) {
+#pragma unroll
+    for (int t = 0; t < CBS; ++t)
+      if (t <= lane) Ld[lane * ldd + t] = Lr[t];
+  }
+  // column `lane` of L^{-1}: X[i][j] = (delta_ij - sum_{k<i} L[i][k] X[k][j]) / L[i][i]
+  double Xc[CBS];
+#pragma unroll
+  for (int i = 0; i < CBS; ++i) {
+    if (i < kb) {
+      double v = (lane == i) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) v -= Ld[i * ldd + k] * Xc[k];
+      Xc[i] = (lane <= i) ? v / Ld[i * ldd + i] : 0.0;
+    } else {
+      Xc[i] = 0.0;
+    }
+  }
+  if (lane < CBS) {
+#pragma unroll
+    for (int i = 0; i < CBS; ++i) Linv[i * (CBS + 1) + lane] = Xc[i];
+  }
+}
+
+// Rows below a diagonal block: X = A_rows L^{-T}, 16 rows per wave step with
+// 16x16x4 FP64 matrix-core products (K = 32).  rows(r) returns the address of
+// column k0 of row r (r < m) of the source; results go to dst(r) (and, when
+// given, to a second destination).  Rows are read before they are written by
+// the same wave, so the product may be in place.
+template <typename Src, typename Dst, typename Dst2>
+__device__ inline void panel_trsm_mfma(int m, int kb, const double* Linv, Src rows, Dst dst, Dst2 dst2) {
+  const int lane = lane_id(), wv = wave_id();
+  const int l16 = lane & 15, g = lane >> 4;
+  const int nblk = (m + 15) / 16;
+  for (int rb = wv; rb < nblk; rb += NWAVES) {
+    const int ra = min(16 * rb + l16, m - 1);   // operand row (clamped; extra rows not stored)
+    const double* src = rows(ra);
+    double av[CBS / 4];
+#pragma unroll
+    for (int kq = 0; kq < CBS / 4; ++kq) {
+      const int k = 4 * kq + g;
+      av[kq] = k < kb ? src[k] : 0.0;
+    }
+    f64x4 acc[CBS / 16];
+#pragma unroll
+    for (int h = 0; h < CBS / 16; ++h) acc[h] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kq = 0; kq < CBS / 4; ++kq) {
+      const int k = 4 * kq + g;
+#pragma unroll
+      for (int h = 0; h < CBS / 16; ++h) acc[h] = mfma16(av[kq], Linv[(16 * h + l16) * (CBS + 1) + k], acc[h]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * rb + acc_row(0.0, g, r);
+      if (row < m) {
+#pragma unroll
+        for (int h = 0; h < CBS / 16; ++h) {
+          if (16 * h + l16 < kb) {
+            dst(row)[16 * h + l16] = acc[h][r];
+            dst2(row, 16 * h + l16, acc[h][r]);
+          }
+        }
+      }
+    }
+  }
+}
+
+// Blocked right-looking Cholesky of the augmented (n+1) x (n+1) matrix in LDS
+// (lower triangle of rows 0..n-1, row n = right-hand side b): on return rows
+// < n hold L and row n holds y = L^{-1} b, so the forward substitution is
+// folded into the factorisation.  Per CBS-column panel:
+//   * wave 0 factorises the diagonal block in registers (lane l = row l) and
+//     inverts the factor;
+//   * the rows below it, the right-hand side included, become A L^{-T}
+//     (matrix-core products);
+//   * the trailing lower triangle is updated with 16x16x4 FP64 matrix-core
+//     products whose operands are read straight from the matrix.
+// Linv: CBS * (CBS + 1) doubles of LDS.  Pivot problems set BA_W_* bits in *flag.
+__device__ inline void wg_cholesky_lds(double* A, int lda, int n, double* Linv, int* flag) {
+  const int lane = lane_id(), wv = wave_id();
+  int bad = 0;
+  for (int k0 = 0; k0 < n; k0 += CBS) {
+    const int kb = min(CBS, n - k0);
+    const int r0 = k0 + kb;
+    const int m = n + 1 - r0;
+    if (wv == 0) {
+      double Lr[CBS];
+#pragma unroll
+      for (int t = 0; t < CBS; ++t)
+        Lr[t] = (lane < kb && t <= lane) ? A[(k0 + lane) * lda + k0 + t] : 0.0;
+      wave_factor_invert(Lr, kb, A + k0 * lda + k0, lda, Linv, bad);
+    }
+    __syncthreads();
+    auto rows = [&](int r) { return (const double*)(A + (r0 + r) * lda + k0); };
+    auto dst = [&](int r) { return A + (r0 + r) * lda + k0; };
+    auto none = [](int, int, double) {};
+    panel_trsm_mfma(m, kb, Linv, rows, dst, none);
+    __syncthreads();
+    if (m > 1) {
+      // kb == CBS here (a shorter panel is the last one, with m == 1)
+      const int T = (m + 15) / 16;
+      const int ntile = T * (T + 1) / 2;
+      const int l16 = lane & 15, g = lane >> 4;
+      for (int t = wv; t < ntile; t += NWAVES) {
+        int ti = 0;
+        while (((ti + 1) * (ti + 2)) / 2 <= t) ++ti;
+        const int tj = t - (ti * (ti + 1)) / 2;
+        f64x4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * ti + acc_row(0.0, g, r), col = 16 * tj + l16;
+          const bool ok = row < m && col <= row && r0 + col < n;
+          acc[r] = ok ? A[(r0 + row) * lda + r0 + col] : 0.0;
+        }
+        // operand rows past the matrix read its last row; their products land
+        // in accumulator entries that are not stored
+        const double* pa = A + min(r0 + 16 * ti + l16, n) * lda + k0 + g;
+        const double* pb = A + min(r0 + 16 * tj + l16, n) * lda + k0 + g;
+#pragma unroll
+        for (int kq = 0; kq < CBS / 4; ++kq) acc = mfma16(-pa[4 * kq], pb[4 * kq], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * ti + acc_row(0.0, g, r), col = 16 * tj + l16;
+          if (row < m && col <= row && r0 + col < n) A[(r0 + row) * lda + r0 + col] = acc[r];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (wv == 0 && lane == 0) *flag = bad;
+  __syncthreads();
+}
+
+// L^T x = y with L and y (row n) from wg_cholesky_lds; x in LDS.  z: n doubles
+// of LDS scratch.
+__device__ inline void wg_backsolve_lds(const double* A, int lda, int n, double* x, double* z) {
+  const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  for (int j = tid; j < n; j += WG) z[j] = A[n * lda + j];
+  __syncthreads();
+  const int nb = (n + CBS - 1) / CBS;
+  for (int bk = nb - 1; bk >= 0; --bk) {
+    const int b0 = bk * CBS, bs = min(CBS, n - b0);
+    if (wv == 0) {
+      double Lc[CBS];
+#pragma unroll
+      for (int s2 = 0; s2 < CBS; ++s2)
+        Lc[s2] = (lane < bs && s2 < bs && s2 >= lane) ? A[(b0 + s2) * lda + b0 + lane] : 0.0;
+      double zz = lane < bs ? z[b0 + lane] : 0.0;
+#pragma unroll
+      for (int s2 = CBS - 1; s2 >= 0; --s2) {
+        if (s2 < bs) {
+          const double xs = readlane_f64(zz, s2) / readlane_f64(Lc[s2], s2);
+          if (lane == s2) zz = xs;
+          else if (lane < s2) zz -= Lc[s2] * xs;
+        }
+      }
+      if (lane < bs) x[b0 + lane] = zz;
+    }
+    __syncthreads();
+    for (int j = tid; j < b0; j += WG) {
+      double v = z[j];
+      for (int s2 = 0; s2 < bs; ++s2) v -= A[(b0 + s2) * lda + j] * x[b0 + s2];
+      z[j] = v;
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __device__ void wg_chol(const Params& P, int w, int iter, char* smem) {
   const WinDesc W = P.win[w];
@@ -171,9 +383,9 @@ __device__ void wg_chol(const Params& P, int w, int iter, char* smem) {
       b[i] = -b[i];
     }
     __syncthreads();
-    wg_cholesky(A, lda, n, colbuf, misc + 1);
-    __syncthreads();
-    if (tid < 64) wave_cholesky_solve(A, lda, n, b, x);
+    // colbuf: the inverse diagonal block, then n doubles of solve scratch
+    wg_cholesky_lds(A, lda, n, colbuf, misc + 1);
+    wg_backsolve_lds(A, lda, n, x, colbuf + CBS * (CBS + 1));
     __syncthreads();
     if (tid == 0) {
       int bad = misc[1];
@@ -289,16 +501,11 @@ __device__ void wg_backsub(const Params& P, int c, int iter, char* smem, int Rca
 #pragma unroll
         for (int m = 0; m < 6; ++m) t += (double)eo.Ej[m] * dxj[m] + (double)eo.Ei[m] * dxa[m];
       }
-      T red[8] = {eo.cd, eo.wd, T(0), T(0), T(0), T(0), T(0), T(0)};
-      double dred[8] = {t, 0, 0, 0, 0, 0, 0, 0};
-      for (int o2 = SEG >> 1; o2 > 0; o2 >>= 1) {
-        const T x0 = __shfl_xor(red[0], o2, 64), x1 = __shfl_xor(red[1], o2, 64);
-        const double x2 = __shfl_xor(dred[0], o2, 64);
-        red[0] += x0; red[1] += x1; dred[0] += x2;
-      }
+      T red[2] = {eo.cd, eo.wd};
+      seg_sum_n<2>(red, SEG);
+      const double tk = seg_sum(t, SEG);
       const T Ck = lam + red[0];
       const T Wk = red[1];
-      const double tk = dred[0];
       if (le.pv && lseg == 0) {
         const double dnew = le.d - ((double)Wk + tk) / (double)Ck;
         if (last) P.depth_out[W.patch_off + S.pk[le.slot]] = dnew;

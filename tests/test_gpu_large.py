@@ -28,6 +28,31 @@ def fp32_tolerance(w, iterations=2, factor=10.0):
     return (max(FP32_TOL[0], factor * dc), max(FP32_TOL[1], factor * drot), max(FP32_TOL[2], factor * dd))
 
 
+def depth_tolerance(w, iterations=2, eps=2.0 ** -18, factor=10.0, floor=1e-3):
+    """Per-patch relative tolerance of FP32-assembled inverse depths: `floor`
+    plus `factor` times the relative change of the FP64 oracle's depth when
+    every target and weight is perturbed by a random relative `eps` (2^-18,
+    about 32 FP32 ulps: the rounding of the few dozen FP32 operations that form
+    each patch's sums).  Patches the Gauss-Newton steps move far from their
+    start (weakly observed, outlier-dominated) amplify rounding by orders of
+    magnitude; this scales their tolerance accordingly."""
+    _, d0 = O.solve_schur(w, iterations=iterations)
+    rng = np.random.default_rng(5)
+    w2 = w.copy()
+    w2.targets = w.targets * (1 + eps * rng.uniform(-1, 1, w.targets.shape))
+    w2.weights = w.weights * (1 + eps * rng.uniform(-1, 1, w.weights.shape))
+    _, d1 = O.solve_schur(w2, iterations=iterations)
+    return floor + factor * np.abs(d1 - d0) / np.abs(d0)
+
+
+def _depth_ok(d_gpu, d_ref, tol):
+    rel = np.abs(d_gpu - d_ref) / np.abs(d_ref)
+    worst = int(np.argmax(rel / tol))
+    print(f"  depth: max rel {rel.max():.2e}, worst vs tolerance at patch {worst}: "
+          f"{rel[worst]:.2e} <= {tol[worst]:.2e}")
+    return bool(np.all(rel <= tol))
+
+
 def _wide(n_frames, ppf, r, seed, fp32=True, n_fixed=2):
     return synth.make_window(n_frames, ppf, r, seed=[2208, 9, seed], outlier_frac=0.1, fp32=fp32,
                              n_fixed=n_fixed)
@@ -79,8 +104,9 @@ def test_fp32_wide_window_matches_oracle(shape):
     pr, dr = O.solve(w)
     dc, drot, dd = compare(out[0][0], out[0][1], pr, dr)
     tol = fp32_tolerance(w)
-    print(f"{shape}: {dc:.2e} m {drot:.2e} deg depth {dd:.2e} (tolerance {tol[0]:.1e} m {tol[1]:.1e} deg {tol[2]:.1e})")
-    assert dc < tol[0] and drot < tol[1] and dd < tol[2]
+    print(f"{shape}: {dc:.2e} m {drot:.2e} deg depth {dd:.2e} (tolerance {tol[0]:.1e} m {tol[1]:.1e} deg)")
+    assert dc < tol[0] and drot < tol[1]
+    assert _depth_ok(out[0][1], dr, depth_tolerance(w))
 
 
 def test_fp64_24_frames_matches_oracle():
@@ -127,5 +153,6 @@ def test_large_windows_64x256_k4_batch_of_8():
         dc, drot, dd = compare(out[i][0], out[i][1], pr, dr)
         tol = fp32_tolerance(wins[i], iterations=4)
         print(f"large window {i}: {dc:.2e} m {drot:.2e} deg depth {dd:.2e} "
-              f"(tolerance {tol[0]:.1e} m {tol[1]:.1e} deg {tol[2]:.1e})")
-        assert dc < tol[0] and drot < tol[1] and dd < tol[2]
+              f"(tolerance {tol[0]:.1e} m {tol[1]:.1e} deg)")
+        assert dc < tol[0] and drot < tol[1]
+        assert _depth_ok(out[i][1], dr, depth_tolerance(wins[i], iterations=4))
