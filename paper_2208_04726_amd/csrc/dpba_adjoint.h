@@ -24,14 +24,14 @@
 
 namespace dpba {
 
-__device__ inline void cross3(const double* a, const double* b, double* c) {
+__device__ __forceinline__ void cross3(const double* a, const double* b, double* c) {
   c[0] = a[1] * b[2] - a[2] * b[1];
   c[1] = a[2] * b[0] - a[0] * b[2];
   c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
 // Exp(xi) = (R, t) for xi = (rho, phi): Rodrigues with series below 1e-2 rad.
-__device__ inline void se3_exp(const double* xi, double* R, double* t) {
+__device__ __forceinline__ void se3_exp(const double* xi, double* R, double* t) {
   const double px = xi[3], py = xi[4], pz = xi[5];
   const double th2 = px * px + py * py + pz * pz;
   double A, B, C;
@@ -61,7 +61,7 @@ __device__ inline void se3_exp(const double* xi, double* R, double* t) {
 
 // ad(xi)^T z for ad(xi) = [[hat(phi), hat(rho)], [0, hat(phi)]]:
 // (-phi x z_rho, -rho x z_rho - phi x z_phi).
-__device__ inline void ad_T(const double* xi, const double* z, double* o) {
+__device__ __forceinline__ void ad_T(const double* xi, const double* z, double* o) {
   double c1[3], c2[3], c3[3];
   cross3(xi + 3, z, c1);
   cross3(xi, z, c2);
@@ -73,7 +73,7 @@ __device__ inline void ad_T(const double* xi, const double* z, double* o) {
 }
 
 // J_l(xi)^T v with J_l = sum_m ad(xi)^m / (m+1)!  (left Jacobian of SE(3)).
-__device__ inline void left_jacobian_T(const double* xi, const double* v, double* out) {
+__device__ __forceinline__ void left_jacobian_T(const double* xi, const double* v, double* out) {
   double term[6], nxt[6];
   for (int m = 0; m < 6; ++m) { term[m] = v[m]; out[m] = v[m]; }
   for (int k = 1; k <= 16; ++k) {
@@ -84,7 +84,7 @@ __device__ inline void left_jacobian_T(const double* xi, const double* v, double
 }
 
 // Ad(Exp(xi))^T v = (R^T v_rho, R^T (v_phi - t x v_rho)).
-__device__ inline void adjoint_exp_T(const double* xi, const double* v, double* out) {
+__device__ __forceinline__ void adjoint_exp_T(const double* xi, const double* v, double* out) {
   double R[9], t[3], c[3];
   se3_exp(xi, R, t);
   cross3(t, v, c);
@@ -98,7 +98,7 @@ __device__ inline void adjoint_exp_T(const double* xi, const double* v, double* 
 // Cotangent of a pose 7-vector (t, q) mapped to the left tangent:
 // d vec7(Exp(e) T)/de at 0 has dt = rho - t x phi ... transposed:
 //   rho_bar = g_t,  phi_bar = t x g_t + (qw g_qv + qv x g_qv) / 2 - qv g_qw / 2.
-__device__ inline void pose7_cotangent(const double* p, const double* g, double* out) {
+__device__ __forceinline__ void pose7_cotangent(const double* p, const double* g, double* out) {
   double c[3], c2[3];
   cross3(p, g, c);
   cross3(p + 3, g + 3, c2);
@@ -112,7 +112,7 @@ __device__ inline void pose7_cotangent(const double* p, const double* g, double*
 // Zero the gradient outputs of a window and lay out the depth cotangent of
 // the final state in position order.
 template <typename T>
-__device__ void wg_adj_init(const Params& P, int w) {
+__device__ __forceinline__ void wg_adj_init(const Params& P, int w) {
   const WinDesc W = P.win[w];
   const int tid = threadIdx.x;
   T* gt = (T*)P.grad_targets + 2 * W.edge_off;
@@ -129,7 +129,7 @@ __device__ void wg_adj_init(const Params& P, int w) {
 // dxi_bar = J_l(dxi)^T xi_bar_{n+1}; also the direct cotangent
 // Ad(Exp(dxi))^T xi_bar_{n+1}.
 template <typename T>
-__device__ void wg_chol_adj(const Params& P, int w, int it, char* smem) {
+__device__ __forceinline__ void wg_chol_adj(const Params& P, int w, int it, char* smem) {
   const WinDesc W = P.win[w];
   const int tid = threadIdx.x;
   int* misc = (int*)smem;
@@ -201,7 +201,7 @@ __device__ void wg_chol_adj(const Params& P, int w, int it, char* smem) {
 // to the edge's left perturbation eps = eps_j - Ad(T_ji) eps_i (g[0..5]) and
 // its inverse depth (g[6]).  With w_i = Ad v_i, w = v_j - w_i,
 // m = d w_rho + w_phi x p + t v_d (the point motion of v) and n = Pi^T u.
-__device__ inline void jac_pair_grad(const double* u, const double* wi, const double* wv,
+__device__ __forceinline__ void jac_pair_grad(const double* u, const double* wi, const double* wv,
                                      double vd, const double* p, double d, const double* t,
                                      double fx, double fy, double* g) {
   const double X = p[0], Y = p[1], Z = p[2];
@@ -233,7 +233,7 @@ __device__ inline void jac_pair_grad(const double* u, const double* wi, const do
 
 // Ad(T) z from the LDS relative pose (R, t, hat(t) R).
 template <typename T>
-__device__ inline void rel_adj(const T* rel, const double* z, double* o) {
+__device__ __forceinline__ void rel_adj(const T* rel, const double* z, double* o) {
   for (int r = 0; r < 3; ++r) {
     o[r] = (double)rel[3 * r] * z[0] + (double)rel[3 * r + 1] * z[1] + (double)rel[3 * r + 2] * z[2] +
            (double)rel[12 + 3 * r] * z[3] + (double)rel[13 + 3 * r] * z[4] + (double)rel[14 + 3 * r] * z[5];
@@ -242,7 +242,7 @@ __device__ inline void rel_adj(const T* rel, const double* z, double* o) {
 }
 // Ad(T)^T z
 template <typename T>
-__device__ inline void rel_adj_T(const T* rel, const double* z, double* o) {
+__device__ __forceinline__ void rel_adj_T(const T* rel, const double* z, double* o) {
   for (int c = 0; c < 3; ++c) {
     o[c] = (double)rel[c] * z[0] + (double)rel[3 + c] * z[1] + (double)rel[6 + c] * z[2];
     o[3 + c] = (double)rel[12 + c] * z[0] + (double)rel[15 + c] * z[1] + (double)rel[18 + c] * z[2] +
@@ -264,7 +264,7 @@ __host__ __device__ inline int edge_adj_lds_bytes(int Rcap, int esize) {
 // gradients, the depth cotangent of x_it (position order) and the chunk's
 // pose-cotangent partial.
 template <typename T>
-__device__ void wg_edge_adj(const Params& P, int c, int it, char* smem, int Rcap) {
+__device__ __forceinline__ void wg_edge_adj(const Params& P, int c, int it, char* smem, int Rcap) {
   double* lp = (double*)smem;
   T* rel = (T*)(smem + al16(Rcap * 7 * 8));
   double* dx = (double*)(smem + backsub_dx_offset(Rcap, (int)sizeof(T)));
@@ -475,7 +475,7 @@ __device__ void wg_edge_adj(const Params& P, int c, int it, char* smem, int Rcap
 }
 
 // x_bar_n for the poses: direct part plus every chunk's partial; fixed frames 0.
-__device__ inline void wg_frame_adj(const Params& P, int w) {
+__device__ __forceinline__ void wg_frame_adj(const Params& P, int w) {
   const WinDesc W = P.win[w];
   const int N = W.n_frames, nfix = W.n_fixed;
   if (P.status[w] != 0) return;

@@ -39,18 +39,18 @@ template <typename T> struct AccT;
 template <> struct AccT<float> { typedef f32x4 type; };
 template <> struct AccT<double> { typedef f64x4 type; };
 
-__device__ inline f32x4 mfma16(float a, float b, f32x4 c) {
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
-__device__ inline f64x4 mfma16(double a, double b, f64x4 c) {
+__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
 // Row of the 16x16 result held in accumulator register r of a lane in lane
 // group g = lane / 16 (the column is lane % 16).  The f32 16x16x4 product
 // keeps four consecutive rows per lane group, the f64 product interleaves them.
-__device__ inline int acc_row(float, int g, int r) { return 4 * g + r; }
-__device__ inline int acc_row(double, int g, int r) { return 4 * r + g; }
+__device__ __forceinline__ int acc_row(float, int g, int r) { return 4 * g + r; }
+__device__ __forceinline__ int acc_row(double, int g, int r) { return 4 * r + g; }
 
 constexpr int SBMAX = 32;       // patches per sub-batch (K block of the Schur product)
 constexpr int SBE = 1024;       // staged edges per sub-batch (SB x lane segment width)
@@ -110,7 +110,7 @@ __host__ __device__ inline int backsub_lds_bytes(int Rcap, int esize) {
 }
 
 // packed index of (m, n), m <= n, in the 21-entry upper triangle of a 6x6
-__device__ inline int sym6(int m, int n) {
+__device__ __forceinline__ int sym6(int m, int n) {
   if (m > n) { int t = m; m = n; n = t; }
   return m * 6 - (m * (m - 1)) / 2 + (n - m);
 }
@@ -129,7 +129,7 @@ struct EdgeOut {
 
 // Linearise one edge.  rel: R (9), t (3), hat(t)R (9) of T_ji in LDS.
 template <typename T>
-__device__ inline void linearize_edge(const T* rel, T xb, T yb, T d, T tx, T ty, T w0,
+__device__ __forceinline__ void linearize_edge(const T* rel, T xb, T yb, T d, T tx, T ty, T w0,
                                       T w1, T fx, T fy, T cx, T cy, T zmin, bool valid,
                                       EdgeOut<T>& o) {
   const T X = rel[0] * xb + rel[1] * yb + rel[2] + rel[9] * d;
@@ -166,7 +166,7 @@ __device__ inline void linearize_edge(const T* rel, T xb, T yb, T d, T tx, T ty,
 }
 
 // Broadcast a value computed by thread 0 to the workgroup.
-__device__ inline int wg_bcast_status(const int32_t* status, int w, int* slot) {
+__device__ __forceinline__ int wg_bcast_status(const int32_t* status, int w, int* slot) {
   if (threadIdx.x == 0) *slot = status[w];
   __syncthreads();
   const int s = *slot;
@@ -177,7 +177,7 @@ __device__ inline int wg_bcast_status(const int32_t* status, int w, int* slot) {
 
 // Relative poses T_ja for j in [lo, hi] into rel[(j - f_lo) * RELW].
 template <typename T>
-__device__ inline void load_relposes(const double* poses, int a, int lo, int hi, int f_lo, T* rel) {
+__device__ __forceinline__ void load_relposes(const double* poses, int a, int lo, int hi, int f_lo, T* rel) {
   for (int j = lo + (int)threadIdx.x; j <= hi; j += WG) {
     double R[9], t[3];
     relative_pose(poses + 7 * a, poses + 7 * j, R, t);
@@ -198,7 +198,7 @@ __device__ inline void load_relposes(const double* poses, int a, int lo, int hi,
 
 // A[p][q] of Ad(T_ji) = [[R, hat(t)R], [0, R]] from the LDS relative pose.
 template <typename T>
-__device__ inline T adj_at(const T* rel, int p, int q) {
+__device__ __forceinline__ T adj_at(const T* rel, int p, int q) {
   if (p < 3) return q < 3 ? rel[3 * p + q] : rel[12 + 3 * p + (q - 3)];
   return q < 3 ? T(0) : rel[3 * (p - 3) + (q - 3)];
 }
@@ -254,7 +254,7 @@ struct WinEdges {   // edge arrays in edge order (inputs, or the gathered copies
   const void* w;
 };
 
-__device__ inline WinEdges win_edges(const Params& P, const WinDesc& W, int gathered, int esize) {
+__device__ __forceinline__ WinEdges win_edges(const Params& P, const WinDesc& W, int gathered, int esize) {
   WinEdges e;
   if (gathered) {
     e.j = P.gj + W.edge_off;
@@ -271,7 +271,7 @@ __device__ inline WinEdges win_edges(const Params& P, const WinDesc& W, int gath
 // `iter` selects the inverse-depth state; `extra` (optional, position order)
 // is staged alongside (the depth cotangents of the adjoint).
 template <typename T>
-__device__ inline void stage_issue(const Params& P, const WinDesc& W, int w, const WinEdges& we,
+__device__ __forceinline__ void stage_issue(const Params& P, const WinDesc& W, int w, const WinEdges& we,
                                    int4 d, int iter, const double* extra, StageRegs<T>& R) {
   const int tid = threadIdx.x;
   const int pos0 = d.x, n = d.y & 255, e0 = d.z, e1 = d.w;
@@ -303,7 +303,7 @@ __device__ inline void stage_issue(const Params& P, const WinDesc& W, int w, con
 }
 
 template <typename T>
-__device__ inline void stage_store(int4 d, const StageRegs<T>& R, Stage<T>& S) {
+__device__ __forceinline__ void stage_store(int4 d, const StageRegs<T>& R, Stage<T>& S) {
   const int tid = threadIdx.x;
   const int n = d.y & 255, ne = d.w - d.z;
 #pragma unroll
@@ -338,7 +338,7 @@ struct LaneEdge {
 };
 
 template <typename T>
-__device__ inline LaneEdge<T> lane_edge(const Stage<T>& S, int slot, bool slot_ok, int n, int lseg, int a) {
+__device__ __forceinline__ LaneEdge<T> lane_edge(const Stage<T>& S, int slot, bool slot_ok, int n, int lseg, int a) {
   LaneEdge<T> L;
   L.slot = slot;
   L.pv = slot_ok && slot < n;
@@ -360,7 +360,7 @@ __device__ inline LaneEdge<T> lane_edge(const Stage<T>& S, int slot, bool slot_o
 }
 
 // Frame range of a chunk: union of its anchors' ranges.
-__device__ inline void chunk_range(const Params& P, const WinDesc& W, const ChunkDesc& cd,
+__device__ __forceinline__ void chunk_range(const Params& P, const WinDesc& W, const ChunkDesc& cd,
                                    int& f_lo, int& f_hi) {
   const int32_t* ar = P.arange + 2 * W.frame_off;
   f_lo = 1 << 30;
@@ -377,7 +377,7 @@ __device__ inline void chunk_range(const Params& P, const WinDesc& W, const Chun
 // value ever carries the whole window's sum.  FP64 assembly: the matrix-core
 // accumulators themselves are the running sums (of the negated entries).
 template <typename T, int MAXT>
-__device__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rcap) {
+__device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rcap) {
   typedef typename AccT<T>::type Acc;
   const AsmLayout L = asm_layout(Rcap, (int)sizeof(T));
   double* lp = (double*)(smem + L.poses);

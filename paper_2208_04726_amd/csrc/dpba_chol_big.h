@@ -30,16 +30,17 @@ __host__ __device__ inline int gather_tiles(int n) {
 __host__ __device__ inline int big_ld(int rcap) { return 6 * rcap + 1; }
 
 // LDS: panel ((n+1) rows padded to 16, CB columns), the diagonal block's
-// factor and its inverse, the right-hand side / solution, flags.
+// factor and its inverse, row-block flags, the right-hand side / solution,
+// the reciprocal diagonal of L.
 __host__ __device__ inline int chol_big_lds_bytes(int n) {
   const int rows = ((n + 1 + 15) / 16) * 16;
-  return 64 + (rows * PLD + 2 * CB * PLD + 2 * (n + 8)) * 8;
+  return 64 + (rows * PLD + 2 * CB * PLD + 16 + 3 * (n + 8)) * 8;
 }
 
 // One 64 x 64 tile of the augmented system of window w, summed from the chunk
 // partials in chunk order (the order of the small-window gather):
 // rows < n hold S + lambda I (lower triangle), row n holds -s.
-__device__ void wg_gather_big(const Params& P, int w, int tile) {
+__device__ __forceinline__ void wg_gather_big(const Params& P, int w, int tile) {
   const WinDesc W = P.win[w];
   const int nfix = W.n_fixed;
   const int n = 6 * (W.n_frames - nfix);
@@ -50,21 +51,46 @@ __device__ void wg_gather_big(const Params& P, int w, int tile) {
   const int bj = tile - (bi * (bi + 1)) / 2;
   const int ld = P.ld_big;
   double* A = P.s_big + (int64_t)w * ld * ld;
-  for (int e = threadIdx.x; e < GT * GT; e += WG) {
-    const int r = GT * bi + e / GT, c = GT * bj + e % GT;
-    if (r > n || c > r || c >= n) continue;
-    double v = 0.0;
-    for (int cc = 0; cc < W.n_chunks; ++cc) {
-      const int ci = W.chunk_off + cc;
-      const int lo_free = P.cstate[2 * ci], Dc = P.cstate[2 * ci + 1];
-      if (Dc == 0) continue;
-      const int off = 6 * (lo_free - nfix);
-      const double* part = P.partial + W.part_off + (int64_t)cc * W.part_stride;
-      if (c < off || c >= off + Dc) continue;
-      if (r == n) v += part[Dc * Dc + (c - off)];
-      else if (r < off + Dc) v += part[(r - off) * Dc + (c - off)];
+  constexpr int EPT = GT * GT / WG;   // elements per thread
+  double v[EPT];
+  int rr[EPT], cc_[EPT];
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int e = threadIdx.x + u * WG;
+    rr[u] = GT * bi + e / GT;
+    cc_[u] = GT * bj + e % GT;
+    v[u] = 0.0;
+  }
+  const int r_lo = GT * bi, r_hi = min(GT * bi + GT - 1, n);
+  const int c_lo = GT * bj, c_hi = min(GT * bj + GT - 1, n - 1);
+  // chunks in order; a chunk whose columns miss the tile, or whose rows miss
+  // it (the right-hand-side row n belongs to every chunk), is skipped
+  for (int cc = 0; cc < W.n_chunks; ++cc) {
+    const int ci = W.chunk_off + cc;
+    const int lo_free = P.cstate[2 * ci], Dc = P.cstate[2 * ci + 1];
+    if (Dc == 0) continue;
+    const int off = 6 * (lo_free - nfix);
+    if (c_hi < off || c_lo >= off + Dc) continue;
+    if (!(r_hi >= off && r_lo < off + Dc) && !(r_lo <= n && n <= r_hi)) continue;
+    const double* part = P.partial + W.part_off + (int64_t)cc * W.part_stride;
+    double a[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      const int r = rr[u], c = cc_[u];
+      a[u] = 0.0;
+      if (r <= n && c <= r && c < n && c >= off && c < off + Dc) {
+        if (r == n) a[u] = part[Dc * Dc + (c - off)];
+        else if (r < off + Dc) a[u] = part[(r - off) * Dc + (c - off)];
+      }
     }
-    A[(int64_t)r * ld + c] = (r == n) ? -v : (r == c ? v + P.lambda : v);
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) v[u] += a[u];
+  }
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int r = rr[u], c = cc_[u];
+    if (r > n || c > r || c >= n) continue;
+    A[(int64_t)r * ld + c] = (r == n) ? -v[u] : (r == c ? v[u] + P.lambda : v[u]);
   }
 }
 
@@ -74,12 +100,13 @@ __device__ void wg_gather_big(const Params& P, int w, int tile) {
 // diagonal block; the rows below become A L^{-T} (matrix-core products, kept
 // in the LDS panel and written back); the trailing lower triangle is updated
 // from the LDS panel, two 16x16 tiles per wave in flight.
-__device__ inline void wg_cholesky_big(double* A, int ld, int n, char* smem, int* flag) {
+__device__ __forceinline__ void wg_cholesky_big(double* A, int ld, int n, char* smem, double* dinv, int* flag) {
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   const int rows_pad = ((n + 1 + 15) / 16) * 16;
   double* Pn = (double*)(smem + 64);           // panel rows below the diagonal block
   double* Linv = Pn + rows_pad * PLD;          // inverse of the diagonal block
   double* Ld = Linv + CB * PLD;                // the diagonal block's factor
+  int* nzb = (int*)(Ld + CB * PLD);            // nonzero flags of the panel's row blocks
   int bad = 0;
   for (int k0 = 0; k0 < n; k0 += CB) {
     const int kb = min(CB, n - k0);
@@ -89,8 +116,8 @@ __device__ inline void wg_cholesky_big(double* A, int ld, int n, char* smem, int
       double Lr[CB];
 #pragma unroll
       for (int t = 0; t < CB; ++t)
-        Lr[t] = (lane < kb && t <= lane) ? A[(int64_t)(k0 + lane) * ld + k0 + t] : 0.0;
-      wave_factor_invert(Lr, kb, Ld, PLD, Linv, bad);
+        Lr[t] = (lane < kb && t <= lane) ? A[(int64_t)(k0 + lane) * ld + k0 + t] : (t == lane ? 1.0 : 0.0);
+      wave_factor_invert(Lr, kb, Ld, PLD, Linv, dinv + k0, bad);
       if (lane < kb) {
 #pragma unroll
         for (int t = 0; t < CB; ++t)
@@ -106,7 +133,7 @@ __device__ inline void wg_cholesky_big(double* A, int ld, int n, char* smem, int
       auto rows = [&](int r) { return (const double*)(A + (int64_t)(r0 + r) * ld + k0); };
       auto dst = [&](int r) { return Pn + r * PLD; };
       auto dst2 = [&](int r, int c, double v) { A[(int64_t)(r0 + r) * ld + k0 + c] = v; };
-      panel_trsm_mfma(m, kb, Linv, rows, dst, dst2);
+      panel_trsm_mfma(m, kb, Linv, rows, dst, dst2, nzb);
     }
     __syncthreads();
     // ---- trailing update A[r][c] -= sum_t P[r][t] P[c][t], c <= r, c < n
@@ -114,18 +141,19 @@ __device__ inline void wg_cholesky_big(double* A, int ld, int n, char* smem, int
       const int T = (m + 15) / 16;
       const int ntile = T * (T + 1) / 2;
       const int l16 = lane & 15, g = lane >> 4;
-      for (int t0 = wv; t0 < ntile; t0 += 2 * NWAVES) {
-        f64x4 acc[2];
-        int ti[2], tj[2];
-        bool has[2];
+      constexpr int TU = 4;   // tiles per wave in flight
+      for (int t0 = wv; t0 < ntile; t0 += TU * NWAVES) {
+        f64x4 acc[TU];
+        int ti[TU], tj[TU];
+        bool has[TU];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < TU; ++u) {
           const int t = t0 + u * NWAVES;
-          has[u] = t < ntile;
           int a = 0;
           while (((a + 1) * (a + 2)) / 2 <= t) ++a;
           ti[u] = a;
           tj[u] = t - (a * (a + 1)) / 2;
+          has[u] = t < ntile && nzb[ti[u]] && nzb[tj[u]];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = 16 * ti[u] + acc_row(0.0, g, r), col = 16 * tj[u] + l16;
@@ -134,7 +162,7 @@ __device__ inline void wg_cholesky_big(double* A, int ld, int n, char* smem, int
           }
         }
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < TU; ++u) {
           if (has[u]) {
             const double* pa = Pn + (16 * ti[u] + l16) * PLD + g;
             const double* pb = Pn + (16 * tj[u] + l16) * PLD + g;
@@ -143,7 +171,7 @@ __device__ inline void wg_cholesky_big(double* A, int ld, int n, char* smem, int
           }
         }
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < TU; ++u) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = 16 * ti[u] + acc_row(0.0, g, r), col = 16 * tj[u] + l16;
@@ -160,7 +188,8 @@ __device__ inline void wg_cholesky_big(double* A, int ld, int n, char* smem, int
 }
 
 // L^T x = y, L in A (lower, ld), y = row n of A; x into LDS `x` (n entries).
-__device__ inline void wg_backsolve_big(const double* A, int ld, int n, double* x, double* z) {
+__device__ __forceinline__ void wg_backsolve_big(const double* A, int ld, int n, const double* dinv, double* x,
+                                        double* z) {
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   for (int j = tid; j < n; j += WG) z[j] = A[(int64_t)n * ld + j];
   __syncthreads();
@@ -176,7 +205,7 @@ __device__ inline void wg_backsolve_big(const double* A, int ld, int n, double* 
 #pragma unroll
       for (int s = CB - 1; s >= 0; --s) {
         if (s < bs) {
-          const double xs = readlane_f64(zz, s) / readlane_f64(Lc[s], s);
+          const double xs = readlane_f64(zz, s) * dinv[b0 + s];
           if (lane == s) zz = xs;
           else if (lane < s) zz -= Lc[s] * xs;
         }
@@ -196,7 +225,7 @@ __device__ inline void wg_backsolve_big(const double* A, int ld, int n, double* 
 // Solve and retraction of a window with n > 126 (the system was gathered by
 // wg_gather_big).
 template <typename T>
-__device__ void wg_chol_big(const Params& P, int w, int iter, char* smem) {
+__device__ __forceinline__ void wg_chol_big(const Params& P, int w, int iter, char* smem) {
   const WinDesc W = P.win[w];
   const int tid = threadIdx.x;
   int* misc = (int*)smem;
@@ -213,10 +242,11 @@ __device__ void wg_chol_big(const Params& P, int w, int iter, char* smem) {
   const int ld = P.ld_big;
   double* A = P.s_big + (int64_t)w * ld * ld;
   const int rows_pad = ((n + 1 + 15) / 16) * 16;
-  double* x = (double*)(smem + 64) + rows_pad * PLD + 2 * CB * PLD;
+  double* x = (double*)(smem + 64) + rows_pad * PLD + 2 * CB * PLD + 16;
   double* z = x + n + 8;
-  wg_cholesky_big(A, ld, n, smem, misc + 1);
-  wg_backsolve_big(A, ld, n, x, z);
+  double* dinv = z + n + 8;
+  wg_cholesky_big(A, ld, n, smem, dinv, misc + 1);
+  wg_backsolve_big(A, ld, n, dinv, x, z);
   if (tid == 0) {
     int bad = misc[1];
     for (int i = 0; i < n; ++i)

@@ -94,8 +94,8 @@ struct Params {
 
 // ---------------------------------------------------------------------------
 // wave / workgroup helpers
-__device__ inline int lane_id() { return threadIdx.x & 63; }
-__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Lane exchanges of the segment sums, done in the vector ALU: DPP quad
 // permutations (the lane 1 and 2 apart), the half-row and row mirrors (the
@@ -106,11 +106,11 @@ __device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadId
 // the additions depends only on the segment width.  All 64 lanes must be
 // active.
 template <int CTRL>
-__device__ inline float dpp_get(float v) {
+__device__ __forceinline__ float dpp_get(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
 template <int CTRL>
-__device__ inline double dpp_get(double v) {
+__device__ __forceinline__ double dpp_get(double v) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
@@ -118,14 +118,14 @@ __device__ inline double dpp_get(double v) {
 }
 // v plus the same lane of the other 16-lane row (ROW = 16) or 32-lane half (32)
 template <int ROW>
-__device__ inline float swap_add(float v) {
+__device__ __forceinline__ float swap_add(float v) {
   const int b = __float_as_int(v);
   const auto r = ROW == 16 ? __builtin_amdgcn_permlane16_swap(b, b, false, false)
                            : __builtin_amdgcn_permlane32_swap(b, b, false, false);
   return __int_as_float(r[0]) + __int_as_float(r[1]);
 }
 template <int ROW>
-__device__ inline double swap_add(double v) {
+__device__ __forceinline__ double swap_add(double v) {
   const long long b = __double_as_longlong(v);
   const int l = (int)(b & 0xffffffffLL), h = (int)(b >> 32);
   const auto lo = ROW == 16 ? __builtin_amdgcn_permlane16_swap(l, l, false, false)
@@ -139,7 +139,7 @@ __device__ inline double swap_add(double v) {
 
 // Sums of v[0..N) over aligned power-of-two lane segments of width seg.
 template <int N, typename T>
-__device__ inline void seg_sum_n(T* v, int seg) {
+__device__ __forceinline__ void seg_sum_n(T* v, int seg) {
   if (seg > 1) {
 #pragma unroll
     for (int m = 0; m < N; ++m) v[m] += dpp_get<0xB1>(v[m]);   // quad_perm [1,0,3,2]
@@ -167,29 +167,29 @@ __device__ inline void seg_sum_n(T* v, int seg) {
 }
 
 template <typename T>
-__device__ inline T seg_sum(T v, int seg) {
+__device__ __forceinline__ T seg_sum(T v, int seg) {
   seg_sum_n<1>(&v, seg);
   return v;
 }
 
 template <typename T>
-__device__ inline void seg_sum8(T* v, int seg) {
+__device__ __forceinline__ void seg_sum8(T* v, int seg) {
   seg_sum_n<8>(v, seg);
 }
 
 // Reciprocal and reciprocal square root: the hardware approximations (about
 // 1 ulp) in FP32, correctly rounded division in FP64.
-__device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ inline double recip(double x) { return 1.0 / x; }
-__device__ inline float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ inline double rsqrt_(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
 
-__device__ inline bool isfinite_d(double x) { return __builtin_isfinite(x); }
-__device__ inline bool isfinite_f(float x) { return __builtin_isfinite(x); }
+__device__ __forceinline__ bool isfinite_d(double x) { return __builtin_isfinite(x); }
+__device__ __forceinline__ bool isfinite_f(float x) { return __builtin_isfinite(x); }
 
 // Exclusive scan of data[0..n) in place by the whole workgroup; returns the
 // total.  lds must hold WG ints.  All threads must call it.
-__device__ inline int wg_exclusive_scan(int32_t* data, int n, int* lds) {
+__device__ __forceinline__ int wg_exclusive_scan(int32_t* data, int n, int* lds) {
   const int tid = threadIdx.x;
   const int per = (n + WG - 1) / WG;
   const int b = tid * per, e = min(n, b + per);
@@ -217,7 +217,7 @@ __device__ inline int wg_exclusive_scan(int32_t* data, int n, int* lds) {
 
 // ---------------------------------------------------------------------------
 // FP64 SE(3) helpers.  Pose 7-vector: t (3), unit quaternion (x, y, z, w).
-__device__ inline void quat_to_rot(const double* q, double* R) {
+__device__ __forceinline__ void quat_to_rot(const double* q, double* R) {
   const double x = q[0], y = q[1], z = q[2], w = q[3];
   R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - z * w);     R[2] = 2 * (x * z + y * w);
   R[3] = 2 * (x * y + z * w);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - x * w);
@@ -225,7 +225,7 @@ __device__ inline void quat_to_rot(const double* q, double* R) {
 }
 
 // Relative pose T_ji = T_j T_i^{-1}: R = R_j R_i^T, t = t_j - R t_i.
-__device__ inline void relative_pose(const double* pi, const double* pj, double* R, double* t) {
+__device__ __forceinline__ void relative_pose(const double* pi, const double* pj, double* R, double* t) {
   double Ri[9], Rj[9];
   quat_to_rot(pi + 3, Ri);
   quat_to_rot(pj + 3, Rj);
@@ -243,7 +243,7 @@ __device__ inline void relative_pose(const double* pi, const double* pj, double*
 // Rodrigues' R = I + A K + B K^2, V = I + B K + C K^2, K = hat(phi); the
 // rotation is applied to the quaternion as q_exp (x) q, then renormalised.
 // Series forms of A, B, C and of the half-angle terms below theta = 1e-2.
-__device__ inline void retract_left(const double* xi, const double* pin, double* pout) {
+__device__ __forceinline__ void retract_left(const double* xi, const double* pin, double* pout) {
   const double rx = xi[0], ry = xi[1], rz = xi[2];
   const double px = xi[3], py = xi[4], pz = xi[5];
   const double th2 = px * px + py * py + pz * pz;

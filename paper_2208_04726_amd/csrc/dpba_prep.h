@@ -32,7 +32,7 @@ constexpr int PU = 8;   // edges per thread in flight in the preparation loops
 __host__ __device__ inline int seg_width(int maxdeg) { return maxdeg <= 16 ? 16 : (maxdeg <= 32 ? 32 : 64); }
 __host__ __device__ inline int sb_width(int seg) { return seg == 64 ? 16 : 32; }
 
-__device__ inline int lower_bound_i32(const int32_t* a, int n, int v) {
+__device__ __forceinline__ int lower_bound_i32(const int32_t* a, int n, int v) {
   int lo = 0, hi = n;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
@@ -42,7 +42,7 @@ __device__ inline int lower_bound_i32(const int32_t* a, int n, int v) {
 }
 
 template <typename T>
-__device__ void wg_prep(const Params& P, int w, int* lds) {
+__device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
   const WinDesc W = P.win[w];
   const int N = W.n_frames, M = W.n_patches, E = W.n_edges;
   const int tid = threadIdx.x;

@@ -17,12 +17,12 @@ constexpr int CBS_LDS = 32 * 33;   // inverse diagonal block of the blocked fact
 // block and solve scratch (the adjoint's column buffers fit in the same space).
 __host__ __device__ inline int chol_lds_bytes(int n) {
   const int lda = n + 1;
-  return 64 + (n * lda + 2 * n + 8) * 8 + (CBS_LDS + 128) * 8;
+  return 64 + (n * lda + 2 * n + 8) * 8 + (CBS_LDS + 2 * 128) * 8;
 }
 
 // Sum the chunk partials of window w into A (n x lda, lower) and b (n).
 // With b2 (adjoint), also the depth-cotangent row: b2 = -sum_k E_k dbar_k / C_k.
-__device__ inline void gather_partials(const Params& P, int w, const WinDesc& W, double* A,
+__device__ __forceinline__ void gather_partials(const Params& P, int w, const WinDesc& W, double* A,
                                        int lda, double* b, int n, double* b2 = nullptr) {
   const int tid = threadIdx.x;
   const int nfix = W.n_fixed;
@@ -52,7 +52,7 @@ __device__ inline void gather_partials(const Params& P, int w, const WinDesc& W,
 // published through an LDS buffer (two alternating buffers, one barrier per
 // column) and every thread applies the rank-one update to its own elements.
 // Writes BA_W_* bits (non-positive or non-finite pivot) to *flag (thread 0).
-__device__ inline void wg_cholesky(double* A, int lda, int n, double* colbuf, int* flag) {
+__device__ __forceinline__ void wg_cholesky(double* A, int lda, int n, double* colbuf, int* flag) {
   const int tid = threadIdx.x;
   const int tr = tid & 31, tc = tid >> 5;
   double Ar[4][8];
@@ -122,7 +122,7 @@ __device__ inline void wg_cholesky(double* A, int lda, int n, double* colbuf, in
 }
 
 // L L^T x = rhs by one wave (lanes hold entries l and l + 64); L in LDS.
-__device__ inline void wave_cholesky_solve(const double* A, int lda, int n, const double* rhs,
+__device__ __forceinline__ void wave_cholesky_solve(const double* A, int lda, int n, const double* rhs,
                                            double* x) {
   const int l = lane_id();
   double y0 = l < n ? rhs[l] : 0.0, y1 = l + 64 < n ? rhs[l + 64] : 0.0;
@@ -148,66 +148,68 @@ __device__ inline void wave_cholesky_solve(const double* A, int lda, int n, cons
 
 constexpr int CBS = 16;   // panel width of the blocked factorisation
 
-__device__ inline double readlane_f64(double v, int lane) {
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// 1/sqrt(x) for x > 0 in FP64: the hardware estimate refined by two Newton
+// steps (within a few ulps).
+__device__ __forceinline__ double rsqrt_f64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * (1.5 - 0.5 * x * y * y);
+  y = y * (1.5 - 0.5 * x * y * y);
+  return y;
+}
+
 // Factorisation of one diagonal block by wave 0 (lane l < kb holds row l,
-// loaded by the caller into Lr), followed by the inverse of the factor.  The
-// factor's rows are written to Ld (LDS, row stride ldd); Linv (LDS, CBS x
-// CBS, row stride CBS + 1) receives L^{-1} (lower, zeros elsewhere).  Lane
-// values are exchanged through LDS (in issue order within the wave).  Pivot
-// problems accumulate BA_W_* bits into bad.
-__device__ inline void wave_factor_invert(double (&Lr)[CBS], int kb, double* Ld, int ldd,
-                                          double* Linv, int& bad) {
+// loaded by the caller into Lr; lanes kb.. hold identity rows), followed by
+// the inverse of the factor.  The factor's rows are written to Ld (row stride
+// ldd), the reciprocals of its diagonal to dinv, and Linv (LDS, CBS x CBS,
+// row stride CBS + 1) receives L^{-1} (lower, zeros elsewhere).  Lane values
+// are exchanged with lane reads; the updates are branch-free (entries above
+// the diagonal hold garbage that is never read).  Pivot problems accumulate
+// BA_W_* bits into bad.
+__device__ __forceinline__ void wave_factor_invert(double (&Lr)[CBS], int kb, double* Ld, int ldd,
+                                          double* Linv, double* dinv, int& bad) {
   const int lane = lane_id();
-  double* col = Linv;   // column exchange buffer until the inverse is written
+  double ilv[CBS];
 #pragma unroll
   for (int kk = 0; kk < CBS; ++kk) {
-    if (kk < kb) {
-      if (lane < CBS) col[lane] = Lr[kk];
-      double piv = col[kk];
-      if (!(piv > 0.0) || !isfinite_d(piv)) {
-        bad |= isfinite_d(piv) ? W_NOT_SPD : W_NONFINITE;
-        piv = 1.0;
-      }
-      const double lkk = sqrt(piv);
-      const double il = 1.0 / lkk;
-      if (lane == kk) Lr[kk] = lkk;
-      else if (lane > kk) Lr[kk] *= il;
-#pragma unroll
-      for (int jj = kk + 1; jj < CBS; ++jj) {
-        if (jj < kb) {
-          const double ljk = col[jj] * il;
-          if (lane >= jj) Lr[jj] -= Lr[kk] * ljk;
-        }
-      }
+    double piv = readlane_f64(Lr[kk], kk);
+    if (!(piv > 0.0) || !isfinite_d(piv)) {
+      bad |= isfinite_d(piv) ? W_NOT_SPD : W_NONFINITE;
+      piv = 1.0;
     }
+    const double il = rsqrt_f64(piv);
+    ilv[kk] = il;
+    Lr[kk] = (lane == kk) ? piv * il : Lr[kk] * il;
+#pragma unroll
+    for (int jj = kk + 1; jj < CBS; ++jj) Lr[jj] -= Lr[kk] * readlane_f64(Lr[kk], jj);
   }
   if (lane < kb) {
 #pragma unroll
     for (int t = 0; t < CBS; ++t)
       if (t <= lane) Ld[lane * ldd + t] = Lr[t];
+    double d = 0.0;
+#pragma unroll
+    for (int t = 0; t < CBS; ++t) d = (t == lane) ? ilv[t] : d;
+    dinv[lane] = d;
   }
   // column `lane` of L^{-1}: X[i][j] = (delta_ij - sum_{k<i} L[i][k] X[k][j]) / L[i][i]
   double Xc[CBS];
 #pragma unroll
   for (int i = 0; i < CBS; ++i) {
-    if (i < kb) {
-      double v = (lane == i) ? 1.0 : 0.0;
+    double v = (lane == i) ? 1.0 : 0.0;
 #pragma unroll
-      for (int k = 0; k < i; ++k) v -= Ld[i * ldd + k] * Xc[k];
-      Xc[i] = (lane <= i) ? v / Ld[i * ldd + i] : 0.0;
-    } else {
-      Xc[i] = 0.0;
-    }
+    for (int k = 0; k < i; ++k) v -= readlane_f64(Lr[k], i) * Xc[k];
+    Xc[i] = (lane <= i) ? v * ilv[i] : 0.0;
   }
   if (lane < CBS) {
 #pragma unroll
-    for (int i = 0; i < CBS; ++i) Linv[i * (CBS + 1) + lane] = Xc[i];
+    for (int i = 0; i < CBS; ++i) Linv[i * (CBS + 1) + lane] = (i < kb) ? Xc[i] : 0.0;
   }
 }
 
@@ -217,7 +219,8 @@ __device__ inline void wave_factor_invert(double (&Lr)[CBS], int kb, double* Ld,
 // given, to a second destination).  Rows are read before they are written by
 // the same wave, so the product may be in place.
 template <typename Src, typename Dst, typename Dst2>
-__device__ inline void panel_trsm_mfma(int m, int kb, const double* Linv, Src rows, Dst dst, Dst2 dst2) {
+__device__ __forceinline__ void panel_trsm_mfma(int m, int kb, const double* Linv, Src rows, Dst dst, Dst2 dst2,
+                                       int* nzb) {
   const int lane = lane_id(), wv = wave_id();
   const int l16 = lane & 15, g = lane >> 4;
   const int nblk = (m + 15) / 16;
@@ -239,6 +242,7 @@ __device__ inline void panel_trsm_mfma(int m, int kb, const double* Linv, Src ro
 #pragma unroll
       for (int h = 0; h < CBS / 16; ++h) acc[h] = mfma16(av[kq], Linv[(16 * h + l16) * (CBS + 1) + k], acc[h]);
     }
+    bool nz = false;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * rb + acc_row(0.0, g, r);
@@ -248,10 +252,16 @@ __device__ inline void panel_trsm_mfma(int m, int kb, const double* Linv, Src ro
           if (16 * h + l16 < kb) {
             dst(row)[16 * h + l16] = acc[h][r];
             dst2(row, 16 * h + l16, acc[h][r]);
+            nz |= acc[h][r] != 0.0;
           }
         }
       }
     }
+    // row blocks whose panel entries are all zero (outside the envelope of
+    // the matrix: frames that share no patch) contribute nothing to the
+    // trailing update, which then skips their tiles
+    const bool any = __any(nz);
+    if (lane == 0) nzb[rb] = any ? 1 : 0;
   }
 }
 
@@ -266,8 +276,9 @@ __device__ inline void panel_trsm_mfma(int m, int kb, const double* Linv, Src ro
 //   * the trailing lower triangle is updated with 16x16x4 FP64 matrix-core
 //     products whose operands are read straight from the matrix.
 // Linv: CBS * (CBS + 1) doubles of LDS.  Pivot problems set BA_W_* bits in *flag.
-__device__ inline void wg_cholesky_lds(double* A, int lda, int n, double* Linv, int* flag) {
+__device__ __forceinline__ void wg_cholesky_lds(double* A, int lda, int n, double* Linv, double* dinv, int* flag) {
   const int lane = lane_id(), wv = wave_id();
+  int* nzb = (int*)(Linv + CBS * (CBS + 1));   // 32 row-block flags
   int bad = 0;
   for (int k0 = 0; k0 < n; k0 += CBS) {
     const int kb = min(CBS, n - k0);
@@ -277,14 +288,14 @@ __device__ inline void wg_cholesky_lds(double* A, int lda, int n, double* Linv, 
       double Lr[CBS];
 #pragma unroll
       for (int t = 0; t < CBS; ++t)
-        Lr[t] = (lane < kb && t <= lane) ? A[(k0 + lane) * lda + k0 + t] : 0.0;
-      wave_factor_invert(Lr, kb, A + k0 * lda + k0, lda, Linv, bad);
+        Lr[t] = (lane < kb && t <= lane) ? A[(k0 + lane) * lda + k0 + t] : (t == lane ? 1.0 : 0.0);
+      wave_factor_invert(Lr, kb, A + k0 * lda + k0, lda, Linv, dinv + k0, bad);
     }
     __syncthreads();
     auto rows = [&](int r) { return (const double*)(A + (r0 + r) * lda + k0); };
     auto dst = [&](int r) { return A + (r0 + r) * lda + k0; };
     auto none = [](int, int, double) {};
-    panel_trsm_mfma(m, kb, Linv, rows, dst, none);
+    panel_trsm_mfma(m, kb, Linv, rows, dst, none, nzb);
     __syncthreads();
     if (m > 1) {
       // kb == CBS here (a shorter panel is the last one, with m == 1)
@@ -295,6 +306,7 @@ __device__ inline void wg_cholesky_lds(double* A, int lda, int n, double* Linv, 
         int ti = 0;
         while (((ti + 1) * (ti + 2)) / 2 <= t) ++ti;
         const int tj = t - (ti * (ti + 1)) / 2;
+        if (!nzb[ti] || !nzb[tj]) continue;
         f64x4 acc;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -323,7 +335,8 @@ __device__ inline void wg_cholesky_lds(double* A, int lda, int n, double* Linv, 
 
 // L^T x = y with L and y (row n) from wg_cholesky_lds; x in LDS.  z: n doubles
 // of LDS scratch.
-__device__ inline void wg_backsolve_lds(const double* A, int lda, int n, double* x, double* z) {
+__device__ __forceinline__ void wg_backsolve_lds(const double* A, int lda, int n, const double* dinv, double* x,
+                                        double* z) {
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   for (int j = tid; j < n; j += WG) z[j] = A[n * lda + j];
   __syncthreads();
@@ -339,7 +352,7 @@ __device__ inline void wg_backsolve_lds(const double* A, int lda, int n, double*
 #pragma unroll
       for (int s2 = CBS - 1; s2 >= 0; --s2) {
         if (s2 < bs) {
-          const double xs = readlane_f64(zz, s2) / readlane_f64(Lc[s2], s2);
+          const double xs = readlane_f64(zz, s2) * dinv[b0 + s2];
           if (lane == s2) zz = xs;
           else if (lane < s2) zz -= Lc[s2] * xs;
         }
@@ -357,7 +370,7 @@ __device__ inline void wg_backsolve_lds(const double* A, int lda, int n, double*
 }
 
 template <typename T>
-__device__ void wg_chol(const Params& P, int w, int iter, char* smem) {
+__device__ __forceinline__ void wg_chol(const Params& P, int w, int iter, char* smem) {
   const WinDesc W = P.win[w];
   const int tid = threadIdx.x;
   int* misc = (int*)smem;
@@ -383,9 +396,10 @@ __device__ void wg_chol(const Params& P, int w, int iter, char* smem) {
       b[i] = -b[i];
     }
     __syncthreads();
-    // colbuf: the inverse diagonal block, then n doubles of solve scratch
-    wg_cholesky_lds(A, lda, n, colbuf, misc + 1);
-    wg_backsolve_lds(A, lda, n, x, colbuf + CBS * (CBS + 1));
+    // colbuf: the inverse diagonal block, 32 row-block flags, the reciprocal
+    // diagonal of L, then n doubles of solve scratch
+    wg_cholesky_lds(A, lda, n, colbuf, colbuf + CBS * (CBS + 1) + 16, misc + 1);
+    wg_backsolve_lds(A, lda, n, colbuf + CBS * (CBS + 1) + 16, x, colbuf + CBS * (CBS + 1) + 16 + NCHOL_MAX);
     __syncthreads();
     if (tid == 0) {
       int bad = misc[1];
@@ -418,7 +432,7 @@ __device__ void wg_chol(const Params& P, int w, int iter, char* smem) {
 // assembly; writes the depth state (position order) or, on the last
 // iteration, depth_out (patch order).
 template <typename T>
-__device__ void wg_backsub(const Params& P, int c, int iter, char* smem, int Rcap) {
+__device__ __forceinline__ void wg_backsub(const Params& P, int c, int iter, char* smem, int Rcap) {
   double* lp = (double*)smem;
   T* rel = (T*)(smem + al16(Rcap * 7 * 8));
   double* dx = (double*)(smem + backsub_dx_offset(Rcap, (int)sizeof(T)));
@@ -520,7 +534,7 @@ __device__ void wg_backsub(const Params& P, int c, int iter, char* smem, int Rca
 }
 
 // Final poses: the last state, or the inputs of a failed window.
-__device__ inline void wg_finalize(const Params& P, int w) {
+__device__ __forceinline__ void wg_finalize(const Params& P, int w) {
   const WinDesc W = P.win[w];
   const int st = P.status[w];
   const double* src = (st != 0 || P.iterations == 0)
