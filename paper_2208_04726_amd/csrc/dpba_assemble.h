@@ -464,6 +464,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
     if (s_lo < s_hi) stage_store<T>(dcur, R, S);
 
     int a = -1, lo = 0, hi = -1, Ra = 0, nz_lo = 0, nz_hi = 0;
+    unsigned tmask = 0;   // this wave's tiles reached by the current source frame
     bool a_free = false;
     for (int s = s_lo; s <= s_hi; ++s) {
       const int an = (s < s_hi) ? (dcur.y >> 8) : -1;
@@ -527,7 +528,9 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
           const int l16 = lane & 15, g = lane >> 4;
 #pragma unroll
           for (int t = 0; t < MAXT; ++t) {
-            if (t < ntl) {
+            // tiles the source frame does not reach hold no products and no
+            // B / v entries of it
+            if (tmask & (1u << t)) {
               const int code = tiles[t_beg + t];
               const int ti = code >> 16, tj = code & 0xffff;
 #pragma unroll
@@ -575,6 +578,18 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
         nz_lo = 6 * (max(lo, lo_free) - lo_free);
         nz_hi = (hi >= lo_free) ? 6 * (hi - lo_free + 1) : 0;
         a_free = a >= nfix;
+        // this wave's tiles that the source frame's outer products reach
+        tmask = 0;
+        for (int t = 0; t < ntl; ++t) {
+          const int code = tiles[t_beg + t];
+          const int ti = code >> 16, tj = code & 0xffff;
+          const bool rows_nz = (16 * ti < nz_hi && 16 * ti + 16 > nz_lo) ||
+                               (16 * ti < Daug && D < 16 * ti + 16);
+          const bool cols_nz = (16 * tj < nz_hi && 16 * tj + 16 > nz_lo) ||
+                               (16 * tj < Daug && D < 16 * tj + 16);
+          if (rows_nz && cols_nz) tmask |= 1u << t;
+        }
+        tmask = __builtin_amdgcn_readfirstlane(tmask);
       }
       const int nsb = dcur.y & 255;
       // prefetch the next sub-batch
@@ -653,14 +668,10 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
         const int nkb = (nsb + 15) >> 4;
 #pragma unroll
         for (int t = 0; t < MAXT; ++t) {
-          if (t < ntl) {
+          if (tmask & (1u << t)) {
             const int code = tiles[t_beg + t];
             const int ti = code >> 16, tj = code & 0xffff;
-            const bool rows_nz = (16 * ti < nz_hi && 16 * ti + 16 > nz_lo) ||
-                                 (16 * ti < Daug && D < 16 * ti + 16);
-            const bool cols_nz = (16 * tj < nz_hi && 16 * tj + 16 > nz_lo) ||
-                                 (16 * tj < Daug && D < 16 * tj + 16);
-            if (rows_nz && cols_nz) {
+            {
               const T* ua = U + (16 * ti + l16) * LDK + 4 * g;
               const T* ub = U + (16 * tj + l16) * LDK + 4 * g;
               for (int kb = 0; kb < nkb; ++kb) {
