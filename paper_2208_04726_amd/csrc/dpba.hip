@@ -221,8 +221,10 @@ template <typename T>
 int set_kernel_attrs() {
   const int lds = 160 * 1024;
   if (hipFuncSetAttribute((const void*)k_assemble<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_assemble<T, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_assemble<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_fused<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_fused<T, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_fused<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_chol<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_chol_big<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
@@ -273,6 +275,15 @@ struct KernelTimer {
   }
 };
 
+// Accumulator tiles per wave: the smallest instantiated count that holds a
+// chunk's lower-triangle tiles in one pass (larger chunks take several passes
+// with 8).
+int maxt_for(int tiles) {
+  if (tiles <= NWAVES * 4) return 4;
+  if (tiles <= NWAVES * 5) return 5;
+  return 8;
+}
+
 struct Plan {
   int W = 0, C = 0, Rcap = 1, nmax = 0, maxt = 4;
   bool fused = false;
@@ -314,7 +325,7 @@ int validate_and_plan(ba_handle* h, const ba_problem* p, Plan& pl) {
       // accumulator tiles per wave: lower-triangle 16x16 tiles of (n+1)^2 over 8 waves
       const int T16 = (n + 1 + 15) / 16;
       const int L = T16 * (T16 + 1) / 2;
-      if (L > NWAVES * 4) pl.maxt = 8;
+      pl.maxt = std::max(pl.maxt, maxt_for(L));
     }
     pl.Rcap = std::max<int>(pl.Rcap, (int)N);
     const double* K = p->intrinsics + 4 * w;
@@ -501,6 +512,7 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
     const int grid = std::min(gW, 4 * h->n_cu);
     KernelTimer kt(h, s, BA_STAGE_FUSED);
     if (pl.maxt == 4) hipLaunchKernelGGL((k_fused<T, 4>), dim3(grid), dim3(WG), lds, s, P, Rcap);
+    else if (pl.maxt == 5) hipLaunchKernelGGL((k_fused<T, 5>), dim3(grid), dim3(WG), lds, s, P, Rcap);
     else hipLaunchKernelGGL((k_fused<T, 8>), dim3(grid), dim3(WG), lds, s, P, Rcap);
     HIPCHK(h, hipGetLastError());
   } else {
@@ -513,6 +525,7 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
       if (gC > 0) {
         KernelTimer kt(h, s, BA_STAGE_ASSEMBLE);
         if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<T, 4>), dim3(gC), dim3(WG), asm_lds, s, P, it, Rcap);
+        else if (pl.maxt == 5) hipLaunchKernelGGL((k_assemble<T, 5>), dim3(gC), dim3(WG), asm_lds, s, P, it, Rcap);
         else hipLaunchKernelGGL((k_assemble<T, 8>), dim3(gC), dim3(WG), asm_lds, s, P, it, Rcap);
       }
       HIPCHK(h, hipGetLastError());
@@ -565,6 +578,7 @@ int launch_backward(ba_handle* h, const ba_problem* p, const Plan& pl, const dou
   // recompute the iterates x_1 .. x_{K-1}
   for (int it = 0; it + 1 < K; ++it) {
     if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<T, 4>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
+    else if (pl.maxt == 5) hipLaunchKernelGGL((k_assemble<T, 5>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
     else hipLaunchKernelGGL((k_assemble<T, 8>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
     hipLaunchKernelGGL(k_chol<T>, dim3(pl.W), dim3(WG), chol_lds, s, P, it);
     hipLaunchKernelGGL(k_backsub<T>, dim3(pl.C), dim3(WG), bs_lds, s, P, it, Rcap);
@@ -576,6 +590,7 @@ int launch_backward(ba_handle* h, const ba_problem* p, const Plan& pl, const dou
   PA.adjoint = 1;
   for (int it = K - 1; it >= 0; --it) {
     if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<T, 4>), dim3(pl.C), dim3(WG), asm_lds, s, PA, it, Rcap);
+    else if (pl.maxt == 5) hipLaunchKernelGGL((k_assemble<T, 5>), dim3(pl.C), dim3(WG), asm_lds, s, PA, it, Rcap);
     else hipLaunchKernelGGL((k_assemble<T, 8>), dim3(pl.C), dim3(WG), asm_lds, s, PA, it, Rcap);
     hipLaunchKernelGGL(k_chol_adj<T>, dim3(pl.W), dim3(WG), chol_adj_lds, s, PA, it);
     hipLaunchKernelGGL(k_edge_adj<T>, dim3(pl.C), dim3(WG), adj_lds, s, PA, it, Rcap);
@@ -766,7 +781,7 @@ int ba_launch(ba_handle* h, void* stream) {
   if (pl.fused) pl.nmax = std::min(NCHOL_MAX, pl.nmax);
   {
     const int T16 = (pl.nmax + 1 + 15) / 16;
-    pl.maxt = T16 * (T16 + 1) / 2 > NWAVES * 4 ? 8 : 4;
+    pl.maxt = maxt_for(T16 * (T16 + 1) / 2);
   }
   const ba_problem* p = &h->prep_problem;
   return h->cfg.precision == BA_PREC_FP32 ? launch_solve<float>(h, p, pl, s)
