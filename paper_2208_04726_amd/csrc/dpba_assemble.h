@@ -470,13 +470,13 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
       const int an = (s < s_hi) ? (dcur.y >> 8) : -1;
       if (an != a && a >= 0) {
         // ---- pair blocks of the finished source frame a
-        __syncthreads();
+        lds_barrier();
         for (int i = tid; i < Ra * TBL; i += WG) {
           T sum = 0;
           for (int x = 0; x < NWAVES * tslots; ++x) sum += tbl[x * Ra * TBL + i];
           tbl[i] = sum;
         }
-        __syncthreads();
+        lds_barrier();
         // G_j = A_j^T Q_j
         for (int i = tid; i < Ra * 36; i += WG) {
           const int jr = i / 36, m = (i % 36) / 6, n = i % 6;
@@ -491,16 +491,21 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
             sum += rj[mm] * Q[sym6(3, n)] + rj[3 + mm] * Q[sym6(4, n)] + rj[6 + mm] * Q[sym6(5, n)];
           G[i] = sum;
         }
-        __syncthreads();
+        lds_barrier();
         // anchor block sum_j A^T Q A and anchor gradient -sum_j A^T V (targets in
         // fixed frames included: J_i = -J_j Ad(T_ji) whatever frame j is)
+        // (42 entries, each a sum over the target frames: 12 interleaved
+        // partial sums per entry, staged in the consumed U buffer, then added
+        // in order)
         T* AQA = G + Ra * 36;
+        constexpr int NP = 12;
         if (a_free) {
-          for (int i = tid; i < 42; i += WG) {
+          if (tid < 42 * NP) {
+            const int i = tid / NP, part = tid % NP;
             T sum = 0;
             if (i < 36) {
               const int m = i / 6, n = i % 6;
-              for (int jr = 0; jr < Ra; ++jr) {
+              for (int jr = part; jr < Ra; jr += NP) {
                 if (lo + jr == a) continue;
                 const T* rj = rel + (lo + jr - f_lo) * RELW;
 #pragma unroll
@@ -508,7 +513,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
               }
             } else {
               const int m = i - 36;
-              for (int jr = 0; jr < Ra; ++jr) {
+              for (int jr = part; jr < Ra; jr += NP) {
                 if (lo + jr == a) continue;
                 const T* rj = rel + (lo + jr - f_lo) * RELW;
                 const T* Q = tbl + jr * TBL;
@@ -516,10 +521,17 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
                 for (int p = 0; p < 6; ++p) sum -= adj_at(rj, p, m) * Q[21 + p];
               }
             }
-            AQA[i] = sum;
+            U[tid] = sum;
+          }
+          lds_barrier();
+          if (tid < 42) {
+            T sum = 0;
+#pragma unroll
+            for (int part = 0; part < NP; ++part) sum += U[tid * NP + part];
+            AQA[tid] = sum;
           }
         }
-        __syncthreads();
+        lds_barrier();
         // Each lane folds this source frame's B / v entries of its tile
         // elements and the staged outer products into its running sums:
         //   (j,j) += Q_j, (a,j) -= A^T Q_j, (a,a) += sum A^T Q A, v_j += V_j,
@@ -564,7 +576,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
             }
           }
         }
-        __syncthreads();
+        lds_barrier();
       }
       if (s == s_hi) break;
       if (an != a) {
@@ -599,7 +611,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
         if (s + 2 < s_hi) dnn = sbd[s + 2];
       }
       for (int i = tid; i < 16 * T16 * LDK; i += WG) U[i] = T(0);
-      __syncthreads();
+      lds_barrier();
 
       // ---- linearise this wave's patches, one lane segment per patch
       T* mytbl = tbl + wv * tslots * Ra * TBL;
@@ -660,7 +672,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
           if (nextra == 2) U[(D + 1) * LDK + slot] = (T)S.pd2[slot] * rs;
         }
       }
-      __syncthreads();
+      lds_barrier();
 
       // ---- matrix-core outer products of the staged rows
       {
@@ -684,7 +696,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
         }
       }
       if (s + 1 < s_hi) stage_store<T>(dnxt, R, S);
-      __syncthreads();
+      lds_barrier();
       dcur = dnxt;
       dnxt = dnn;
     }

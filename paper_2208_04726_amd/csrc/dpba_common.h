@@ -187,6 +187,17 @@ __device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ bool isfinite_d(double x) { return __builtin_isfinite(x); }
 __device__ __forceinline__ bool isfinite_f(float x) { return __builtin_isfinite(x); }
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS (and
+// scalar) operations, not for its global loads, so loads issued ahead (the
+// prefetch of the next sub-batch) stay in flight across it.  Use only where
+// no global memory written before it is read after it by another wave.
+__device__ __forceinline__ void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt, expcnt unconstrained
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Exclusive scan of data[0..n) in place by the whole workgroup; returns the
 // total.  lds must hold WG ints.  All threads must call it.
 __device__ __forceinline__ int wg_exclusive_scan(int32_t* data, int n, int* lds) {

@@ -500,7 +500,7 @@ __device__ __forceinline__ void wg_backsub(const Params& P, int c, int iter, cha
       stage_issue<T>(P, W, w, we, dnxt, iter, nullptr, R);
       if (s + 2 < s_hi) dnn = sbd[s + 2];
     }
-    __syncthreads();
+    lds_barrier();
     const double* dxa = dx + 6 * a;
     for (int ps = 0; ps < npass; ++ps) {
       const int slot_in_wave = ps * segs + sidx;
@@ -526,7 +526,7 @@ __device__ __forceinline__ void wg_backsub(const Params& P, int c, int iter, cha
         else dnext[pos0 + le.slot] = dnew;
       }
     }
-    __syncthreads();
+    lds_barrier();
     if (s + 1 < s_hi) stage_store<T>(dnxt, R, S);
     dcur = dnxt;
     dnxt = dnn;
