@@ -289,8 +289,10 @@ __device__ __forceinline__ void stage_issue(const Params& P, const WinDesc& W, i
     }
   }
   if (tid <= n) {
+    // edge offset of the patch, made relative to the sub-batch when stored
+    // (so the load is not waited for here)
     const int32_t* est = P.estart + W.patch_off + w;
-    R.pe = (tid < n ? est[pos0 + tid] : e1) - e0;
+    R.pe = tid < n ? est[pos0 + tid] : e1;
   }
   if (tid < n) {
     R.pk = P.plist[W.patch_off + pos0 + tid];
@@ -317,7 +319,7 @@ __device__ __forceinline__ void stage_store(int4 d, const StageRegs<T>& R, Stage
       S.w[2 * q + 1] = R.w[2 * r + 1];
     }
   }
-  if (tid <= n) S.pe[tid] = R.pe;
+  if (tid <= n) S.pe[tid] = R.pe - d.z;
   if (tid < n) {
     S.pk[tid] = R.pk;
     S.px[tid] = R.px;
@@ -393,6 +395,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
   const int w = cd.window;
   const WinDesc W = P.win[w];
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  if (tid == 0) *(T*)(misc + 8) = T(0);   // zero slot of the fold's entry lookup
   const int st = wg_bcast_status(P.status, w, misc);
   if (st != 0) {
     if (tid == 0) { P.cstate[2 * c] = 0; P.cstate[2 * c + 1] = 0; }
@@ -536,8 +539,15 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
         // elements and the staged outer products into its running sums:
         //   (j,j) += Q_j, (a,j) -= A^T Q_j, (a,a) += sum A^T Q A, v_j += V_j,
         //   v_a -= sum A^T V, and -= sum_k u_k u_k^T.
+        // The entry is located by selects (an element index into the stage's
+        // LDS, a zero slot for entries the source frame does not touch), so the
+        // lanes do not diverge and a tile's four loads are issued together.
         {
           const int l16 = lane & 15, g = lane >> 4;
+          constexpr int ES = (int)sizeof(T);
+          const int o_tbl = L.tbl / ES, o_G = L.G / ES, o_AQA = o_G + Ra * 36;
+          const int o_zero = (L.misc + 32) / ES;
+          const T* base = (const T*)smem;
 #pragma unroll
           for (int t = 0; t < MAXT; ++t) {
             // tiles the source frame does not reach hold no products and no
@@ -545,32 +555,41 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
             if (tmask & (1u << t)) {
               const int code = tiles[t_beg + t];
               const int ti = code >> 16, tj = code & 0xffff;
+              const int col = 16 * tj + l16;
+              const int cf = col / 6, n = col - 6 * cf, fc = lo_free + cf;
+              const bool cin = fc >= lo && fc <= hi;
+              int idx[4];
+              bool neg[4];
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
-                const int row = 16 * ti + acc_row(T(0), g, r), col = 16 * tj + l16;
-                T val = 0;
-                if (col < D && (row < D ? col <= row : row == D)) {
-                  const int fc = lo_free + col / 6, n = col % 6;
-                  if (row == D) {
-                    if (fc == a) val = a_free ? AQA[36 + n] : T(0);
-                    else if (fc >= lo && fc <= hi) val = tbl[(fc - lo) * TBL + 21 + n];
-                  } else {
-                    const int fr = lo_free + row / 6, m = row % 6;
-                    if (fr == fc) {
-                      if (fr == a) val = a_free ? AQA[m * 6 + n] : T(0);
-                      else if (fr >= lo && fr <= hi) val = tbl[(fr - lo) * TBL + sym6(m, n)];
-                    } else if (fr == a && fc >= lo && fc <= hi) {
-                      val = -G[(fc - lo) * 36 + m * 6 + n];
-                    } else if (fc == a && fr >= lo && fr <= hi) {
-                      val = -G[(fr - lo) * 36 + n * 6 + m];
-                    }
-                  }
-                }
+                const int row = 16 * ti + acc_row(T(0), g, r);
+                const int rf = row / 6, m = row - 6 * rf, fr = lo_free + rf;
+                const bool rin = fr >= lo && fr <= hi;
+                const int mn = min(m, n), mx = max(m, n);
+                const int i_v = fc == a ? o_AQA + 36 + n : (cin ? o_tbl + (fc - lo) * TBL + 21 + n : o_zero);
+                const int i_d = fr == a ? o_AQA + m * 6 + n
+                                        : (rin ? o_tbl + (fr - lo) * TBL + mn * 6 - (mn * (mn - 1)) / 2 + (mx - mn) : o_zero);
+                const bool ga = fr == a && cin, gb = fc == a && rin;
+                const int i_g = ga ? o_G + (fc - lo) * 36 + m * 6 + n : o_G + (fr - lo) * 36 + n * 6 + m;
+                const bool lower = row < D && col <= row;
+                int i = o_zero;
+                i = (row == D && col < D && a_free | (fc != a)) ? i_v : i;
+                i = (lower && fr == fc && (a_free | (fr != a))) ? i_d : i;
+                i = (lower && fr != fc && (ga || gb)) ? i_g : i;
+                idx[r] = i;
+                neg[r] = lower && fr != fc && (ga || gb);
+              }
+              T val[4];
+#pragma unroll
+              for (int r = 0; r < 4; ++r) val[r] = base[idx[r]];
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const T v = neg[r] ? -val[r] : val[r];
                 if constexpr (sizeof(T) == 4) {
-                  sh[t * 4 + r] += (double)val - (double)acc[t][r];
+                  sh[t * 4 + r] += (double)v - (double)acc[t][r];
                   acc[t][r] = T(0);
                 } else {
-                  acc[t][r] -= val;
+                  acc[t][r] -= v;
                 }
               }
             }
