@@ -501,7 +501,7 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
   const int gW = pl.capacity ? h->cfg.max_windows : pl.W;
   const int gC = pl.capacity ? (int)h->cap_chunks : pl.C;
   const int Rcap = pl.Rcap;
-  const int asm_lds = asm_layout(Rcap, (int)sizeof(T)).total;
+  const int asm_lds = asm_layout(Rcap, (int)sizeof(T), pl.maxt).total;
   const int chol_lds = chol_lds_bytes(std::min(pl.nmax, NCHOL_MAX));
   const int big_lds = chol_big_lds_bytes(pl.nmax);
   const int bs_lds = backsub_lds_bytes(Rcap, (int)sizeof(T));
@@ -567,7 +567,7 @@ int launch_backward(ba_handle* h, const ba_problem* p, const Plan& pl, const dou
   int r = upload_descriptors(h, pl, s);
   if (r != BA_OK) return r;
   const int Rcap = pl.Rcap, esz = (int)sizeof(T);
-  const int asm_lds = asm_layout(Rcap, esz).total;
+  const int asm_lds = asm_layout(Rcap, esz, pl.maxt).total;
   const int bs_lds = backsub_lds_bytes(Rcap, esz);
   const int chol_lds = chol_lds_bytes(pl.nmax);
   const int chol_adj_lds = chol_lds + 2 * 8 * pl.nmax + 64;
@@ -902,7 +902,7 @@ int ba_debug_reduced_system(ba_handle* h, const ba_problem* p, int32_t window, d
   else hipLaunchKernelGGL(k_prep<double>, dim3(pl.W), dim3(WG), 0, s, P);
   HIPCHK(h, hipGetLastError());
   if (pl.C > 0) {
-    const int al = asm_layout(pl.Rcap, esz).total;
+    const int al = asm_layout(pl.Rcap, esz, 8).total;
     if (f32) hipLaunchKernelGGL((k_assemble<float, 8>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
     else hipLaunchKernelGGL((k_assemble<double, 8>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
     HIPCHK(h, hipGetLastError());

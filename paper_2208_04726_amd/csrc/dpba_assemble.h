@@ -51,6 +51,20 @@ __device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
 // keeps four consecutive rows per lane group, the f64 product interleaves them.
 __device__ __forceinline__ int acc_row(float, int g, int r) { return 4 * g + r; }
 __device__ __forceinline__ int acc_row(double, int g, int r) { return 4 * r + g; }
+// Slot of the tile element (row, col) in the entry image of the tile pass
+// that starts at lower-triangle tile p0 and holds Lp tiles; -1 outside it.
+__device__ __forceinline__ int img_slot(int row, int col, int p0, int Lp) {
+  const int ti = row >> 4, tj = col >> 4;
+  const int t = ((ti * (ti + 1)) >> 1) + tj - p0;
+  if (t < 0 || t >= Lp) return -1;
+  const int r16 = row & 15;   // FP32 accumulator rows: 4 * (lane / 16) + element
+  return t * 256 + (16 * (r16 >> 2) + (col & 15)) * 4 + (r16 & 3);
+}
+// (m, n), m <= n, of the packed upper-triangle index e of a 6x6 block
+__device__ __forceinline__ void unsym6(int e, int& m, int& n) {
+  m = (e >= 6) + (e >= 11) + (e >= 15) + (e >= 18) + (e >= 20);
+  n = e - (m * 6 - (m * (m - 1)) / 2) + m;
+}
 
 constexpr int SBMAX = 32;       // patches per sub-batch (K block of the Schur product)
 constexpr int SBE = 1024;       // staged edges per sub-batch (SB x lane segment width)
@@ -60,9 +74,19 @@ constexpr int RELW = 25;        // LDS words per relative pose: R(9) t(3) hat(t)
 // LDS layout of the assembly and back-substitution stages, in bytes, for
 // windows of at most Rcap frames.  Shared with the host to size the launch.
 struct AsmLayout {
-  int poses, rel, tbl, G, U, tiles, stage, misc, total;
+  int poses, rel, tbl, G, U, tiles, stage, img, misc, total;
   int Tcap;
 };
+constexpr int LDS_BYTES = 160 * 1024;   // LDS of one compute unit
+// FP32 assembly stages a source frame's B / v entries in an LDS image laid
+// out like the matrix-core accumulators of one tile pass (tile, lane,
+// element), so each lane folds a tile with one 16-byte load.  Elements of
+// the image for windows of at most Tcap tile rows and passes of maxt tiles
+// per wave.
+__host__ __device__ inline int img_elems(int Tcap, int maxt) {
+  const int lt = (Tcap * (Tcap + 1)) / 2, pp = NWAVES * maxt;
+  return 256 * (lt < pp ? lt : pp);
+}
 __host__ __device__ inline int stage_bytes(int esize) {
   return SBE * (4 + 4 * esize) + SBMAX * (4 + 2 * esize + 16) + (SBMAX + 1) * 4;
 }
@@ -82,7 +106,9 @@ __host__ __device__ inline int table_rows(int Rcap, int esize) {
   return a > b ? a : b;
 }
 __host__ __device__ inline int al16(int o) { return (o + 15) & ~15; }
-__host__ __device__ inline AsmLayout asm_layout(int Rcap, int esize) {
+// maxt of 4 or 5 adds the FP32 entry image when the LDS has room for it
+// (img == 0 otherwise).
+__host__ __device__ inline AsmLayout asm_layout(int Rcap, int esize, int maxt = 0) {
   AsmLayout L;
   const int Dcap = 6 * Rcap;
   L.Tcap = (Dcap + 1 + 15) / 16;
@@ -94,6 +120,11 @@ __host__ __device__ inline AsmLayout asm_layout(int Rcap, int esize) {
   L.U = o;     o = al16(o + 16 * L.Tcap * LDK * esize);
   L.tiles = o; o = al16(o + 4 * ((L.Tcap * (L.Tcap + 1)) / 2 + 4));
   L.stage = o; o = al16(o + stage_bytes(esize));
+  L.img = 0;
+  if (esize == 4 && maxt > 0 && maxt <= 5) {   // the 8-tile passes keep the register budget for the gather
+    const int ib = img_elems(L.Tcap, maxt) * esize;
+    if (o + ib + 64 + 255 <= LDS_BYTES) { L.img = o; o = al16(o + ib); }
+  }
   L.misc = o;  o += 64;
   L.total = (o + 255) & ~255;
   return L;
@@ -381,7 +412,7 @@ __device__ __forceinline__ void chunk_range(const Params& P, const WinDesc& W, c
 template <typename T, int MAXT>
 __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, char* smem, int Rcap) {
   typedef typename AccT<T>::type Acc;
-  const AsmLayout L = asm_layout(Rcap, (int)sizeof(T));
+  const AsmLayout L = asm_layout(Rcap, (int)sizeof(T), MAXT);
   double* lp = (double*)(smem + L.poses);
   T* rel = (T*)(smem + L.rel);
   T* tbl = (T*)(smem + L.tbl);
@@ -410,6 +441,12 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
   double* part = P.partial + W.part_off + (int64_t)(c - W.chunk_off) * W.part_stride;
   if (D == 0) return;   // every frame the chunk touches is fixed: nothing to assemble
 
+  // entry image (FP32 only); empty between source frames
+  T* img = (sizeof(T) == 4 && MAXT <= 5 && L.img) ? (T*)(smem + L.img) : nullptr;
+  if (img) {
+    const int ne = img_elems(L.Tcap, MAXT) / 4;
+    for (int i = tid; i < ne; i += WG) ((float4*)img)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   const double* poses = state_poses<T>(P, W, iter);
   for (int i = tid; i < 7 * N; i += WG) lp[i] = poses[i];
   const int32_t* ar = P.arange + 2 * W.frame_off;
@@ -478,6 +515,22 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
           T sum = 0;
           for (int x = 0; x < NWAVES * tslots; ++x) sum += tbl[x * Ra * TBL + i];
           tbl[i] = sum;
+          if (img) {
+            // Q_j into the (j, j) block, V_j into the gradient row
+            const int jr = i / TBL, e = i - jr * TBL, j = lo + jr;
+            if (j != a && j >= lo_free) {
+              const int J6 = 6 * (j - lo_free);
+              int row = D, col = J6 + e - 21;
+              if (e < 21) {
+                int m, n;
+                unsym6(e, m, n);
+                row = J6 + n;
+                col = J6 + m;
+              }
+              const int sl = img_slot(row, col, p0, Lp);
+              if (sl >= 0) img[sl] = sum;
+            }
+          }
         }
         lds_barrier();
         // G_j = A_j^T Q_j
@@ -493,6 +546,15 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
           if (m >= 3)
             sum += rj[mm] * Q[sym6(3, n)] + rj[3 + mm] * Q[sym6(4, n)] + rj[6 + mm] * Q[sym6(5, n)];
           G[i] = sum;
+          if (img && a_free) {
+            // -A^T Q_j into the (a, j) block (its transpose when j > a)
+            const int j = lo + jr;
+            if (j != a && j >= lo_free) {
+              const int A6 = 6 * (a - lo_free), J6 = 6 * (j - lo_free);
+              const int sl = a > j ? img_slot(A6 + m, J6 + n, p0, Lp) : img_slot(J6 + n, A6 + m, p0, Lp);
+              if (sl >= 0) img[sl] = -sum;
+            }
+          }
         }
         lds_barrier();
         // anchor block sum_j A^T Q A and anchor gradient -sum_j A^T V (targets in
@@ -532,6 +594,17 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
 #pragma unroll
             for (int part = 0; part < NP; ++part) sum += U[tid * NP + part];
             AQA[tid] = sum;
+            if (img) {
+              const int A6 = 6 * (a - lo_free);
+              int sl = -1;
+              if (tid < 36) {
+                const int m = tid / 6, n = tid % 6;
+                if (m >= n) sl = img_slot(A6 + m, A6 + n, p0, Lp);
+              } else {
+                sl = img_slot(D, A6 + tid - 36, p0, Lp);
+              }
+              if (sl >= 0) img[sl] = sum;
+            }
           }
         }
         lds_barrier();
@@ -542,7 +615,27 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
         // The entry is located by selects (an element index into the stage's
         // LDS, a zero slot for entries the source frame does not touch), so the
         // lanes do not diverge and a tile's four loads are issued together.
-        {
+        if constexpr (sizeof(T) == 4 && MAXT <= 5) {
+          if (img) {
+            // the image holds the entries at the accumulator positions; the
+            // tiles read are cleared for the next source frame
+#pragma unroll
+            for (int t = 0; t < MAXT; ++t) {
+              if (tmask & (1u << t)) {
+                float4* src = (float4*)img + (t_beg + t - p0) * 64 + lane;
+                const float4 v = *src;
+                *src = make_float4(0.f, 0.f, 0.f, 0.f);
+                const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                  sh[t * 4 + r] += (double)vv[r] - (double)acc[t][r];
+                  acc[t][r] = T(0);
+                }
+              }
+            }
+          }
+        }
+        if (!img) {
           const int l16 = lane & 15, g = lane >> 4;
           constexpr int ES = (int)sizeof(T);
           const int o_tbl = L.tbl / ES, o_G = L.G / ES, o_AQA = o_G + Ra * 36;
