@@ -323,7 +323,7 @@ __device__ __forceinline__ void wg_edge_adj(const Params& P, int c, int it, char
     stage_issue<T>(P, W, w, we, dcur, it, dbar_in, R);
   }
   __syncthreads();
-  if (s_lo < s_hi) stage_store<T>(dcur, R, S);
+  if (s_lo < s_hi) stage_store<T>(dcur, R, S, dbar_in != nullptr);
   int a = -1, lo = 0, hi = -1, Ra = 0;
   for (int s = s_lo; s <= s_hi; ++s) {
     const int an = (s < s_hi) ? (dcur.y >> 8) : -1;
@@ -354,11 +354,10 @@ __device__ __forceinline__ void wg_edge_adj(const Params& P, int c, int it, char
       for (int i = tid; i < NWAVES * 4 * 6; i += WG) gA[i] = 0.0;
     }
     const int nsb = dcur.y & 255, pos0 = dcur.x, e0 = dcur.z;
-    int4 dnn = dnxt;
-    if (s + 1 < s_hi) {
-      stage_issue<T>(P, W, w, we, dnxt, it, dbar_in, R);
-      if (s + 2 < s_hi) dnn = sbd[s + 2];
-    }
+    int dnn = 0;
+    const bool pre = s + 2 < s_hi;
+    if (s + 1 < s_hi) stage_issue<T>(P, W, w, we, dnxt, it, dbar_in, R);
+    if (pre) dnn = desc_prefetch(sbd + s + 2);
     __syncthreads();
     const double* dxa = dx + 6 * a;
     const double* qxa = qx + 6 * a;
@@ -466,9 +465,13 @@ __device__ __forceinline__ void wg_edge_adj(const Params& P, int c, int it, char
       }
     }
     __syncthreads();
-    if (s + 1 < s_hi) stage_store<T>(dnxt, R, S);
+    if (s + 1 < s_hi) stage_store<T>(dnxt, R, S, dbar_in != nullptr);
     dcur = dnxt;
-    dnxt = dnn;
+    {
+      // taken on every path, so no load is in flight into the next iteration
+      const int4 dt = desc_take(dnn);
+      if (pre) dnxt = dt;
+    }
   }
   __syncthreads();
   for (int i = tid; i < 6 * N; i += WG) fc[i] = facc[i];

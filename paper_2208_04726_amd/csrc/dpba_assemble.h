@@ -74,7 +74,7 @@ constexpr int RELW = 25;        // LDS words per relative pose: R(9) t(3) hat(t)
 // LDS layout of the assembly and back-substitution stages, in bytes, for
 // windows of at most Rcap frames.  Shared with the host to size the launch.
 struct AsmLayout {
-  int poses, rel, tbl, G, U, tiles, stage, img, misc, total;
+  int poses, rel, tbl, G, U, tiles, arng, stage, img, misc, total;
   int Tcap;
 };
 constexpr int LDS_BYTES = 160 * 1024;   // LDS of one compute unit
@@ -119,6 +119,7 @@ __host__ __device__ inline AsmLayout asm_layout(int Rcap, int esize, int maxt = 
   L.G = o;     o = al16(o + (Rcap * 36 + 42) * esize);
   L.U = o;     o = al16(o + 16 * L.Tcap * LDK * esize);
   L.tiles = o; o = al16(o + 4 * ((L.Tcap * (L.Tcap + 1)) / 2 + 4));
+  L.arng = o;  o = al16(o + 4 * 2 * RMAX);
   L.stage = o; o = al16(o + stage_bytes(esize));
   L.img = 0;
   if (esize == 4 && maxt > 0 && maxt <= 5) {   // the 8-tile passes keep the register budget for the gather
@@ -319,24 +320,22 @@ __device__ __forceinline__ void stage_issue(const Params& P, const WinDesc& W, i
       R.w[2 * r + 1] = wt[2 * q + 1];
     }
   }
-  if (tid <= n) {
-    // edge offset of the patch, made relative to the sub-batch when stored
-    // (so the load is not waited for here)
-    const int32_t* est = P.estart + W.patch_off + w;
-    R.pe = tid < n ? est[pos0 + tid] : e1;
-  }
+  // (registers the loads land in are not written otherwise: a write would
+  // wait for the loads in flight)
   if (tid < n) {
+    // edge offset of the patch, made relative to the sub-batch when stored
+    R.pe = P.estart[W.patch_off + w + pos0 + tid];
     R.pk = P.plist[W.patch_off + pos0 + tid];
     const T* pxy = (const T*)P.pxy + 2 * (W.patch_off + pos0 + tid);
     R.px = pxy[0];
     R.py = pxy[1];
     R.pd = state_depth(P, W, iter)[pos0 + tid];
-    R.pd2 = extra ? extra[W.patch_off + pos0 + tid] : 0.0;
+    if (extra) R.pd2 = extra[W.patch_off + pos0 + tid];
   }
 }
 
 template <typename T>
-__device__ __forceinline__ void stage_store(int4 d, const StageRegs<T>& R, Stage<T>& S) {
+__device__ __forceinline__ void stage_store(int4 d, const StageRegs<T>& R, Stage<T>& S, bool extra) {
   const int tid = threadIdx.x;
   const int n = d.y & 255, ne = d.w - d.z;
 #pragma unroll
@@ -350,14 +349,15 @@ __device__ __forceinline__ void stage_store(int4 d, const StageRegs<T>& R, Stage
       S.w[2 * q + 1] = R.w[2 * r + 1];
     }
   }
-  if (tid <= n) S.pe[tid] = R.pe - d.z;
   if (tid < n) {
+    S.pe[tid] = R.pe - d.z;
     S.pk[tid] = R.pk;
     S.px[tid] = R.px;
     S.py[tid] = R.py;
     S.pd[tid] = R.pd;
-    S.pd2[tid] = R.pd2;
+    if (extra) S.pd2[tid] = R.pd2;
   }
+  if (tid == n) S.pe[n] = ne;
 }
 
 // One lane's edge of the staged sub-batch: slot `slot` (patch), lane `lseg`
@@ -419,6 +419,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
   T* G = (T*)(smem + L.G);
   T* U = (T*)(smem + L.U);
   int* tiles = (int*)(smem + L.tiles);
+  int* arng = (int*)(smem + L.arng);   // target frame ranges of the chunk's source frames
   int* misc = (int*)(smem + L.misc);
   Stage<T> S(smem + L.stage);
 
@@ -450,6 +451,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
   const double* poses = state_poses<T>(P, W, iter);
   for (int i = tid; i < 7 * N; i += WG) lp[i] = poses[i];
   const int32_t* ar = P.arange + 2 * W.frame_off;
+  for (int i = tid; i < 2 * (cd.a_hi - cd.a_lo); i += WG) arng[i] = ar[2 * cd.a_lo + i];
   const int32_t* sbs = P.sbstart + W.frame_off + w;
   const int4* sbd = P.sbd + W.sb_off;
   const WinEdges we = win_edges(P, W, P.wmeta[4 * w + 1], (int)sizeof(T));
@@ -501,7 +503,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
       stage_issue<T>(P, W, w, we, dcur, iter, dbar_in, R);
     }
     __syncthreads();   // previous pass done with the stage and the poses are in LDS
-    if (s_lo < s_hi) stage_store<T>(dcur, R, S);
+    if (s_lo < s_hi) stage_store<T>(dcur, R, S, dbar_in != nullptr);
 
     int a = -1, lo = 0, hi = -1, Ra = 0, nz_lo = 0, nz_hi = 0;
     unsigned tmask = 0;   // this wave's tiles reached by the current source frame
@@ -694,8 +696,8 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
       if (an != a) {
         // ---- start of source frame an: relative poses, empty pair tables
         a = an;
-        lo = ar[2 * a];
-        hi = ar[2 * a + 1];
+        lo = arng[2 * (a - cd.a_lo)];
+        hi = arng[2 * (a - cd.a_lo) + 1];
         Ra = hi - lo + 1;
         load_relposes<T>(lp, a, lo, hi, f_lo, rel);
         for (int i = tid; i < NWAVES * tslots * Ra * TBL; i += WG) tbl[i] = T(0);
@@ -716,12 +718,11 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
         tmask = __builtin_amdgcn_readfirstlane(tmask);
       }
       const int nsb = dcur.y & 255;
-      // prefetch the next sub-batch
-      int4 dnn = dnxt;
-      if (s + 1 < s_hi) {
-        stage_issue<T>(P, W, w, we, dnxt, iter, dbar_in, R);
-        if (s + 2 < s_hi) dnn = sbd[s + 2];
-      }
+      // prefetch the next sub-batch and the descriptor of the one after
+      int dnn = 0;
+      const bool pre = s + 2 < s_hi;
+      if (s + 1 < s_hi) stage_issue<T>(P, W, w, we, dnxt, iter, dbar_in, R);
+      if (pre) dnn = desc_prefetch(sbd + s + 2);
       for (int i = tid; i < 16 * T16 * LDK; i += WG) U[i] = T(0);
       lds_barrier();
 
@@ -807,10 +808,14 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
           }
         }
       }
-      if (s + 1 < s_hi) stage_store<T>(dnxt, R, S);
+      if (s + 1 < s_hi) stage_store<T>(dnxt, R, S, dbar_in != nullptr);
       lds_barrier();
       dcur = dnxt;
-      dnxt = dnn;
+      {
+      // taken on every path, so no load is in flight into the next iteration
+      const int4 dt = desc_take(dnn);
+      if (pre) dnxt = dt;
+    }
     }
 
     // ---- chunk partial: lower triangle of S and s, FP64

@@ -95,6 +95,16 @@ struct Params {
 // ---------------------------------------------------------------------------
 // wave / workgroup helpers
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+// Sub-batch descriptor prefetch: lane k loads component k % 4, so the load is
+// a per-lane one whose wait falls where the descriptor is taken (lane reads,
+// a loop iteration later), not behind the other loads in flight.
+__device__ __forceinline__ int desc_prefetch(const int4* d) {
+  return ((const int*)d)[lane_id() & 3];
+}
+__device__ __forceinline__ int4 desc_take(int v) {
+  return make_int4(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 1),
+                   __builtin_amdgcn_readlane(v, 2), __builtin_amdgcn_readlane(v, 3));
+}
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Lane exchanges of the segment sums, done in the vector ALU: DPP quad

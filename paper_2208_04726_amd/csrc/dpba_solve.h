@@ -486,7 +486,7 @@ __device__ __forceinline__ void wg_backsub(const Params& P, int c, int iter, cha
   if (s_lo + 1 < s_hi) dnxt = sbd[s_lo + 1];
   stage_issue<T>(P, W, w, we, dcur, iter, nullptr, R);
   __syncthreads();
-  stage_store<T>(dcur, R, S);
+  stage_store<T>(dcur, R, S, false);
   int a = -1;
   double* dnext = state_depth(P, W, iter + 1);
   for (int s = s_lo; s < s_hi; ++s) {
@@ -495,11 +495,10 @@ __device__ __forceinline__ void wg_backsub(const Params& P, int c, int iter, cha
       a = an;
       load_relposes<T>(lp, a, ar[2 * a], ar[2 * a + 1], 0, rel);
     }
-    int4 dnn = dnxt;
-    if (s + 1 < s_hi) {
-      stage_issue<T>(P, W, w, we, dnxt, iter, nullptr, R);
-      if (s + 2 < s_hi) dnn = sbd[s + 2];
-    }
+    int dnn = 0;
+    const bool pre = s + 2 < s_hi;
+    if (s + 1 < s_hi) stage_issue<T>(P, W, w, we, dnxt, iter, nullptr, R);
+    if (pre) dnn = desc_prefetch(sbd + s + 2);
     lds_barrier();
     const double* dxa = dx + 6 * a;
     for (int ps = 0; ps < npass; ++ps) {
@@ -527,9 +526,13 @@ __device__ __forceinline__ void wg_backsub(const Params& P, int c, int iter, cha
       }
     }
     lds_barrier();
-    if (s + 1 < s_hi) stage_store<T>(dnxt, R, S);
+    if (s + 1 < s_hi) stage_store<T>(dnxt, R, S, false);
     dcur = dnxt;
-    dnxt = dnn;
+    {
+      // taken on every path, so no load is in flight into the next iteration
+      const int4 dt = desc_take(dnn);
+      if (pre) dnxt = dt;
+    }
   }
 }
 
