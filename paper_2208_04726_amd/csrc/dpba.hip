@@ -22,7 +22,7 @@ using namespace dpba;
 // kernels
 template <typename T>
 __global__ void __launch_bounds__(WG) k_prep(Params P) {
-  __shared__ int lds[WG + 16 + 2 * RMAX];
+  __shared__ int lds[PREP_LDS_INTS];
   if ((int)blockIdx.x >= P.counts[0]) return;
   wg_prep<T>(P, blockIdx.x, lds);
 }
@@ -508,7 +508,7 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
   if (gW == 0) return BA_OK;
   if (pl.fused && pl.big) return fail(h, BA_E_CAPACITY, "the fused schedule holds at most 21 free frames per window");
   if (pl.fused) {
-    const int lds = std::max(std::max(asm_lds, chol_lds), std::max(bs_lds, (WG + 16 + 2 * RMAX) * 4));
+    const int lds = std::max(std::max(asm_lds, chol_lds), std::max(bs_lds, PREP_LDS_INTS * 4));
     const int grid = std::min(gW, 4 * h->n_cu);
     KernelTimer kt(h, s, BA_STAGE_FUSED);
     if (pl.maxt == 4) hipLaunchKernelGGL((k_fused<T, 4>), dim3(grid), dim3(WG), lds, s, P, Rcap);

@@ -326,7 +326,7 @@ __device__ __forceinline__ void wg_edge_adj(const Params& P, int c, int it, char
   if (s_lo < s_hi) stage_store<T>(dcur, R, S, dbar_in != nullptr);
   int a = -1, lo = 0, hi = -1, Ra = 0;
   for (int s = s_lo; s <= s_hi; ++s) {
-    const int an = (s < s_hi) ? (dcur.y >> 8) : -1;
+    const int an = (s < s_hi) ? ((dcur.y >> 8) & 0xff) : -1;
     if (an != a && a >= 0) {
       // fold this source frame's tables into the per-frame sums, fixed order
       __syncthreads();

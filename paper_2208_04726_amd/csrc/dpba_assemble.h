@@ -490,6 +490,14 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
     const int ntl = t_end - t_beg;
     Acc acc[MAXT];
     double sh[4 * MAXT];
+    // Regular source frames (every patch with the same target-frame sequence)
+    // with one table copy per lane segment: each lane accumulates the
+    // pair-table row of its one target frame, in registers for the whole
+    // source frame in the FP32 passes of at most five tiles per wave
+    constexpr bool kRegTbl = sizeof(T) == 4 && MAXT <= 5;
+    T qacc[kRegTbl ? TBL : 1];
+    int qj = -1;
+    bool regular = false;
 #pragma unroll
     for (int t = 0; t < MAXT; ++t) acc[t] = Acc{T(0), T(0), T(0), T(0)};
 #pragma unroll
@@ -509,9 +517,15 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
     unsigned tmask = 0;   // this wave's tiles reached by the current source frame
     bool a_free = false;
     for (int s = s_lo; s <= s_hi; ++s) {
-      const int an = (s < s_hi) ? (dcur.y >> 8) : -1;
+      const int an = (s < s_hi) ? ((dcur.y >> 8) & 0xff) : -1;
       if (an != a && a >= 0) {
         // ---- pair blocks of the finished source frame a
+        if (kRegTbl && regular && qj >= 0) {
+          // the lane's register row into its segment's table copy
+          T* row = tbl + ((wv * tslots + sidx) * Ra + (qj - lo)) * TBL;
+#pragma unroll
+          for (int q = 0; q < TBL; ++q) row[q] = qacc[q];
+        }
         lds_barrier();
         for (int i = tid; i < Ra * TBL; i += WG) {
           T sum = 0;
@@ -701,6 +715,16 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
         Ra = hi - lo + 1;
         load_relposes<T>(lp, a, lo, hi, f_lo, rel);
         for (int i = tid; i < NWAVES * tslots * Ra * TBL; i += WG) tbl[i] = T(0);
+        // one table copy per lane segment and one target frame per lane: the
+        // rows are summed in the same order in registers (five-tile FP32
+        // passes) or in LDS (otherwise), so the sums do not depend on the
+        // kernel variant a batch selects
+        regular = sizeof(T) == 4 && (dcur.y & SB_REGULAR) && tslots == segs;   // FP32 assembly
+        if constexpr (kRegTbl) {
+#pragma unroll
+          for (int q = 0; q < TBL; ++q) qacc[q] = T(0);
+          qj = -1;
+        }
         nz_lo = 6 * (max(lo, lo_free) - lo_free);
         nz_hi = (hi >= lo_free) ? 6 * (hi - lo_free + 1) : 0;
         a_free = a >= nfix;
@@ -740,9 +764,27 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
                           le.w1, fx, fy, cx, cy, zmin, le.has && (j != a), eo);
         // pair tables Q_aj (21) and V_aj (6); segments of a wave take turns,
         // and duplicate (k, j) edges inside a segment are added one lane at a time
+        bool anydup = false;
+        if (sizeof(T) == 4 && regular) {
+          if (eo.active) {
+            T* racc = qacc;
+            if constexpr (kRegTbl) qj = j;
+            else racc = mytbl + (sidx * Ra + (j - lo)) * TBL;
+            int q = 0;
+#pragma unroll
+            for (int m = 0; m < 6; ++m) {
+              const T a0 = eo.w0 * eo.J0[m], a1 = eo.w1 * eo.J1[m];
+#pragma unroll
+              for (int n = m; n < 6; ++n, ++q) racc[q] = a1 * eo.J1[n] + (a0 * eo.J0[n] + racc[q]);
+            }
+            const T b0 = eo.w0 * eo.r0, b1 = eo.w1 * eo.r1;
+#pragma unroll
+            for (int m = 0; m < 6; ++m) racc[21 + m] = b1 * eo.J1[m] + (b0 * eo.J0[m] + racc[21 + m]);
+          }
+        } else {
         const int jprev = __shfl_up(j, 1, 64);
         const bool dup = eo.active && lseg > 0 && jprev == j;
-        const bool anydup = __any(dup);
+        anydup = __any(dup);
         T* tb = mytbl + ((sidx % tslots) * Ra + (j - lo)) * TBL;
         for (int sgi = 0; sgi < segs; sgi += tslots) {
           for (int ln = 0; ln < (anydup ? SEG : 1); ++ln) {
@@ -758,6 +800,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
                 tb[21 + m] += eo.w0 * eo.r0 * eo.J0[m] + eo.w1 * eo.r1 * eo.J1[m];
             }
           }
+        }
         }
         T red[8] = {eo.cd, eo.wd, eo.Ei[0], eo.Ei[1], eo.Ei[2], eo.Ei[3], eo.Ei[4], eo.Ei[5]};
         seg_sum8(red, SEG);

@@ -28,6 +28,12 @@ namespace dpba {
 // window's largest patch degree: one segment of lanes per patch, at most 1024
 // staged edges per sub-batch.
 constexpr int PU = 8;   // edges per thread in flight in the preparation loops
+// LDS of the preparation pass (ints): scan scratch, flags, per-frame ranges
+// and per-frame regularity flags
+constexpr int PREP_LDS_INTS = WG + 16 + 3 * RMAX;
+// bit of a sub-batch descriptor's .y: every patch of the source frame has the
+// same strictly increasing sequence of target frames
+constexpr int SB_REGULAR = 1 << 16;
 
 __host__ __device__ inline int seg_width(int maxdeg) { return maxdeg <= 16 ? 16 : (maxdeg <= 32 ? 32 : 64); }
 __host__ __device__ inline int sb_width(int seg) { return seg == 64 ? 16 : 32; }
@@ -302,6 +308,28 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
       }
     }
   }
+  // Regular source frames: every patch has the target-frame sequence of the
+  // frame's first patch, strictly increasing.  Lane x of a patch's segment
+  // then meets one target frame for the whole source frame.
+  int* reg = lr + 2 * RMAX;
+  for (int a = tid; a < N; a += WG) reg[a] = 1;
+  __syncthreads();
+  {
+    const int32_t* ej = gathered ? P.gj + W.edge_off : jj;
+    for (int q = tid; q < M; q += WG) {
+      const int a = anc[unsorted_p ? pk[q] : q];
+      const int p0 = acnt[a];
+      const int b = est[q], n = est[q + 1] - b, b0 = est[p0];
+      bool ok = n == est[p0 + 1] - b0;
+      if (q == p0) {
+        for (int x = 1; ok && x < n; ++x) ok = ej[b + x - 1] < ej[b + x];
+      } else {
+        for (int x = 0; ok && x < n; ++x) ok = ej[b + x] == ej[b0 + x];
+      }
+      if (!ok) reg[a] = 0;
+    }
+  }
+  __syncthreads();
   // sub-batches per source frame
   const int maxdeg = flags[3];
   const int SBw = sb_width(seg_width(maxdeg));
@@ -323,7 +351,7 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
     int s = sbs[a];
     for (int q = p0; q < p1; q += SBw, ++s) {
       const int n = min(SBw, p1 - q);
-      sbd[s] = make_int4(q, (a << 8) | n, est[q], est[q + n]);
+      sbd[s] = make_int4(q, (reg[a] ? SB_REGULAR : 0) | (a << 8) | n, est[q], est[q + n]);
     }
   }
   __syncthreads();

@@ -490,7 +490,7 @@ __device__ __forceinline__ void wg_backsub(const Params& P, int c, int iter, cha
   int a = -1;
   double* dnext = state_depth(P, W, iter + 1);
   for (int s = s_lo; s < s_hi; ++s) {
-    const int an = dcur.y >> 8, nsb = dcur.y & 255, pos0 = dcur.x;
+    const int an = (dcur.y >> 8) & 0xff, nsb = dcur.y & 255, pos0 = dcur.x;
     if (an != a) {
       a = an;
       load_relposes<T>(lp, a, ar[2 * a], ar[2 * a + 1], 0, rel);

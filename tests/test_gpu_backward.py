@@ -61,9 +61,12 @@ def test_vjp_method_scale_matches_oracle(precision, tol):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_translation_loss_grad_method_scale(precision):
     """End to end through BAFunction: L = sum of squared camera-centre errors.
-    FP32: the forward state differs from FP64 by ~2e-5 m while the centre
-    errors are ~1e-3 m, so L and its cotangent carry a few-percent relative
-    error before the adjoint runs; FP64 matches to rounding."""
+    FP64 matches the oracle to rounding.  FP32: the forward state differs from
+    the FP64 one by ~2e-5 m while the centre errors are ~4e-3 m, so L and the
+    cotangent reaching the solve differ from the FP64 ones by a few percent.
+    L is held to the bound that state difference implies, and the gradient to
+    the oracle's vector-Jacobian product of the cotangent the solve received
+    (the adjoint's own precision, as in the fixed-cotangent test)."""
     need_gpu()
     from paper_2208_04726_amd.solver import BAFunction, Solver, make_batch, capacities_for
     w = synth.method_scale_window(2)
@@ -73,6 +76,12 @@ def test_translation_loss_grad_method_scale(precision):
     tg = b.targets.clone().requires_grad_(True)
     wt = b.weights.clone().requires_grad_(True)
     poses, depth = BAFunction.apply(tg, wt, s, b)
+    seen = {}
+
+    def keep(g):
+        seen["gp"] = g.detach().double().cpu().numpy()
+
+    poses.register_hook(keep)
     q = poses[:, 3:]
     x, y, z, qw = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
     Rm = torch.stack([
@@ -88,9 +97,27 @@ def test_translation_loss_grad_method_scale(precision):
     gwt = wt.grad.double().cpu().numpy()
     eg, ew = rel_err(gy, gy_ref), rel_err(gwt, gw_ref)
     print(precision, "loss", float(L), L_ref, "rel err targets", eg, "weights", ew)
-    tol = 1e-8 if precision == "fp64" else 5e-2
-    assert abs(float(L) - L_ref) < tol * L_ref
-    assert eg < tol and ew < tol
+    if precision == "fp64":
+        assert abs(float(L) - L_ref) < 1e-8 * L_ref
+        assert eg < 1e-8 and ew < 1e-8
+        return
+    # L = |e + dc|^2 with e the oracle's centre errors and dc the difference of
+    # the FP32 centres from the oracle's: |L - L_ref| <= 2 |e| |dc| + |dc|^2
+    pr, _ = O.solve(w)
+    nf = w.n_fixed
+    c_ref = O.camera_centres(torch.as_tensor(pr)).numpy()[nf:]
+    e = c_ref - synth.camera_centres(w.poses_gt)[nf:]
+    dc = np.linalg.norm(c.detach().double().cpu().numpy()[nf:] - c_ref)
+    bound = 2.0 * np.linalg.norm(e) * dc + dc * dc
+    print("fp32 |L - L_ref|", abs(float(L) - L_ref), "bound", bound)
+    assert abs(float(L) - L_ref) <= 1.01 * bound + 1e-12 * L_ref
+    gy2, gw2 = O.cotangent_grad(w, seen["gp"], np.zeros(w.n_patches))
+    e2, w2 = rel_err(gy, gy2), rel_err(gwt, gw2)
+    print("fp32 gradient vs oracle VJP of the received cotangent: targets", e2, "weights", w2)
+    # the weight gradient carries the residuals at the linearisation points,
+    # which the ~2e-5 m state difference moves by ~f * 2e-5 / Z ~ 3e-3 px
+    # against ~1 px of noise; the target gradient does not
+    assert e2 < 1e-3 and w2 < 5e-3
 
 
 def test_vjp_fp64_subwindow_vs_central_differences():
