@@ -28,9 +28,10 @@ namespace dpba {
 // window's largest patch degree: one segment of lanes per patch, at most 1024
 // staged edges per sub-batch.
 constexpr int PU = 8;   // edges per thread in flight in the preparation loops
-// LDS of the preparation pass (ints): scan scratch, flags, per-frame ranges
-// and per-frame regularity flags
-constexpr int PREP_LDS_INTS = WG + 16 + 3 * RMAX;
+// LDS of the preparation pass (ints): scan scratch, flags, per-frame ranges,
+// and per frame a regularity flag and the extremes of its patches' first and
+// last target frames
+constexpr int PREP_LDS_INTS = WG + 16 + 7 * RMAX;
 // bit of a sub-batch descriptor's .y: every patch of the source frame has the
 // same strictly increasing sequence of target frames
 constexpr int SB_REGULAR = 1 << 16;
@@ -67,16 +68,27 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
   const int32_t* kk = P.kk + W.edge_off;
   const int32_t* jj = P.jj + W.edge_off;
   // lds: [0, WG) scan scratch; flags at WG: [0] bad index, [1] edges unsorted,
-  // [2] patches unsorted, [3] max degree, [4] non-finite; per-frame range at WG+16
+  // [2] patches unsorted, [3] max degree, [4] non-finite, [5] duplicate edge;
+  // per-frame range at WG+16, then per frame: regular, min / max first target
+  // frame, min / max last target frame
   int* flags = lds + WG;
   int* lr = lds + WG + 16;   // [2 * RMAX]
+  int* rg = lr + 2 * RMAX;   // [5 * RMAX]
 
   if (tid < 16) flags[tid] = 0;
-  for (int a = tid; a < N; a += WG) { lr[2 * a] = a; lr[2 * a + 1] = a; }
+  for (int a = tid; a < N; a += WG) {
+    lr[2 * a] = a;
+    lr[2 * a + 1] = a;
+    rg[a] = 1;
+    rg[a + RMAX] = 1 << 30;
+    rg[a + 2 * RMAX] = -1;
+    rg[a + 3 * RMAX] = 1 << 30;
+    rg[a + 4 * RMAX] = -1;
+  }
   __syncthreads();
 
   // ---- validation and order checks (coalesced, no atomics on the data path)
-  bool bad = false, uns_e = false, uns_p = false, nonfin = false;
+  bool bad = false, uns_e = false, uns_p = false, nonfin = false, dup_e = false;
   for (int a = tid; a < N; a += WG) {
     const double* p = P.poses_in + 7 * (W.frame_off + a);
     for (int m = 0; m < 7; ++m) nonfin |= !isfinite_d(p[m]);
@@ -122,6 +134,7 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
       if (e0 + u * WG < E) {
         bad |= (k[u] < 0 || k[u] >= M || j[u] < 0 || j[u] >= N);
         uns_e |= (kp[u] > k[u] || (kp[u] == k[u] && jp[u] > j[u]));
+        dup_e |= kp[u] == k[u] && jp[u] == j[u];
       }
     }
   }
@@ -129,6 +142,7 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
   if (__any(uns_e) && lane_id() == 0) atomicOr(&flags[1], 1);
   if (__any(uns_p) && lane_id() == 0) atomicOr(&flags[2], 1);
   if (__any(nonfin) && lane_id() == 0) atomicOr(&flags[4], 1);
+  if (__any(dup_e) && lane_id() == 0) atomicOr(&flags[5], 1);   // meaningful for sorted edges
   __syncthreads();
   if (flags[0]) {
     if (tid == 0) {
@@ -204,6 +218,9 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
         }
         csr[b + y + 1] = e;
       }
+      bool dup = false;
+      for (int x = 1; x < n; ++x) dup |= jj[csr[b + x]] == jj[csr[b + x - 1]];
+      if (dup) flags[5] = 1;
     }
   }
 
@@ -281,7 +298,14 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
         if (n[u] > 0) {
           atomicMin(&lr[2 * a[u]], j0[u]);
           atomicMax(&lr[2 * a[u] + 1], j1[u]);
+          atomicMin(&rg[a[u] + RMAX], j0[u]);
+          atomicMax(&rg[a[u] + 2 * RMAX], j0[u]);
+          atomicMin(&rg[a[u] + 3 * RMAX], j1[u]);
+          atomicMax(&rg[a[u] + 4 * RMAX], j1[u]);
         }
+        // sorted targets fill [j0, j1] exactly when there are j1 - j0 + 1
+        // of them and none repeats
+        if (n[u] == 0 || n[u] != j1[u] - j0[u] + 1) rg[a[u]] = 0;
       }
     }
   }
@@ -308,26 +332,14 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
       }
     }
   }
-  // Regular source frames: every patch has the target-frame sequence of the
-  // frame's first patch, strictly increasing.  Lane x of a patch's segment
-  // then meets one target frame for the whole source frame.
-  int* reg = lr + 2 * RMAX;
-  for (int a = tid; a < N; a += WG) reg[a] = 1;
-  __syncthreads();
+  // Regular source frames: every patch has the same strictly increasing
+  // target-frame sequence (contiguous, unique, with the same first and last
+  // frame).  Lane x of a patch's segment then meets one target frame for the
+  // whole source frame.
   {
-    const int32_t* ej = gathered ? P.gj + W.edge_off : jj;
-    for (int q = tid; q < M; q += WG) {
-      const int a = anc[unsorted_p ? pk[q] : q];
-      const int p0 = acnt[a];
-      const int b = est[q], n = est[q + 1] - b, b0 = est[p0];
-      bool ok = n == est[p0 + 1] - b0;
-      if (q == p0) {
-        for (int x = 1; ok && x < n; ++x) ok = ej[b + x - 1] < ej[b + x];
-      } else {
-        for (int x = 0; ok && x < n; ++x) ok = ej[b + x] == ej[b0 + x];
-      }
-      if (!ok) reg[a] = 0;
-    }
+    int* reg = lr + 2 * RMAX;
+    for (int a = tid; a < N; a += WG)
+      reg[a] = !flags[5] && reg[a] && reg[a + RMAX] == reg[a + 2 * RMAX] && reg[a + 3 * RMAX] == reg[a + 4 * RMAX];
   }
   __syncthreads();
   // sub-batches per source frame
@@ -351,7 +363,7 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
     int s = sbs[a];
     for (int q = p0; q < p1; q += SBw, ++s) {
       const int n = min(SBw, p1 - q);
-      sbd[s] = make_int4(q, (reg[a] ? SB_REGULAR : 0) | (a << 8) | n, est[q], est[q + n]);
+      sbd[s] = make_int4(q, (lr[2 * RMAX + a] ? SB_REGULAR : 0) | (a << 8) | n, est[q], est[q + n]);
     }
   }
   __syncthreads();
