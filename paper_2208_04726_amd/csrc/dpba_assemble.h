@@ -520,8 +520,26 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
       const int an = (s < s_hi) ? ((dcur.y >> 8) & 0xff) : -1;
       if (an != a && a >= 0) {
         // ---- pair blocks of the finished source frame a
-        if (kRegTbl && regular && qj >= 0) {
-          // the lane's register row into its segment's table copy
+        // regular frames with two segments per wave first add the segments'
+        // rows (in registers or in LDS, the same sums), then the waves' copies
+        // are added; otherwise every copy is added
+        const int cstride = (regular && tslots == 2) ? 2 : 1;
+        if (regular && tslots == 2) {
+          if constexpr (kRegTbl) {
+#pragma unroll
+            for (int q = 0; q < TBL; ++q) qacc[q] = swap_add<32>(qacc[q]);
+            qj = max(qj, __shfl_xor(qj, 32, 64));
+            if (sidx == 0 && qj >= 0) {
+              T* row = tbl + (wv * 2 * Ra + (qj - lo)) * TBL;
+#pragma unroll
+              for (int q = 0; q < TBL; ++q) row[q] = qacc[q];
+            }
+          } else {
+            T* c0 = tbl + wv * 2 * Ra * TBL;
+            for (int i = lane; i < Ra * TBL; i += 64) c0[i] = c0[i] + c0[Ra * TBL + i];
+          }
+        } else if (kRegTbl && regular && qj >= 0) {
+          // the lane's register row into its wave's table copy
           T* row = tbl + ((wv * tslots + sidx) * Ra + (qj - lo)) * TBL;
 #pragma unroll
           for (int q = 0; q < TBL; ++q) row[q] = qacc[q];
@@ -529,7 +547,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
         lds_barrier();
         for (int i = tid; i < Ra * TBL; i += WG) {
           T sum = 0;
-          for (int x = 0; x < NWAVES * tslots; ++x) sum += tbl[x * Ra * TBL + i];
+          for (int x = 0; x < NWAVES * tslots; x += cstride) sum += tbl[x * Ra * TBL + i];
           tbl[i] = sum;
           if (img) {
             // Q_j into the (j, j) block, V_j into the gradient row
@@ -747,7 +765,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
       const bool pre = s + 2 < s_hi;
       if (s + 1 < s_hi) stage_issue<T>(P, W, w, we, dnxt, iter, dbar_in, R);
       if (pre) dnn = desc_prefetch(sbd + s + 2);
-      for (int i = tid; i < 16 * T16 * LDK; i += WG) U[i] = T(0);
+      for (int i = tid; i < (16 * T16 * LDK * (int)sizeof(T)) / 16; i += WG) ((float4*)U)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
       lds_barrier();
 
       // ---- linearise this wave's patches, one lane segment per patch
