@@ -280,18 +280,21 @@ __device__ __forceinline__ void wg_cholesky_lds(double* A, int lda, int n, doubl
   const int lane = lane_id(), wv = wave_id();
   int* nzb = (int*)(Linv + CBS * (CBS + 1));   // 32 row-block flags
   int bad = 0;
+  // factor and invert the diagonal block at k0 (wave 0)
+  auto factor = [&](int k0) {
+    const int kb = min(CBS, n - k0);
+    double Lr[CBS];
+#pragma unroll
+    for (int t = 0; t < CBS; ++t)
+      Lr[t] = (lane < kb && t <= lane) ? A[(k0 + lane) * lda + k0 + t] : (t == lane ? 1.0 : 0.0);
+    wave_factor_invert(Lr, kb, A + k0 * lda + k0, lda, Linv, dinv + k0, bad);
+  };
+  if (wv == 0) factor(0);
+  __syncthreads();
   for (int k0 = 0; k0 < n; k0 += CBS) {
     const int kb = min(CBS, n - k0);
     const int r0 = k0 + kb;
     const int m = n + 1 - r0;
-    if (wv == 0) {
-      double Lr[CBS];
-#pragma unroll
-      for (int t = 0; t < CBS; ++t)
-        Lr[t] = (lane < kb && t <= lane) ? A[(k0 + lane) * lda + k0 + t] : (t == lane ? 1.0 : 0.0);
-      wave_factor_invert(Lr, kb, A + k0 * lda + k0, lda, Linv, dinv + k0, bad);
-    }
-    __syncthreads();
     auto rows = [&](int r) { return (const double*)(A + (r0 + r) * lda + k0); };
     auto dst = [&](int r) { return A + (r0 + r) * lda + k0; };
     auto none = [](int, int, double) {};
@@ -302,11 +305,11 @@ __device__ __forceinline__ void wg_cholesky_lds(double* A, int lda, int n, doubl
       const int T = (m + 15) / 16;
       const int ntile = T * (T + 1) / 2;
       const int l16 = lane & 15, g = lane >> 4;
-      for (int t = wv; t < ntile; t += NWAVES) {
+      auto update = [&](int t) {
         int ti = 0;
         while (((ti + 1) * (ti + 2)) / 2 <= t) ++ti;
         const int tj = t - (ti * (ti + 1)) / 2;
-        if (!nzb[ti] || !nzb[tj]) continue;
+        if (!nzb[ti] || !nzb[tj]) return;
         f64x4 acc;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -325,6 +328,15 @@ __device__ __forceinline__ void wg_cholesky_lds(double* A, int lda, int n, doubl
           const int row = 16 * ti + acc_row(0.0, g, r), col = 16 * tj + l16;
           if (row < m && col <= row && r0 + col < n) A[(r0 + row) * lda + r0 + col] = acc[r];
         }
+      };
+      // Look-ahead: wave 0 updates the leading tile, which holds the next
+      // diagonal block, and factors that block while the other waves update
+      // the rest of the trailing matrix.
+      if (wv == 0) {
+        update(0);
+        if (r0 < n) factor(r0);
+      } else {
+        for (int t = wv; t < ntile; t += NWAVES - 1) update(t);
       }
     }
     __syncthreads();
