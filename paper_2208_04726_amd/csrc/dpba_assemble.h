@@ -137,8 +137,10 @@ __host__ __device__ inline int backsub_dx_offset(int Rcap, int esize) {
 __host__ __device__ inline int backsub_stage_offset(int Rcap, int esize) {
   return al16(backsub_dx_offset(Rcap, esize) + Rcap * 6 * 8);
 }
+// then 64 bytes of flags and the target frame ranges of the chunk's source
+// frames (2 * RMAX ints)
 __host__ __device__ inline int backsub_lds_bytes(int Rcap, int esize) {
-  return backsub_stage_offset(Rcap, esize) + stage_bytes(esize) + 64;
+  return backsub_stage_offset(Rcap, esize) + stage_bytes(esize) + 64 + 8 * RMAX;
 }
 
 // packed index of (m, n), m <= n, in the 21-entry upper triangle of a 6x6

@@ -479,6 +479,8 @@ __device__ __forceinline__ void wg_backsub(const Params& P, int c, int iter, cha
   for (int i = tid; i < 7 * N; i += WG) lp[i] = poses[i];
   for (int i = tid; i < 6 * N; i += WG) dx[i] = P.dxi[6 * W.frame_off + i];
   const int32_t* ar = P.arange + 2 * W.frame_off;
+  int* arng = misc + 16;   // target frame ranges of the chunk's source frames
+  for (int i = tid; i < 2 * (cd.a_hi - cd.a_lo); i += WG) arng[i] = ar[2 * cd.a_lo + i];
   const int32_t* sbs = P.sbstart + W.frame_off + w;
   const int4* sbd = P.sbd + W.sb_off;
   const WinEdges we = win_edges(P, W, P.wmeta[4 * w + 1], (int)sizeof(T));
@@ -505,7 +507,7 @@ __device__ __forceinline__ void wg_backsub(const Params& P, int c, int iter, cha
     const int an = (dcur.y >> 8) & 0xff, nsb = dcur.y & 255, pos0 = dcur.x;
     if (an != a) {
       a = an;
-      load_relposes<T>(lp, a, ar[2 * a], ar[2 * a + 1], 0, rel);
+      load_relposes<T>(lp, a, arng[2 * (a - cd.a_lo)], arng[2 * (a - cd.a_lo) + 1], 0, rel);
     }
     int dnn = 0;
     const bool pre = s + 2 < s_hi;
