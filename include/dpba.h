@@ -183,9 +183,12 @@ enum {
   BA_STAGE_COUNT = 6
 };
 
-/* Measurement aid: with timing enabled, every kernel that ba_solve or
- * ba_launch enqueues (not while the stream is being captured) is bracketed by
- * a pair of HIP events on its stream.  ba_kernel_times waits for the
+#define BA_TIMING_ALL ((1 << BA_STAGE_COUNT) - 1)
+
+/* Measurement aid: `enable` is a mask of stages (bit s for BA_STAGE s,
+ * BA_TIMING_ALL for all, 0 to stop).  Every kernel of a timed stage that
+ * ba_solve or ba_launch enqueues (not while the stream is being captured) is
+ * bracketed by a pair of HIP events on its stream.  ba_kernel_times waits for the
  * bracketed launches, writes per stage the summed kernel time in ms
  * (ms_out[BA_STAGE_COUNT]) and the number of launches
  * (launches_out[BA_STAGE_COUNT]) since the previous ba_kernel_times, and

@@ -197,7 +197,7 @@ struct ba_handle {
   double *dxi = nullptr, *pose_buf = nullptr, *depth_buf = nullptr;
   // per-kernel timing (ba_set_timing): event pairs around each launch
   struct TimedLaunch { int stage; hipEvent_t a, b; };
-  bool timing = false;
+  int timing = 0;   // mask of timed stages
   std::vector<hipEvent_t> ev_pool;
   std::vector<TimedLaunch> timed;
   std::string err;
@@ -254,7 +254,7 @@ struct KernelTimer {
   int stage;
   hipEvent_t a = nullptr;
   KernelTimer(ba_handle* h_, hipStream_t s_, int stage_) : h(h_), s(s_), stage(stage_) {
-    if (!h->timing) return;
+    if (!(h->timing & (1 << stage))) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     a = take_event(h);
@@ -790,7 +790,7 @@ int ba_launch(ba_handle* h, void* stream) {
 
 int ba_set_timing(ba_handle* h, int32_t enable) {
   if (!h) return BA_E_INVAL;
-  h->timing = enable != 0;
+  h->timing = enable & BA_TIMING_ALL;
   return BA_OK;
 }
 

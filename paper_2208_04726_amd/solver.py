@@ -174,9 +174,18 @@ class Solver:
         last prepared problem."""
         self._check(self.lib.ba_launch(self.h, ctypes.c_void_p(stream.cuda_stream)))
 
-    def set_timing(self, enable: bool = True):
-        """Bracket every kernel launch with events (ba_set_timing)."""
-        self._check(self.lib.ba_set_timing(self.h, 1 if enable else 0))
+    def set_timing(self, enable: bool = True, stages=None):
+        """Bracket the kernel launches of `stages` (names from native.STAGES;
+        all when None) with events (ba_set_timing)."""
+        if not enable:
+            mask = 0
+        elif stages is None:
+            mask = (1 << len(native.STAGES)) - 1
+        else:
+            mask = 0
+            for st in stages:
+                mask |= 1 << native.STAGES.index(st)
+        self._check(self.lib.ba_set_timing(self.h, mask))
 
     def kernel_times(self):
         """{stage: (total ms, launches)} since the previous call (waits for them)."""
