@@ -139,8 +139,12 @@ __host__ __device__ inline int backsub_stage_offset(int Rcap, int esize) {
 }
 // then 64 bytes of flags and the target frame ranges of the chunk's source
 // frames (2 * RMAX ints)
+// and the per-target-frame vectors dx_j - Ad(T_ja) dx_a (6 doubles per frame)
+__host__ __device__ inline int backsub_delta_offset(int Rcap, int esize) {
+  return al16(backsub_stage_offset(Rcap, esize) + stage_bytes(esize) + 64 + 8 * RMAX);
+}
 __host__ __device__ inline int backsub_lds_bytes(int Rcap, int esize) {
-  return backsub_stage_offset(Rcap, esize) + stage_bytes(esize) + 64 + 8 * RMAX;
+  return backsub_delta_offset(Rcap, esize) + Rcap * 6 * 8;
 }
 
 // packed index of (m, n), m <= n, in the 21-entry upper triangle of a 6x6
@@ -162,7 +166,7 @@ struct EdgeOut {
 };
 
 // Linearise one edge.  rel: R (9), t (3), hat(t)R (9) of T_ji in LDS.
-template <typename T>
+template <typename T, bool kEi = true>
 __device__ __forceinline__ void linearize_edge(const T* rel, T xb, T yb, T d, T tx, T ty, T w0,
                                       T w1, T fx, T fy, T cx, T cy, T zmin, bool valid,
                                       EdgeOut<T>& o) {
@@ -191,11 +195,13 @@ __device__ __forceinline__ void linearize_edge(const T* rel, T xb, T yb, T d, T 
 #pragma unroll
   for (int m = 0; m < 6; ++m) o.Ej[m] = g0 * o.J0[m] + g1 * o.J1[m];
   // Ei = -Ad^T Ej with Ad^T = [[R^T, 0], [(hat(t)R)^T, R^T]]
+  if constexpr (kEi) {
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
     o.Ei[m] = -(rel[m] * o.Ej[0] + rel[3 + m] * o.Ej[1] + rel[6 + m] * o.Ej[2]);
     o.Ei[3 + m] = -(rel[12 + m] * o.Ej[0] + rel[15 + m] * o.Ej[1] + rel[18 + m] * o.Ej[2] +
                     rel[m] * o.Ej[3] + rel[3 + m] * o.Ej[4] + rel[6 + m] * o.Ej[5]);
+  }
   }
 }
 

@@ -448,6 +448,7 @@ __device__ __forceinline__ void wg_backsub(const Params& P, int c, int iter, cha
   double* lp = (double*)smem;
   T* rel = (T*)(smem + al16(Rcap * 7 * 8));
   double* dx = (double*)(smem + backsub_dx_offset(Rcap, (int)sizeof(T)));
+  double* dl = (double*)(smem + backsub_delta_offset(Rcap, (int)sizeof(T)));
   const int o = backsub_stage_offset(Rcap, (int)sizeof(T));
   Stage<T> S(smem + o);
   int* misc = (int*)(smem + o + stage_bytes((int)sizeof(T)));
@@ -507,26 +508,44 @@ __device__ __forceinline__ void wg_backsub(const Params& P, int c, int iter, cha
     const int an = (dcur.y >> 8) & 0xff, nsb = dcur.y & 255, pos0 = dcur.x;
     if (an != a) {
       a = an;
-      load_relposes<T>(lp, a, arng[2 * (a - cd.a_lo)], arng[2 * (a - cd.a_lo) + 1], 0, rel);
+      const int lo = arng[2 * (a - cd.a_lo)], hi = arng[2 * (a - cd.a_lo) + 1];
+      load_relposes<T>(lp, a, lo, hi, 0, rel);
+      // E_ik^T dx_a = -sum_j E_jk^T Ad(T_ja) dx_a: per target frame the
+      // vector dx_j - Ad(T_ja) dx_a, so an edge adds E_jk^T (dx_j - Ad dx_a)
+      for (int j = lo + tid; j <= hi; j += WG) {
+        double R[9], t[3];
+        relative_pose(lp + 7 * a, lp + 7 * j, R, t);
+        const double* xa = dx + 6 * a;
+        double Rp[3], Rr[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          Rr[r] = R[3 * r] * xa[0] + R[3 * r + 1] * xa[1] + R[3 * r + 2] * xa[2];
+          Rp[r] = R[3 * r] * xa[3] + R[3 * r + 1] * xa[4] + R[3 * r + 2] * xa[5];
+        }
+        // Ad (rho, phi) = (R rho + t x (R phi), R phi)
+        const double ad[6] = {Rr[0] + t[1] * Rp[2] - t[2] * Rp[1], Rr[1] + t[2] * Rp[0] - t[0] * Rp[2],
+                              Rr[2] + t[0] * Rp[1] - t[1] * Rp[0], Rp[0], Rp[1], Rp[2]};
+#pragma unroll
+        for (int m = 0; m < 6; ++m) dl[6 * j + m] = dx[6 * j + m] - ad[m];
+      }
     }
     int dnn = 0;
     const bool pre = s + 2 < s_hi;
     if (s + 1 < s_hi) stage_issue<T>(P, W, w, we, dnxt, iter, nullptr, R);
     if (pre) dnn = desc_prefetch(sbd + s + 2);
     lds_barrier();
-    const double* dxa = dx + 6 * a;
     for (int ps = 0; ps < npass; ++ps) {
       const int slot_in_wave = ps * segs + sidx;
       const LaneEdge<T> le = lane_edge<T>(S, wv * spw + slot_in_wave, slot_in_wave < spw, nsb, lseg, a);
       EdgeOut<T> eo;
       const int j = le.j;
-      linearize_edge<T>(rel + j * RELW, le.xb, le.yb, (T)le.d, le.t0, le.t1, le.w0, le.w1, fx,
-                        fy, cx, cy, zmin, le.has && (j != a), eo);
+      linearize_edge<T, false>(rel + j * RELW, le.xb, le.yb, (T)le.d, le.t0, le.t1, le.w0, le.w1, fx,
+                               fy, cx, cy, zmin, le.has && (j != a), eo);
       double t = 0.0;
       if (eo.active) {
-        const double* dxj = dx + 6 * j;
+        const double* dj = dl + 6 * j;
 #pragma unroll
-        for (int m = 0; m < 6; ++m) t += (double)eo.Ej[m] * dxj[m] + (double)eo.Ei[m] * dxa[m];
+        for (int m = 0; m < 6; ++m) t += (double)eo.Ej[m] * dj[m];
       }
       T red[2] = {eo.cd, eo.wd};
       seg_sum_n<2>(red, SEG);
