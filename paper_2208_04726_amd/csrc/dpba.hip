@@ -62,10 +62,11 @@ __global__ void __launch_bounds__(WG) k_gather_big(Params P, int tiles) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(WG) k_backsub(Params P, int iter, int Rcap) {
+__global__ void __launch_bounds__(WG) k_backsub(Params P, int iter, int Rcap, int nparts) {
   extern __shared__ __align__(16) char smem[];
-  if ((int)blockIdx.x >= P.counts[1]) return;
-  wg_backsub<T>(P, blockIdx.x, iter, smem, Rcap);
+  const int c = blockIdx.x / nparts;
+  if (c >= P.counts[1]) return;
+  wg_backsub<T>(P, c, blockIdx.x % nparts, nparts, iter, smem, Rcap);
 }
 
 __global__ void __launch_bounds__(WG) k_finalize(Params P) {
@@ -114,7 +115,7 @@ __global__ void __launch_bounds__(WG) k_fused(Params P, int Rcap) {
       __syncthreads();
       wg_chol<T>(P, w, it, smem);
       __syncthreads();
-      wg_backsub<T>(P, c, it, smem, Rcap);
+      wg_backsub<T>(P, c, 0, 1, it, smem, Rcap);
       __syncthreads();
     }
     wg_finalize(P, w);
@@ -356,13 +357,14 @@ int build_descriptors(ba_handle* h, const ba_problem* p, Plan& pl, int sched) {
   if (sched == BA_SCHED_FUSED) pl.fused = true;
   else if (sched == BA_SCHED_SPLIT) pl.fused = false;
   else pl.fused = W >= h->n_cu / 4;
-  // anchors per chunk for the split schedule: fixed, or aim for ~2 workgroups per CU
+  // anchors per chunk for the split schedule: fixed, or aim for one assembly
+  // workgroup per CU
   int c = 1;
   if (!pl.fused) {
     if (cfg.chunk_frames > 0) {
       c = cfg.chunk_frames;
     } else {
-      const int64_t target = 2LL * h->n_cu;
+      const int64_t target = h->n_cu;
       c = (int)std::max<int64_t>(1, (total_anchor + target - 1) / target);
     }
   }
@@ -505,6 +507,9 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
   const int chol_lds = chol_lds_bytes(std::min(pl.nmax, NCHOL_MAX));
   const int big_lds = chol_big_lds_bytes(pl.nmax);
   const int bs_lds = backsub_lds_bytes(Rcap, (int)sizeof(T));
+  // the back-substitution splits each chunk's sub-batches over several
+  // workgroups, for about two workgroups per CU
+  const int bs_parts = gC > 0 ? std::max(1, std::min(4, (2 * h->n_cu + gC - 1) / gC)) : 1;
   if (gW == 0) return BA_OK;
   if (pl.fused && pl.big) return fail(h, BA_E_CAPACITY, "the fused schedule holds at most 21 free frames per window");
   if (pl.fused) {
@@ -541,7 +546,7 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
       HIPCHK(h, hipGetLastError());
       if (gC > 0) {
         KernelTimer kt(h, s, BA_STAGE_BACKSUB);
-        hipLaunchKernelGGL(k_backsub<T>, dim3(gC), dim3(WG), bs_lds, s, P, it, Rcap);
+        hipLaunchKernelGGL(k_backsub<T>, dim3(gC * bs_parts), dim3(WG), bs_lds, s, P, it, Rcap, bs_parts);
       }
       HIPCHK(h, hipGetLastError());
     }
@@ -581,7 +586,7 @@ int launch_backward(ba_handle* h, const ba_problem* p, const Plan& pl, const dou
     else if (pl.maxt == 5) hipLaunchKernelGGL((k_assemble<T, 5>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
     else hipLaunchKernelGGL((k_assemble<T, 8>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
     hipLaunchKernelGGL(k_chol<T>, dim3(pl.W), dim3(WG), chol_lds, s, P, it);
-    hipLaunchKernelGGL(k_backsub<T>, dim3(pl.C), dim3(WG), bs_lds, s, P, it, Rcap);
+    hipLaunchKernelGGL(k_backsub<T>, dim3(pl.C), dim3(WG), bs_lds, s, P, it, Rcap, 1);
     HIPCHK(h, hipGetLastError());
   }
   hipLaunchKernelGGL(k_adj_init<T>, dim3(pl.W), dim3(WG), 0, s, P);

@@ -444,7 +444,8 @@ __device__ __forceinline__ void wg_chol(const Params& P, int w, int iter, char* 
 // assembly; writes the depth state (position order) or, on the last
 // iteration, depth_out (patch order).
 template <typename T>
-__device__ __forceinline__ void wg_backsub(const Params& P, int c, int iter, char* smem, int Rcap) {
+__device__ __forceinline__ void wg_backsub(const Params& P, int c, int part, int nparts, int iter, char* smem,
+                                           int Rcap) {
   double* lp = (double*)smem;
   T* rel = (T*)(smem + al16(Rcap * 7 * 8));
   double* dx = (double*)(smem + backsub_dx_offset(Rcap, (int)sizeof(T)));
@@ -461,7 +462,7 @@ __device__ __forceinline__ void wg_backsub(const Params& P, int c, int iter, cha
   const int32_t* acnt = P.acnt + W.frame_off + w;
   const int32_t* plist = P.plist + W.patch_off;
   if (st != 0) {
-    if (last) {
+    if (last && part == 0) {
       // failed window: its outputs are its inputs
       if (!(st & W_BAD_INDEX)) {
         for (int q = acnt[cd.a_lo] + tid; q < acnt[cd.a_hi]; q += WG) {
@@ -493,7 +494,10 @@ __device__ __forceinline__ void wg_backsub(const Params& P, int c, int iter, cha
   const int spw = SBw / NWAVES;
   const int npass = (spw + segs - 1) / segs;
   const int lseg = lane & (SEG - 1), sidx = lane / SEG;
-  const int s_lo = sbs[cd.a_lo], s_hi = sbs[cd.a_hi];
+  // this workgroup's share of the chunk's sub-batches (patches are
+  // independent here)
+  const int c_lo = sbs[cd.a_lo], c_n = sbs[cd.a_hi] - c_lo;
+  const int s_lo = c_lo + (c_n * part) / nparts, s_hi = c_lo + (c_n * (part + 1)) / nparts;
   if (s_lo >= s_hi) return;
 
   StageRegs<T> R;
