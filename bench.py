@@ -294,6 +294,8 @@ def main():
     ap.add_argument("--serve-schedule", default="split", choices=["fused", "split"])
     ap.add_argument("--serve-chunk", type=int, default=4)
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--large-only", action="store_true",
+                    help="run only the 64x256 large-window batch (for its profile) and print its record")
     ap.add_argument("--large-windows", type=int, default=8)
     ap.add_argument("--large-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -312,6 +314,10 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.large_only:
+        import torch
+        print(json.dumps(run_large(args, torch)), flush=True)
+        return
     if args.pmc_workload:
         pmc_workload(args)
         return
