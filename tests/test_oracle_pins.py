@@ -135,6 +135,23 @@ def test_projection_hand_point():
     assert abs(float(lin["r"][0, 1]) - 240.0) < 1e-12
 
 
+def test_worked_edge_golden():
+    """The hand-worked edge of tests/golden/worked_edge.json (Eq. 2 reprojection,
+    Eq. 6 residual, depth and target-pose Jacobians)."""
+    import json, os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "worked_edge.json")))
+    poses = torch.tensor([g["pose_i"], g["pose_j"]], dtype=O.DT)
+    lin = O.edge_linearization(poses, torch.tensor([g["inverse_depth"]], dtype=O.DT),
+                               torch.tensor([g["pixel"]], dtype=O.DT), torch.tensor([0]),
+                               torch.tensor([0]), torch.tensor([1]),
+                               torch.tensor([g["target"]], dtype=O.DT), g["intrinsics"])
+    e = g["expected"]
+    assert bool(lin["active"][0])
+    assert np.allclose(lin["r"][0].numpy(), e["residual"], atol=1e-12, rtol=0)
+    assert np.allclose(lin["Jd"][0].numpy(), e["depth_jacobian"], atol=1e-10, rtol=0)
+    assert np.allclose(lin["Jj"][0].numpy(), e["target_pose_jacobian"], atol=1e-10, rtol=0)
+
+
 def test_reprojection_matches_scene_model():
     """At the true state with exact targets, every visible edge has zero residual:
     Eq. 2 in inverse-depth form agrees with the world-point camera model."""
