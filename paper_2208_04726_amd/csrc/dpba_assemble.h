@@ -192,8 +192,11 @@ __device__ __forceinline__ void linearize_edge(const T* rel, T xb, T yb, T d, T 
   const T g0 = o.w0 * jd0, g1 = o.w1 * jd1;
   o.cd = g0 * jd0 + g1 * jd1;
   o.wd = g0 * o.r0 + g1 * o.r1;
+  // (J0[1] = J1[0] = 0: those products are left out, not multiplied by zero)
+  o.Ej[0] = g0 * o.J0[0];
+  o.Ej[1] = g1 * o.J1[1];
 #pragma unroll
-  for (int m = 0; m < 6; ++m) o.Ej[m] = g0 * o.J0[m] + g1 * o.J1[m];
+  for (int m = 2; m < 6; ++m) o.Ej[m] = g0 * o.J0[m] + g1 * o.J1[m];
   // Ei = -Ad^T Ej with Ad^T = [[R^T, 0], [(hat(t)R)^T, R^T]]
   if constexpr (kEi) {
 #pragma unroll
@@ -796,16 +799,26 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
             T* racc = qacc;
             if constexpr (kRegTbl) qj = j;
             else racc = mytbl + (sidx * Ra + (j - lo)) * TBL;
+            // Q += w0 J0 J0^T + w1 J1 J1^T, V += w0 r0 J0 + w1 r1 J1, with the
+            // structural zeros J0[1] = J1[0] = 0 left out
             int q = 0;
 #pragma unroll
             for (int m = 0; m < 6; ++m) {
               const T a0 = eo.w0 * eo.J0[m], a1 = eo.w1 * eo.J1[m];
 #pragma unroll
-              for (int n = m; n < 6; ++n, ++q) racc[q] = a1 * eo.J1[n] + (a0 * eo.J0[n] + racc[q]);
+              for (int n = m; n < 6; ++n, ++q) {
+                const bool z0 = m == 1 || n == 1, z1 = m == 0 || n == 0;
+                if (z0 && z1) continue;
+                if (z0) racc[q] = a1 * eo.J1[n] + racc[q];
+                else if (z1) racc[q] = a0 * eo.J0[n] + racc[q];
+                else racc[q] = a1 * eo.J1[n] + (a0 * eo.J0[n] + racc[q]);
+              }
             }
             const T b0 = eo.w0 * eo.r0, b1 = eo.w1 * eo.r1;
+            racc[21] = b0 * eo.J0[0] + racc[21];
+            racc[22] = b1 * eo.J1[1] + racc[22];
 #pragma unroll
-            for (int m = 0; m < 6; ++m) racc[21 + m] = b1 * eo.J1[m] + (b0 * eo.J0[m] + racc[21 + m]);
+            for (int m = 2; m < 6; ++m) racc[21 + m] = b1 * eo.J1[m] + (b0 * eo.J0[m] + racc[21 + m]);
           }
         } else {
         const int jprev = __shfl_up(j, 1, 64);
