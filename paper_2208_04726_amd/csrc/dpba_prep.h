@@ -85,6 +85,11 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
     rg[a + 3 * RMAX] = 1 << 30;
     rg[a + 4 * RMAX] = -1;
   }
+  // run ends / run starts of the edges per patch (read when the edges are sorted)
+  for (int k = tid; k < M; k += WG) {
+    cnt[k] = 0;
+    fill[k] = 0;
+  }
   __syncthreads();
 
   // ---- validation and order checks (coalesced, no atomics on the data path)
@@ -117,9 +122,11 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
     }
   }
   // edges in batches of PU per thread, so that the loads of a batch are in
-  // flight together
+  // flight together.  The same pass records where each patch's run of edges
+  // starts (fill) and ends (cnt), which gives the counts when the edges turn
+  // out to be sorted.
   for (int e0 = tid; e0 < E; e0 += PU * WG) {
-    int k[PU], j[PU], kp[PU], jp[PU];
+    int k[PU], j[PU], kp[PU], jp[PU], kn[PU];
 #pragma unroll
     for (int u = 0; u < PU; ++u) {
       const int e = e0 + u * WG;
@@ -128,13 +135,20 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
       j[u] = in ? jj[e] : 0;
       kp[u] = (in && e > 0) ? kk[e - 1] : -1;
       jp[u] = (in && e > 0) ? jj[e - 1] : -1;
+      kn[u] = (in && e + 1 < E) ? kk[e + 1] : -1;
     }
 #pragma unroll
     for (int u = 0; u < PU; ++u) {
-      if (e0 + u * WG < E) {
-        bad |= (k[u] < 0 || k[u] >= M || j[u] < 0 || j[u] >= N);
+      const int e = e0 + u * WG;
+      if (e < E) {
+        const bool kbad = k[u] < 0 || k[u] >= M;
+        bad |= (kbad || j[u] < 0 || j[u] >= N);
         uns_e |= (kp[u] > k[u] || (kp[u] == k[u] && jp[u] > j[u]));
         dup_e |= kp[u] == k[u] && jp[u] == j[u];
+        if (!kbad) {
+          if (kp[u] != k[u]) fill[k[u]] = e;
+          if (kn[u] != k[u]) cnt[k[u]] = e + 1;
+        }
       }
     }
   }
@@ -154,45 +168,22 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
   const int unsorted_e = flags[1], unsorted_p = flags[2];
 
   // ---- edges per patch and first CSR slot of each patch
-  for (int k = tid; k < M; k += WG) cnt[k] = 0;
-  __syncthreads();
-  if (!unsorted_e) {
-    // sorted by (patch, target): run boundaries give the counts
-    for (int e0 = tid; e0 < E; e0 += PU * WG) {
-      int k[PU], kn[PU];
-#pragma unroll
-      for (int u = 0; u < PU; ++u) {
-        const int e = e0 + u * WG;
-        k[u] = e < E ? kk[e] : -1;
-        kn[u] = e + 1 < E ? kk[e + 1] : -1;
-      }
-#pragma unroll
-      for (int u = 0; u < PU; ++u)
-        if (e0 + u * WG < E && kn[u] != k[u]) cnt[k[u]] = e0 + u * WG + 1;   // one past the run
+  if (unsorted_e) {
+    for (int k = tid; k < M; k += WG) {
+      cnt[k] = 0;
+      fill[k] = 0;
     }
-    __syncthreads();
-    for (int e0 = tid; e0 < E; e0 += PU * WG) {
-      int k[PU], kq[PU];
-#pragma unroll
-      for (int u = 0; u < PU; ++u) {
-        const int e = e0 + u * WG;
-        k[u] = e < E ? kk[e] : -1;
-        kq[u] = (e < E && e > 0) ? kk[e - 1] : -1;
-      }
-#pragma unroll
-      for (int u = 0; u < PU; ++u)
-        if (e0 + u * WG < E && kq[u] != k[u]) cnt[k[u]] -= e0 + u * WG;     // minus the run start
-    }
-  } else {
-    for (int k = tid; k < M; k += WG) fill[k] = 0;
     __syncthreads();
     for (int e = tid; e < E; e += WG) atomicAdd(&cnt[kk[e]], 1);
+    __syncthreads();
   }
-  __syncthreads();
   int mx = 0;
   for (int k = tid; k < M; k += WG) {
-    ptr[k] = cnt[k];
-    mx = max(mx, cnt[k]);
+    // sorted edges: the run end minus the run start (0 for a patch without edges)
+    const int c = unsorted_e ? cnt[k] : cnt[k] - fill[k];
+    cnt[k] = c;
+    ptr[k] = c;
+    mx = max(mx, c);
   }
   atomicMax(&flags[3], mx);
   __syncthreads();
