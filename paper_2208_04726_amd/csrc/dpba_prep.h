@@ -282,11 +282,18 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
 #pragma unroll
     for (int u = 0; u < PU; ++u) {
       const int q = q0 + u * WG;
+      // positions are in frame order, so neighbouring lanes mostly carry the
+      // same frame and the same first / last target: a lane equal to its left
+      // neighbour leaves the per-frame extremes to it (fewer LDS atomics on
+      // the same few words)
+      const int al = __shfl_up(a[u], 1, 64), j0l = __shfl_up(j0[u], 1, 64);
+      const int j1l = __shfl_up(j1[u], 1, 64), nl = __shfl_up(n[u], 1, 64);
+      const bool same = lane_id() > 0 && al == a[u] && j0l == j0[u] && j1l == j1[u] && (nl > 0) == (n[u] > 0);
       if (q < M) {
         pxy[2 * q] = (T)((x[u] - W.cx) / W.fx);
         pxy[2 * q + 1] = (T)((y[u] - W.cy) / W.fy);
         dep[q] = d[u];
-        if (n[u] > 0) {
+        if (n[u] > 0 && !same) {
           atomicMin(&lr[2 * a[u]], j0[u]);
           atomicMax(&lr[2 * a[u] + 1], j1[u]);
           atomicMin(&rg[a[u] + RMAX], j0[u]);
