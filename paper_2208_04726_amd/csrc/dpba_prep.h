@@ -343,26 +343,31 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
   // sub-batches per source frame
   const int maxdeg = flags[3];
   const int SBw = sb_width(seg_width(maxdeg));
-  if (tid == 0) {
-    int s = 0;
-    for (int a = 0; a < N; ++a) {
+  if (tid < 64) {
+    // wave 0, one frame per lane (at most 64): sub-batch counts, their prefix
+    // sum, and the frame's descriptors
+    const int a = tid;
+    const int p0 = a < N ? acnt[a] : 0, p1 = a < N ? acnt[a + 1] : 0;
+    const int c = (p1 - p0 + SBw - 1) / SBw;
+    int incl = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(incl, off, 64);
+      if (tid >= off) incl += v;
+    }
+    if (a < N) {
+      int s = incl - c;
       sbs[a] = s;
-      s += (acnt[a + 1] - acnt[a] + SBw - 1) / SBw;
+      if (a == N - 1) sbs[N] = incl;
+      ar[2 * a] = lr[2 * a];
+      ar[2 * a + 1] = lr[2 * a + 1];
+      const int flag = (lr[2 * RMAX + a] ? SB_REGULAR : 0) | (a << 8);
+      for (int q = p0; q < p1; q += SBw, ++s) {
+        const int n = min(SBw, p1 - q);
+        sbd[s] = make_int4(q, flag | n, est[q], est[q + n]);
+      }
     }
-    sbs[N] = s;
-  }
-  for (int a = tid; a < N; a += WG) {
-    ar[2 * a] = lr[2 * a];
-    ar[2 * a + 1] = lr[2 * a + 1];
-  }
-  __syncthreads();
-  for (int a = tid; a < N; a += WG) {
-    const int p0 = acnt[a], p1 = acnt[a + 1];
-    int s = sbs[a];
-    for (int q = p0; q < p1; q += SBw, ++s) {
-      const int n = min(SBw, p1 - q);
-      sbd[s] = make_int4(q, (lr[2 * RMAX + a] ? SB_REGULAR : 0) | (a << 8) | n, est[q], est[q + n]);
-    }
+    if (N == 0 && a == 0) sbs[0] = 0;
   }
   __syncthreads();
   if (tid == 0) {
