@@ -743,7 +743,11 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
         hi = arng[2 * (a - cd.a_lo) + 1];
         Ra = hi - lo + 1;
         load_relposes<T>(lp, a, lo, hi, f_lo, rel);
-        for (int i = tid; i < NWAVES * tslots * Ra * TBL; i += WG) tbl[i] = T(0);
+        {
+          const int nt = NWAVES * tslots * Ra * TBL, n4 = (nt * (int)sizeof(T)) / 16;
+          for (int i = tid; i < n4; i += WG) ((float4*)tbl)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+          for (int i = (n4 * 16) / (int)sizeof(T) + tid; i < nt; i += WG) tbl[i] = T(0);
+        }
         // one table copy per lane segment and one target frame per lane: the
         // rows are summed in the same order in registers (five-tile FP32
         // passes) or in LDS (otherwise), so the sums do not depend on the
