@@ -99,7 +99,7 @@ __device__ __forceinline__ void wg_gather_big(const Params& P, int w, int tile) 
 // bits in *flag.  Per 16-column panel: wave 0 factorises and inverts the
 // diagonal block; the rows below become A L^{-T} (matrix-core products, kept
 // in the LDS panel and written back); the trailing lower triangle is updated
-// from the LDS panel, two 16x16 tiles per wave in flight.
+// from the LDS panel, four 16x16 tiles per wave in flight.
 __device__ __forceinline__ void wg_cholesky_big(double* A, int ld, int n, char* smem, double* dinv, int* flag) {
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   const int rows_pad = ((n + 1 + 15) / 16) * 16;
