@@ -133,3 +133,24 @@ def test_empty_batch():
     torch.cuda.synchronize()
     assert po.shape == (0, 7) and do.shape == (0,)
     assert len(s.status()) == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_irregular_graph_method_scale(precision):
+    """Each patch of a 22x96 window keeps a random 85% of its edges, so the
+    patches of a source frame have different target sequences: the general
+    pair-table path (LDS tables per lane segment), against the oracle."""
+    need_gpu()
+    w = synth.method_scale_window(6)
+    rng = np.random.default_rng(61)
+    keep = rng.uniform(size=w.n_edges) < 0.85
+    d = w.copy()
+    d.kk, d.jj = w.kk[keep].copy(), w.jj[keep].copy()
+    d.targets, d.weights = w.targets[keep].copy(), w.weights[keep].copy()
+    (r,), st = solve_gpu([d], precision, "split")
+    assert st[0] == 0
+    pr, dr = O.solve(d)
+    dc, drot, dd = compare(r[0], r[1], pr, dr)
+    print(precision, "irregular 22x96:", f"{dc:.2e} m {drot:.2e} deg depth {dd:.2e}")
+    tol = FP64_TOL if precision == "fp64" else (1e-4, 1e-2, 1e-3)
+    assert dc < tol[0] and drot < tol[1] and dd < tol[2], (dc, drot, dd)
