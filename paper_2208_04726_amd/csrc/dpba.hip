@@ -356,7 +356,7 @@ int build_descriptors(ba_handle* h, const ba_problem* p, Plan& pl, int sched) {
   for (int w = 0; w < W; ++w) total_anchor += p->frame_off[w + 1] - p->frame_off[w];
   if (sched == BA_SCHED_FUSED) pl.fused = true;
   else if (sched == BA_SCHED_SPLIT) pl.fused = false;
-  else pl.fused = W >= h->n_cu / 4;
+  else pl.fused = false;   // AUTO: the split schedule, faster at every batch size measured
   // anchors per chunk for the split schedule: fixed, or aim for one assembly
   // workgroup per CU
   int c = 1;
@@ -649,8 +649,7 @@ int ba_create(const ba_config* cfg, ba_handle** out) {
                                                             cfg->chunk_frames)));
     h->cap_partial = blocks * (Dmax * Dmax + 2 * Dmax);
   }
-  h->launch_fused = cfg->schedule == BA_SCHED_FUSED ||
-                    (cfg->schedule == BA_SCHED_AUTO && cfg->max_windows >= h->n_cu / 4);
+  h->launch_fused = cfg->schedule == BA_SCHED_FUSED;
   bool ok = true;
   auto dmalloc = [&](void** ptr, size_t bytes) {
     if (!ok) return;
