@@ -639,7 +639,15 @@ int ba_create(const ba_config* cfg, ba_handle** out) {
                 E = std::max<int64_t>(cfg->max_edges, 1);
   const int64_t Dmax = 6LL * cfg->max_frames_per_window;
   const size_t esz = cfg->precision == BA_PREC_FP32 ? 4 : 8;
-  h->cap_chunks = std::max<int64_t>(F, W);
+  // chunks per call: the split schedule's chunking gives at most n_cu + W
+  // (about n_cu groups of source frames, plus one partial group per window),
+  // or F / chunk_frames + W with fixed chunking; the fused schedule one per
+  // window.  The capacity-sized launches of ba_launch use this bound.
+  {
+    int64_t cap_c = std::min<int64_t>(F, (int64_t)h->n_cu + W);
+    if (cfg->chunk_frames > 0) cap_c = std::min<int64_t>(F, (F + cfg->chunk_frames - 1) / cfg->chunk_frames + W);
+    h->cap_chunks = std::max<int64_t>(cap_c, W);
+  }
   {
     // partial blocks: one chunk per window, and about two chunks per CU
     // across the batch (or the fixed chunking)
