@@ -792,7 +792,11 @@ int ba_launch(ba_handle* h, void* stream) {
   pl.big = !pl.fused && pl.nmax > NCHOL_MAX;
   if (pl.fused) pl.nmax = std::min(NCHOL_MAX, pl.nmax);
   {
-    const int T16 = (pl.nmax + 1 + 15) / 16;
+    // tile passes sized for windows with at least two fixed poses (the gauge
+    // of the method); a window with fewer takes a second tile pass, with the
+    // same results
+    const int n2 = 6 * std::max(pl.Rcap - 2, 1);
+    const int T16 = (std::min(pl.nmax, n2) + 1 + 15) / 16;
     pl.maxt = maxt_for(T16 * (T16 + 1) / 2);
   }
   const ba_problem* p = &h->prep_problem;
