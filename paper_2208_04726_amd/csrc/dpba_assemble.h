@@ -218,24 +218,28 @@ __device__ __forceinline__ int wg_bcast_status(const int32_t* status, int w, int
 }
 
 
+// One relative pose's LDS entry: R (9), t (3), hat(t) R (9).
+template <typename T>
+__device__ __forceinline__ void store_relpose(const double* R, const double* t, T* o) {
+#pragma unroll
+  for (int m = 0; m < 9; ++m) o[m] = (T)R[m];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) o[9 + m] = (T)t[m];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    o[12 + c] = (T)(-t[2] * R[3 + c] + t[1] * R[6 + c]);
+    o[15 + c] = (T)(t[2] * R[c] - t[0] * R[6 + c]);
+    o[18 + c] = (T)(-t[1] * R[c] + t[0] * R[3 + c]);
+  }
+}
+
 // Relative poses T_ja for j in [lo, hi] into rel[(j - f_lo) * RELW].
 template <typename T>
 __device__ __forceinline__ void load_relposes(const double* poses, int a, int lo, int hi, int f_lo, T* rel) {
   for (int j = lo + (int)threadIdx.x; j <= hi; j += WG) {
     double R[9], t[3];
     relative_pose(poses + 7 * a, poses + 7 * j, R, t);
-    T* o = rel + (j - f_lo) * RELW;
-#pragma unroll
-    for (int m = 0; m < 9; ++m) o[m] = (T)R[m];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) o[9 + m] = (T)t[m];
-    // hat(t) R
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      o[12 + c] = (T)(-t[2] * R[3 + c] + t[1] * R[6 + c]);
-      o[15 + c] = (T)(t[2] * R[c] - t[0] * R[6 + c]);
-      o[18 + c] = (T)(-t[1] * R[c] + t[0] * R[3 + c]);
-    }
+    store_relpose<T>(R, t, rel + (j - f_lo) * RELW);
   }
 }
 

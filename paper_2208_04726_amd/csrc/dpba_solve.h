@@ -513,12 +513,13 @@ __device__ __forceinline__ void wg_backsub(const Params& P, int c, int part, int
     if (an != a) {
       a = an;
       const int lo = arng[2 * (a - cd.a_lo)], hi = arng[2 * (a - cd.a_lo) + 1];
-      load_relposes<T>(lp, a, lo, hi, 0, rel);
-      // E_ik^T dx_a = -sum_j E_jk^T Ad(T_ja) dx_a: per target frame the
-      // vector dx_j - Ad(T_ja) dx_a, so an edge adds E_jk^T (dx_j - Ad dx_a)
+      // relative poses, and since E_ik^T dx_a = -sum_j E_jk^T Ad(T_ja) dx_a,
+      // per target frame the vector dx_j - Ad(T_ja) dx_a, so an edge adds
+      // E_jk^T (dx_j - Ad dx_a)
       for (int j = lo + tid; j <= hi; j += WG) {
         double R[9], t[3];
         relative_pose(lp + 7 * a, lp + 7 * j, R, t);
+        store_relpose<T>(R, t, rel + j * RELW);
         const double* xa = dx + 6 * a;
         double Rp[3], Rr[3];
 #pragma unroll
