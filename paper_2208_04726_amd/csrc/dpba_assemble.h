@@ -740,6 +740,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
         lds_barrier();
       }
       if (s == s_hi) break;
+      const bool started = an != a;
       if (an != a) {
         // ---- start of source frame an: relative poses, empty pair tables
         a = an;
@@ -784,8 +785,19 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
       const bool pre = s + 2 < s_hi;
       if (s + 1 < s_hi) stage_issue<T>(P, W, w, we, dnxt, iter, dbar_in, R);
       if (pre) dnn = desc_prefetch(sbd + s + 2);
-      for (int i = tid; i < (16 * T16 * LDK * (int)sizeof(T)) / 16; i += WG) ((float4*)U)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-      lds_barrier();
+      // The staged rows start from zero.  A regular source frame writes every
+      // (target, patch) entry it owns in each sub-batch (zero for an inactive
+      // edge), so U is cleared at the frame's start only, plus the columns of
+      // a short last sub-batch that the products read past its patches.
+      const int nkb = (nsb + 15) >> 4;
+      const bool clear_all = !regular || started;
+      if (clear_all) {
+        for (int i = tid; i < (16 * T16 * LDK * (int)sizeof(T)) / 16; i += WG) ((float4*)U)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      } else if (nsb & 15) {
+        const int nc = 16 * nkb - nsb;
+        for (int i = tid; i < 16 * T16 * nc; i += WG) U[(i / nc) * LDK + nsb + i % nc] = T(0);
+      }
+      if (clear_all || (nsb & 15)) lds_barrier();
 
       // ---- linearise this wave's patches, one lane segment per patch
       T* mytbl = tbl + wv * tslots * Ra * TBL;
@@ -859,10 +871,17 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
         // the source frame's columns, w_k / sqrt(C_k) at column D
         const int slot = le.slot;
         T* ucol = U + (6 * (j - lo_free)) * LDK + slot;
-        for (int ln = 0; ln < (anydup ? SEG : 1); ++ln) {
-          if (le.pv && eo.active && j >= lo_free && (!anydup || lseg == ln)) {
+        if (regular) {
+          if (le.pv && le.has && j != a && j >= lo_free) {
 #pragma unroll
-            for (int m = 0; m < 6; ++m) ucol[m * LDK] += eo.Ej[m] * rs;
+            for (int m = 0; m < 6; ++m) ucol[m * LDK] = eo.active ? eo.Ej[m] * rs : T(0);
+          }
+        } else {
+          for (int ln = 0; ln < (anydup ? SEG : 1); ++ln) {
+            if (le.pv && eo.active && j >= lo_free && (!anydup || lseg == ln)) {
+#pragma unroll
+              for (int m = 0; m < 6; ++m) ucol[m * LDK] += eo.Ej[m] * rs;
+            }
           }
         }
         if (le.pv && lseg == 0) {
@@ -880,7 +899,6 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
       // ---- matrix-core outer products of the staged rows
       {
         const int l16 = lane & 15, g = lane >> 4;
-        const int nkb = (nsb + 15) >> 4;
 #pragma unroll
         for (int t = 0; t < MAXT; ++t) {
           if (tmask & (1u << t)) {
