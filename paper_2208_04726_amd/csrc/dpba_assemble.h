@@ -501,8 +501,11 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
   for (int tp = 0; tp < npasses_t; ++tp) {
     const int p0 = tp * per_pass;
     const int Lp = min(per_pass, Ltot - p0);
-    const int t_beg = p0 + (wv * Lp) / NWAVES, t_end = p0 + ((wv + 1) * Lp) / NWAVES;
-    const int ntl = t_end - t_beg;
+    // this wave's tiles of the pass: p0 + wv, p0 + wv + NWAVES, ... (spread
+    // over the rows, so that the tiles a source frame reaches are shared out
+    // evenly among the waves)
+    const int ntl = Lp > wv ? (Lp - wv + NWAVES - 1) / NWAVES : 0;
+    const int t_beg = p0 + wv;   // tile t of the wave is t_beg + NWAVES * t
     Acc acc[MAXT];
     double sh[4 * MAXT];
     // Regular source frames (every patch with the same target-frame sequence)
@@ -671,7 +674,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
 #pragma unroll
             for (int t = 0; t < MAXT; ++t) {
               if (tmask & (1u << t)) {
-                float4* src = (float4*)img + (t_beg + t - p0) * 64 + lane;
+                float4* src = (float4*)img + (t_beg + NWAVES * t - p0) * 64 + lane;
                 const float4 v = *src;
                 *src = make_float4(0.f, 0.f, 0.f, 0.f);
                 const float vv[4] = {v.x, v.y, v.z, v.w};
@@ -695,7 +698,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
             // tiles the source frame does not reach hold no products and no
             // B / v entries of it
             if (tmask & (1u << t)) {
-              const int code = tiles[t_beg + t];
+              const int code = tiles[t_beg + NWAVES * t];
               const int ti = code >> 16, tj = code & 0xffff;
               const int col = 16 * tj + l16;
               const int cf = col / 6, n = col - 6 * cf, fc = lo_free + cf;
@@ -769,7 +772,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
         // this wave's tiles that the source frame's outer products reach
         tmask = 0;
         for (int t = 0; t < ntl; ++t) {
-          const int code = tiles[t_beg + t];
+          const int code = tiles[t_beg + NWAVES * t];
           const int ti = code >> 16, tj = code & 0xffff;
           const bool rows_nz = (16 * ti < nz_hi && 16 * ti + 16 > nz_lo) ||
                                (16 * ti < Daug && D < 16 * ti + 16);
@@ -902,7 +905,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
 #pragma unroll
         for (int t = 0; t < MAXT; ++t) {
           if (tmask & (1u << t)) {
-            const int code = tiles[t_beg + t];
+            const int code = tiles[t_beg + NWAVES * t];
             const int ti = code >> 16, tj = code & 0xffff;
             {
               const T* ua = U + (16 * ti + l16) * LDK + 4 * g;
@@ -932,7 +935,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
 #pragma unroll
       for (int t = 0; t < MAXT; ++t) {
         if (t < ntl) {
-          const int code = tiles[t_beg + t];
+          const int code = tiles[t_beg + NWAVES * t];
           const int ti = code >> 16, tj = code & 0xffff;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
