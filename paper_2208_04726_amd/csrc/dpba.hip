@@ -54,6 +54,16 @@ __global__ void __launch_bounds__(WG) k_chol_big(Params P, int iter) {
   wg_chol_big<T>(P, w, iter, smem);
 }
 
+// Panel j of the factorisation of the windows with n > 126:
+// blockIdx.x = window * (1 + groups) + b, b = 0 the panel workgroup, b >= 1
+// the trailing-update workgroups.
+__global__ void __launch_bounds__(WG) k_chol_panel(Params P, int j, int groups) {
+  extern __shared__ __align__(16) char smem[];
+  const int w = blockIdx.x / (1 + groups);
+  if (w >= P.counts[0]) return;
+  wg_chol_panel(P, w, j, blockIdx.x % (1 + groups), smem);
+}
+
 // Reduced systems of the windows with n > 126: blockIdx.x = window * tiles + tile.
 __global__ void __launch_bounds__(WG) k_gather_big(Params P, int tiles) {
   const int w = blockIdx.x / tiles;
@@ -194,6 +204,7 @@ struct ba_handle {
   double *xib = nullptr, *xid = nullptr, *qxi = nullptr, *dbar = nullptr, *fcot = nullptr;
   double* partial = nullptr;
   double* s_big = nullptr;   // augmented reduced systems, windows with n > 126
+  double* big_aux = nullptr; // their factorisation side data
   int ld_big = 0;
   double *dxi = nullptr, *pose_buf = nullptr, *depth_buf = nullptr;
   // per-kernel timing (ba_set_timing): event pairs around each launch
@@ -229,6 +240,7 @@ int set_kernel_attrs() {
   if (hipFuncSetAttribute((const void*)k_fused<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_chol<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_chol_big<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chol_panel, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_backsub<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_debug_gather<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_chol_adj<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
@@ -458,6 +470,7 @@ void fill_params(ba_handle* h, const ba_problem* p, const Plan& pl, Params& P) {
   P.partial = h->partial;
   P.s_big = h->s_big;
   P.ld_big = h->ld_big;
+  P.big_aux = h->big_aux;
   P.dxi = h->dxi;
   P.pose_buf = h->pose_buf;
   P.depth_buf = h->depth_buf;
@@ -540,6 +553,11 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
         if (pl.big) {
           const int tiles = gather_tiles(pl.nmax);
           hipLaunchKernelGGL(k_gather_big, dim3(gW * tiles), dim3(WG), 0, s, P, tiles);
+          for (int j = 0; CB * j < pl.nmax; ++j) {
+            const int groups = upd_groups(pl.nmax, j);
+            hipLaunchKernelGGL(k_chol_panel, dim3(gW * (1 + groups)), dim3(WG), chol_panel_lds_bytes(pl.nmax), s, P, j,
+                               groups);
+          }
           hipLaunchKernelGGL(k_chol_big<T>, dim3(gW), dim3(WG), big_lds, s, P, it);
         }
       }
@@ -681,6 +699,7 @@ int ba_create(const ba_config* cfg, ba_handle** out) {
   if (6 * cfg->max_frames_per_window > NCHOL_MAX) {
     h->ld_big = big_ld(cfg->max_frames_per_window);
     dmalloc((void**)&h->s_big, 8 * (size_t)W * h->ld_big * h->ld_big);
+    dmalloc((void**)&h->big_aux, 8 * (size_t)W * big_aux_stride(h->ld_big));
   }
   dmalloc((void**)&h->dxi, 8 * 6 * F);
   const int64_t slots = cfg->iterations + 1;
@@ -864,6 +883,7 @@ void ba_destroy(ba_handle* h) {
   hipFree(h->cstate);
   hipFree(h->partial);
   hipFree(h->s_big);
+  hipFree(h->big_aux);
   hipFree(h->dxi);
   hipFree(h->pose_buf);
   hipFree(h->depth_buf);

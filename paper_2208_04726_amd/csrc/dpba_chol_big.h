@@ -2,16 +2,20 @@
 // the depth-eliminated system (Sec. 3.1, Schur complement) no longer fits in
 // the LDS of one workgroup, so it is summed into an (n+1) x (n+1) FP64 matrix
 // in device memory (row n carries the right-hand side -s) by many
-// workgroups, then factorised in place by one workgroup per window with a
-// blocked right-looking Cholesky:
-//   * each 16 x 16 diagonal block is factorised and inverted by one wave;
-//   * the rows below it (the right-hand-side row included, which folds the
-//     forward substitution L y = -s into the factorisation) are multiplied by
-//     the inverse with matrix-core products;
-//   * the trailing lower triangle is updated with 16x16x4 FP64 matrix-core
-//     products from the panel held in LDS.
-// The back substitution L^T dxi = y runs by 16-row blocks from the bottom,
-// then the free poses are retracted as in the small-window solve.
+// workgroups, then factorised in place by a blocked right-looking Cholesky
+// with one launch per 16-column panel j:
+//   * one workgroup per window applies panel j-1 to column block j, then
+//     factorises and inverts the 16 x 16 diagonal block (one wave) and turns
+//     the rows below it (the right-hand-side row included, which folds the
+//     forward substitution L y = -s into the factorisation) into A L^{-T}
+//     with matrix-core products;
+//   * in the same launch, many more workgroups apply panel j-1 to the rest
+//     of the trailing lower triangle (16x16x4 FP64 matrix-core products),
+//     so the update of a window is spread over the chip instead of one CU.
+// Every entry receives the same products in the same order as in a
+// one-workgroup factorisation.  The back substitution L^T dxi = y runs by
+// 16-row blocks from the bottom, then the free poses are retracted as in the
+// small-window solve.
 #pragma once
 #include "dpba_solve.h"
 
@@ -29,13 +33,45 @@ __host__ __device__ inline int gather_tiles(int n) {
 }
 __host__ __device__ inline int big_ld(int rcap) { return 6 * rcap + 1; }
 
-// LDS: panel ((n+1) rows padded to 16, CB columns), the diagonal block's
-// factor and its inverse, row-block flags, the right-hand side / solution,
-// the reciprocal diagonal of L.
-__host__ __device__ inline int chol_big_lds_bytes(int n) {
-  const int rows = ((n + 1 + 15) / 16) * 16;
-  return 64 + (rows * PLD + 2 * CB * PLD + 16 + 3 * (n + 8)) * 8;
+// Per-window side data of the factorisation (FP64 words, after the window's
+// slot): the reciprocal diagonal of L (ld words), then as ints the nonzero
+// flags of the row blocks below the last two panels (2 x 32) and the pivot
+// flags of the factorisation (one int).
+__host__ __device__ inline int big_aux_stride(int ld) { return ld + 40; }
+struct BigAux {
+  double* dinv;
+  int* nzb;    // nzb + 32 * (panel & 1)
+  int* bad;
+};
+__device__ __forceinline__ BigAux big_aux(const Params& P, int w) {
+  double* base = P.big_aux + (int64_t)w * big_aux_stride(P.ld_big);
+  int* ints = (int*)(base + P.ld_big);
+  return {base, ints, ints + 64};
 }
+
+constexpr int TU_PANEL = 4;   // tiles per wave in flight, panel workgroup
+constexpr int TU_UPD = 2;     // tiles per wave in flight, update workgroups
+constexpr int UPD_TILES = TU_UPD * NWAVES;   // tiles per update workgroup
+
+// Lower 16x16 tiles right of column block j of the trailing matrix at panel
+// j (rows and columns from 16 j), which the update workgroups of launch j
+// take from panel j - 1.
+__host__ __device__ inline int upd_tiles(int n, int j) {
+  const int m = n + 1 - CB * j;
+  if (j == 0 || m <= 0) return 0;
+  const int T = (m + 15) / 16;
+  return T * (T - 1) / 2;
+}
+__host__ __device__ inline int upd_groups(int n, int j) { return (upd_tiles(n, j) + UPD_TILES - 1) / UPD_TILES; }
+
+// LDS of a panel launch: flags, the diagonal block's inverse, row-block
+// flags, the column block ((n+1) rows padded to 16).
+__host__ __device__ inline int chol_panel_lds_bytes(int n) {
+  return 64 + CB * PLD * 8 + 32 * 4 + ((n + 1 + 15) / 16) * 16 * PLD * 8;
+}
+// LDS of the back substitution: flags, the solution, the running right-hand
+// side, the reciprocal diagonal, two staged 16-row blocks of L.
+__host__ __device__ inline int chol_big_lds_bytes(int n) { return 64 + 3 * (n + 8) * 8 + 2 * CB * (n + 1) * 8; }
 
 // One 64 x 64 tile of the augmented system of window w, summed from the chunk
 // partials in chunk order (the order of the small-window gather):
@@ -94,118 +130,218 @@ __device__ __forceinline__ void wg_gather_big(const Params& P, int w, int tile) 
   }
 }
 
-// Blocked Cholesky of the augmented matrix A (lower, ld) in place; on return
-// rows < n hold L and row n holds y = L^{-1} b.  Pivot problems set BA_W_*
-// bits in *flag.  Per 16-column panel: wave 0 factorises and inverts the
-// diagonal block; the rows below become A L^{-T} (matrix-core products, kept
-// in the LDS panel and written back); the trailing lower triangle is updated
-// from the LDS panel, four 16x16 tiles per wave in flight.
-__device__ __forceinline__ void wg_cholesky_big(double* A, int ld, int n, char* smem, double* dinv, int* flag) {
-  const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
-  const int rows_pad = ((n + 1 + 15) / 16) * 16;
-  double* Pn = (double*)(smem + 64);           // panel rows below the diagonal block
-  double* Linv = Pn + rows_pad * PLD;          // inverse of the diagonal block
-  double* Ld = Linv + CB * PLD;                // the diagonal block's factor
-  int* nzb = (int*)(Ld + CB * PLD);            // nonzero flags of the panel's row blocks
-  int bad = 0;
-  for (int k0 = 0; k0 < n; k0 += CB) {
-    const int kb = min(CB, n - k0);
-    const int r0 = k0 + kb;             // first row below the block
-    const int m = n + 1 - r0;           // rows below, the right-hand-side row included
-    if (wv == 0) {
-      double Lr[CB];
+// Applies the panel of L held in columns kp .. kp+15 of A to lower 16x16
+// tiles of the trailing matrix at r0 = kp + 16: tile (ti, tj) covers rows
+// r0 + 16 ti .. and columns r0 + 16 tj ..;  A[r][c] -= sum_t L[r][kp+t] L[c][kp+t]
+// for c <= r, c < n, r <= n, as four 16x16x4 FP64 matrix-core steps in
+// panel-column order.  The wave takes tiles t_beg, t_beg + NWAVES, .. below
+// t_end, TU at a time; tile_of maps an index to (ti, tj).  Tiles whose panel
+// row blocks are all zero (nzb, relative to r0) are skipped.
+template <int TU, typename TileOf>
+__device__ __forceinline__ void apply_panel(double* A, int ld, int n, int kp, int t_beg, int t_end, TileOf tile_of,
+                                            const int* nzb) {
+  const int lane = lane_id(), l16 = lane & 15, g = lane >> 4;
+  const int r0 = kp + CB, m = n + 1 - r0;
+  for (int t0 = t_beg; t0 < t_end; t0 += TU * NWAVES) {
+    f64x4 acc[TU];
+    double pa[TU][4], pb[TU][4];
+    int ti[TU], tj[TU];
+    bool has[TU];
 #pragma unroll
-      for (int t = 0; t < CB; ++t)
-        Lr[t] = (lane < kb && t <= lane) ? A[(int64_t)(k0 + lane) * ld + k0 + t] : (t == lane ? 1.0 : 0.0);
-      wave_factor_invert(Lr, kb, Ld, PLD, Linv, dinv + k0, bad);
-      if (lane < kb) {
+    for (int u = 0; u < TU; ++u) {
+      const int t = t0 + u * NWAVES;
+      ti[u] = 0;
+      tj[u] = 0;
+      if (t < t_end) tile_of(t, ti[u], tj[u]);
+      has[u] = t < t_end && nzb[ti[u]] && nzb[tj[u]];
+      const int ra = 16 * ti[u] + l16, ca = 16 * tj[u] + l16;
 #pragma unroll
-        for (int t = 0; t < CB; ++t)
-          if (t <= lane) A[(int64_t)(k0 + lane) * ld + k0 + t] = Lr[t];
+      for (int kq = 0; kq < 4; ++kq) {
+        pa[u][kq] = (has[u] && ra < m) ? A[(int64_t)(r0 + ra) * ld + kp + g + 4 * kq] : 0.0;
+        pb[u][kq] = (has[u] && ca < m) ? A[(int64_t)(r0 + ca) * ld + kp + g + 4 * kq] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * ti[u] + acc_row(0.0, g, r), col = 16 * tj[u] + l16;
+        const bool ok = has[u] && row < m && col <= row && r0 + col < n;
+        acc[u][r] = ok ? A[(int64_t)(r0 + row) * ld + r0 + col] : 0.0;
       }
     }
-    // zero the panel rows past the matrix (operands of the last tiles)
-    for (int i = m + tid; i < rows_pad - r0; i += WG)
 #pragma unroll
-      for (int t = 0; t < CB; ++t) Pn[i * PLD + t] = 0.0;
-    __syncthreads();
-    {
-      auto rows = [&](int r) { return (const double*)(A + (int64_t)(r0 + r) * ld + k0); };
-      auto dst = [&](int r) { return Pn + r * PLD; };
-      auto dst2 = [&](int r, int c, double v) { A[(int64_t)(r0 + r) * ld + k0 + c] = v; };
-      panel_trsm_mfma(m, kb, Linv, rows, dst, dst2, nzb);
-    }
-    __syncthreads();
-    // ---- trailing update A[r][c] -= sum_t P[r][t] P[c][t], c <= r, c < n
-    if (m > 1) {
-      const int T = (m + 15) / 16;
-      const int ntile = T * (T + 1) / 2;
-      const int l16 = lane & 15, g = lane >> 4;
-      constexpr int TU = 4;   // tiles per wave in flight
-      for (int t0 = wv; t0 < ntile; t0 += TU * NWAVES) {
-        f64x4 acc[TU];
-        int ti[TU], tj[TU];
-        bool has[TU];
+    for (int u = 0; u < TU; ++u) {
+      if (has[u]) {
 #pragma unroll
-        for (int u = 0; u < TU; ++u) {
-          const int t = t0 + u * NWAVES;
-          int a = 0;
-          while (((a + 1) * (a + 2)) / 2 <= t) ++a;
-          ti[u] = a;
-          tj[u] = t - (a * (a + 1)) / 2;
-          has[u] = t < ntile && nzb[ti[u]] && nzb[tj[u]];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = 16 * ti[u] + acc_row(0.0, g, r), col = 16 * tj[u] + l16;
-            const bool ok = has[u] && row < m && col <= row && r0 + col < n;
-            acc[u][r] = ok ? A[(int64_t)(r0 + row) * ld + r0 + col] : 0.0;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < TU; ++u) {
-          if (has[u]) {
-            const double* pa = Pn + (16 * ti[u] + l16) * PLD + g;
-            const double* pb = Pn + (16 * tj[u] + l16) * PLD + g;
-#pragma unroll
-            for (int kq = 0; kq < CB / 4; ++kq) acc[u] = mfma16(-pa[4 * kq], pb[4 * kq], acc[u]);
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < TU; ++u) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = 16 * ti[u] + acc_row(0.0, g, r), col = 16 * tj[u] + l16;
-            if (has[u] && row < m && col <= row && r0 + col < n)
-              A[(int64_t)(r0 + row) * ld + r0 + col] = acc[u][r];
-          }
-        }
+        for (int kq = 0; kq < 4; ++kq) acc[u] = mfma16(-pa[u][kq], pb[u][kq], acc[u]);
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < TU; ++u) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * ti[u] + acc_row(0.0, g, r), col = 16 * tj[u] + l16;
+        if (has[u] && row < m && col <= row && r0 + col < n) A[(int64_t)(r0 + row) * ld + r0 + col] = acc[u][r];
+      }
+    }
   }
-  if (wv == 0 && lane == 0) *flag = bad;
+}
+
+// Launch j of the factorisation of window w (k0 = 16 j): workgroup b = 0
+// brings column block j up to date with panel j-1 (in LDS), factorises its
+// diagonal block and forms the rows below it; workgroups b >= 1 apply panel j-1 to
+// their share of the tiles right of column block j.  The two sets of
+// entries are disjoint, and both only read panel j-1, which launch j-1
+// finished.  Pivot problems accumulate BA_W_* bits in the side data.
+__device__ __forceinline__ void wg_chol_panel(const Params& P, int w, int j, int b, char* smem) {
+  const WinDesc W = P.win[w];
+  const int n = 6 * (W.n_frames - W.n_fixed);
+  // the status word is not written during the factorisation
+  if (n <= NCHOL_MAX || P.status[w] != 0) return;
+  const int k0 = CB * j;
+  if (k0 >= n) return;   // a window with fewer panels
+  const int ld = P.ld_big;
+  double* A = P.s_big + (int64_t)w * ld * ld;
+  const BigAux ax = big_aux(P, w);
+  const int* nzb_prev = ax.nzb + 32 * ((j + 1) & 1);
+  const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  if (b > 0) {
+    const int t_end = min(b * UPD_TILES, upd_tiles(n, j));
+    apply_panel<TU_UPD>(A, ld, n, k0 - CB, (b - 1) * UPD_TILES + wv, t_end,
+                        [](int t, int& ti, int& tj) {
+                          int a = 0;
+                          while (((a + 1) * (a + 2)) / 2 <= t) ++a;
+                          ti = a + 1;
+                          tj = t - (a * (a + 1)) / 2 + 1;
+                        },
+                        nzb_prev);
+    return;
+  }
+  double* Linv = (double*)(smem + 64);
+  int* nzb = (int*)(Linv + CB * PLD);
+  double* Cb = (double*)(nzb + 32);   // column block j, rows k0 .. n (LDS, stride PLD)
+  const int mc = n + 1 - k0;
+  {
+    // column block j with panel j-1 applied (tiles (ti, 0) of apply_panel),
+    // kept in LDS for the factorisation and the rows below
+    const int l16 = lane & 15, g = lane >> 4;
+    const int T = (mc + 15) / 16, kp = k0 - CB;
+    double pb[4];
+    const bool col_nz = j > 0 && nzb_prev[0];
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq) pb[kq] = (col_nz && l16 < mc) ? A[(int64_t)(k0 + l16) * ld + kp + g + 4 * kq] : 0.0;
+    for (int t0 = wv; t0 < T; t0 += TU_PANEL * NWAVES) {
+      f64x4 acc[TU_PANEL];
+      double pa[TU_PANEL][4];
+      bool has[TU_PANEL];
+#pragma unroll
+      for (int u = 0; u < TU_PANEL; ++u) {
+        const int ti = t0 + u * NWAVES;
+        has[u] = ti < T && col_nz && nzb_prev[ti];
+        const int ra = 16 * ti + l16;
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq)
+          pa[u][kq] = (has[u] && ra < mc) ? A[(int64_t)(k0 + ra) * ld + kp + g + 4 * kq] : 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * ti + acc_row(0.0, g, r), col = l16;
+          const bool ok = ti < T && row < mc && col <= row && k0 + col < n;
+          acc[u][r] = ok ? A[(int64_t)(k0 + row) * ld + k0 + col] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TU_PANEL; ++u) {
+        if (has[u]) {
+#pragma unroll
+          for (int kq = 0; kq < 4; ++kq) acc[u] = mfma16(-pa[u][kq], pb[kq], acc[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TU_PANEL; ++u) {
+        const int ti = t0 + u * NWAVES;
+        if (ti < T) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * ti + acc_row(0.0, g, r), col = l16;
+            const bool ok = row < mc && col <= row && k0 + col < n;
+            Cb[row * PLD + col] = ok ? acc[u][r] : 0.0;
+          }
+        }
+      }
+    }
+  }
   __syncthreads();
+  const int kb = min(CB, n - k0);
+  if (wv == 0) {
+    double Lr[CB];
+#pragma unroll
+    for (int t = 0; t < CB; ++t) Lr[t] = (lane < kb && t <= lane) ? Cb[lane * PLD + t] : (t == lane ? 1.0 : 0.0);
+    int bad = 0;
+    wave_factor_invert(Lr, kb, A + (int64_t)k0 * ld + k0, ld, Linv, ax.dinv + k0, bad);
+    if (lane == 0) *ax.bad = (j == 0 ? 0 : *ax.bad) | bad;
+  }
+  __syncthreads();
+  const int r0 = k0 + kb, m = n + 1 - r0;
+  {
+    auto rows = [&](int r) { return (const double*)(Cb + (kb + r) * PLD); };
+    auto dst = [&](int r) { return A + (int64_t)(r0 + r) * ld + k0; };
+    auto none = [](int, int, double) {};
+    panel_trsm_mfma(m, kb, Linv, rows, dst, none, nzb);
+  }
+  __syncthreads();
+  if (tid < (m + 15) / 16) ax.nzb[32 * (j & 1) + tid] = nzb[tid];
 }
 
 // L^T x = y, L in A (lower, ld), y = row n of A; x into LDS `x` (n entries).
+// By 16-row blocks from the bottom: the rows of block b (columns up to its
+// diagonal) are staged in LDS while block b+1 is solved, so each step waits
+// on LDS only.  buf: 2 x 16 rows of n + 1 doubles; dv: n doubles.
+constexpr int BS_PF = (CB * NBIG_MAX + WG - 1) / WG;   // staged entries per thread
 __device__ __forceinline__ void wg_backsolve_big(const double* A, int ld, int n, const double* dinv, double* x,
-                                        double* z) {
+                                        double* z, double* dv, double* buf) {
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
-  for (int j = tid; j < n; j += WG) z[j] = A[(int64_t)n * ld + j];
-  __syncthreads();
+  const int ldb = n + 1;
+  double pf[BS_PF];
+  // block b's rows b0 .. b0+bs-1, columns 0 .. b0+bs-1, into registers
+  auto fetch = [&](int b) {
+    const int b0 = b * CB, bs = min(CB, n - b0), cols = b0 + bs;
+#pragma unroll
+    for (int u = 0; u < BS_PF; ++u) {
+      const int e = tid + u * WG;
+      const int r = e / cols, c = e - r * cols;
+      pf[u] = r < bs ? A[(int64_t)(b0 + r) * ld + c] : 0.0;
+    }
+  };
+  auto stash = [&](int b) {
+    const int b0 = b * CB, bs = min(CB, n - b0), cols = b0 + bs;
+    double* dst = buf + (b & 1) * CB * ldb;
+#pragma unroll
+    for (int u = 0; u < BS_PF; ++u) {
+      const int e = tid + u * WG;
+      const int r = e / cols, c = e - r * cols;
+      if (r < bs) dst[r * ldb + c] = pf[u];
+    }
+  };
   const int nb = (n + CB - 1) / CB;
+  fetch(nb - 1);
+  for (int j = tid; j < n; j += WG) {
+    z[j] = A[(int64_t)n * ld + j];
+    dv[j] = dinv[j];
+  }
+  stash(nb - 1);
+  __syncthreads();
   for (int b = nb - 1; b >= 0; --b) {
     const int b0 = b * CB, bs = min(CB, n - b0);
+    const double* L = buf + (b & 1) * CB * ldb;
+    if (b > 0) fetch(b - 1);
     if (wv == 0) {
       // lane t holds column t of the diagonal block and z_t
       double Lc[CB];
 #pragma unroll
-      for (int s = 0; s < CB; ++s) Lc[s] = (lane < bs && s < bs && s >= lane) ? A[(int64_t)(b0 + s) * ld + b0 + lane] : 0.0;
+      for (int s = 0; s < CB; ++s) Lc[s] = (lane < bs && s < bs && s >= lane) ? L[s * ldb + b0 + lane] : 0.0;
       double zz = lane < bs ? z[b0 + lane] : 0.0;
 #pragma unroll
       for (int s = CB - 1; s >= 0; --s) {
         if (s < bs) {
-          const double xs = readlane_f64(zz, s) * dinv[b0 + s];
+          const double xs = readlane_f64(zz, s) * dv[b0 + s];
           if (lane == s) zz = xs;
           else if (lane < s) zz -= Lc[s] * xs;
         }
@@ -215,15 +351,16 @@ __device__ __forceinline__ void wg_backsolve_big(const double* A, int ld, int n,
     __syncthreads();
     for (int j = tid; j < b0; j += WG) {
       double v = z[j];
-      for (int s = 0; s < bs; ++s) v -= A[(int64_t)(b0 + s) * ld + j] * x[b0 + s];
+      for (int s = 0; s < bs; ++s) v -= L[s * ldb + j] * x[b0 + s];
       z[j] = v;
     }
+    if (b > 0) stash(b - 1);
     __syncthreads();
   }
 }
 
-// Solve and retraction of a window with n > 126 (the system was gathered by
-// wg_gather_big).
+// Back substitution and retraction of a window with n > 126 (the system was
+// gathered by wg_gather_big and factorised by the panel launches).
 template <typename T>
 __device__ __forceinline__ void wg_chol_big(const Params& P, int w, int iter, char* smem) {
   const WinDesc W = P.win[w];
@@ -241,14 +378,13 @@ __device__ __forceinline__ void wg_chol_big(const Params& P, int w, int iter, ch
   }
   const int ld = P.ld_big;
   double* A = P.s_big + (int64_t)w * ld * ld;
-  const int rows_pad = ((n + 1 + 15) / 16) * 16;
-  double* x = (double*)(smem + 64) + rows_pad * PLD + 2 * CB * PLD + 16;
+  double* x = (double*)(smem + 64);
   double* z = x + n + 8;
-  double* dinv = z + n + 8;
-  wg_cholesky_big(A, ld, n, smem, dinv, misc + 1);
-  wg_backsolve_big(A, ld, n, dinv, x, z);
+  double* dv = z + n + 8;
+  const BigAux ax = big_aux(P, w);
+  wg_backsolve_big(A, ld, n, ax.dinv, x, z, dv, dv + n + 8);
   if (tid == 0) {
-    int bad = misc[1];
+    int bad = *ax.bad;
     for (int i = 0; i < n; ++i)
       if (!isfinite_d(x[i])) bad |= W_NONFINITE;
     misc[2] = bad;

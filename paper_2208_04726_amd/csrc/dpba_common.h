@@ -73,6 +73,7 @@ struct Params {
   double* partial;      // chunk partials of S (lower, D x D) and s (D), FP64
   double* s_big;        // [W][ld_big^2] augmented reduced systems of windows with n > 126
   int32_t ld_big;
+  double* big_aux;      // [W][ld_big + 40] factorisation side data of those windows
   double* dxi;          // [F*6] pose steps
   double* pose_buf;     // [K+1][F*7] pose state after each iteration (slot 0: inputs)
   double* depth_buf;    // [K+1][P] inverse-depth state after each iteration, position order
