@@ -553,7 +553,7 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
         if (pl.big) {
           const int tiles = gather_tiles(pl.nmax);
           hipLaunchKernelGGL(k_gather_big, dim3(gW * tiles), dim3(WG), 0, s, P, tiles);
-          for (int j = 0; CB * j < pl.nmax; ++j) {
+          for (int j = 0; PW * j < pl.nmax; ++j) {
             const int groups = upd_groups(pl.nmax, j);
             hipLaunchKernelGGL(k_chol_panel, dim3(gW * (1 + groups)), dim3(WG), chol_panel_lds_bytes(pl.nmax), s, P, j,
                                groups);

@@ -33,41 +33,45 @@ __host__ __device__ inline int gather_tiles(int n) {
 }
 __host__ __device__ inline int big_ld(int rcap) { return 6 * rcap + 1; }
 
+// The factorisation advances by panels of two 16-column sub-blocks.
+constexpr int PW = 2 * CB;     // panel width
+constexpr int CLD = PW + 1;    // LDS row stride of a panel's column block
+
 // Per-window side data of the factorisation (FP64 words, after the window's
-// slot): the reciprocal diagonal of L (ld words), then as ints the nonzero
-// flags of the row blocks below the last two panels (2 x 32) and the pivot
-// flags of the factorisation (one int).
-__host__ __device__ inline int big_aux_stride(int ld) { return ld + 40; }
+// slot): the reciprocal diagonal of L (ld words), then as ints, for the last
+// two panels (panel & 1), the nonzero flags of the 16-row blocks below each
+// sub-block (32 + 32), and the pivot flags of the factorisation (one int).
+__host__ __device__ inline int big_aux_stride(int ld) { return ld + 72; }
 struct BigAux {
   double* dinv;
-  int* nzb;    // nzb + 32 * (panel & 1)
+  int* nzb;    // panel p: nzb + 64 * (p & 1), first sub-block, then + 32 the second
   int* bad;
 };
 __device__ __forceinline__ BigAux big_aux(const Params& P, int w) {
   double* base = P.big_aux + (int64_t)w * big_aux_stride(P.ld_big);
   int* ints = (int*)(base + P.ld_big);
-  return {base, ints, ints + 64};
+  return {base, ints, ints + 128};
 }
 
-constexpr int TU_PANEL = 4;   // tiles per wave in flight, panel workgroup
+constexpr int TU_PANEL = 4;   // row tiles per wave in flight, panel workgroup
 constexpr int TU_UPD = 2;     // tiles per wave in flight, update workgroups
 constexpr int UPD_TILES = TU_UPD * NWAVES;   // tiles per update workgroup
 
 // Lower 16x16 tiles right of column block j of the trailing matrix at panel
-// j (rows and columns from 16 j), which the update workgroups of launch j
-// take from panel j - 1.
+// j (rows and columns from 32 j, tile columns 2 and up), which the update
+// workgroups of launch j take from panel j - 1.
 __host__ __device__ inline int upd_tiles(int n, int j) {
-  const int m = n + 1 - CB * j;
+  const int m = n + 1 - PW * j;
   if (j == 0 || m <= 0) return 0;
   const int T = (m + 15) / 16;
-  return T * (T - 1) / 2;
+  return T >= 2 ? (T - 2) * (T - 1) / 2 : 0;
 }
 __host__ __device__ inline int upd_groups(int n, int j) { return (upd_tiles(n, j) + UPD_TILES - 1) / UPD_TILES; }
 
 // LDS of a panel launch: flags, the diagonal block's inverse, row-block
-// flags, the column block ((n+1) rows padded to 16).
+// flags, the column block ((n+1) rows padded to 16, stride CLD).
 __host__ __device__ inline int chol_panel_lds_bytes(int n) {
-  return 64 + CB * PLD * 8 + 32 * 4 + ((n + 1 + 15) / 16) * 16 * PLD * 8;
+  return 64 + CB * PLD * 8 + 64 * 4 + ((n + 1 + 15) / 16) * 16 * CLD * 8;
 }
 // LDS of the back substitution: flags, the solution, the running right-hand
 // side, the reciprocal diagonal, two staged 16-row blocks of L.
@@ -130,128 +134,165 @@ __device__ __forceinline__ void wg_gather_big(const Params& P, int w, int tile) 
   }
 }
 
-// Applies the panel of L held in columns kp .. kp+15 of A to lower 16x16
-// tiles of the trailing matrix at r0 = kp + 16: tile (ti, tj) covers rows
-// r0 + 16 ti .. and columns r0 + 16 tj ..;  A[r][c] -= sum_t L[r][kp+t] L[c][kp+t]
-// for c <= r, c < n, r <= n, as four 16x16x4 FP64 matrix-core steps in
-// panel-column order.  The wave takes tiles t_beg, t_beg + NWAVES, .. below
-// t_end, TU at a time; tile_of maps an index to (ti, tj).  Tiles whose panel
-// row blocks are all zero (nzb, relative to r0) are skipped.
+// Applies panel j-1 (columns kp = k0 - 32 .. k0 - 1 of L in A: two 16-column
+// sub-blocks) to lower 16x16 tiles of the trailing matrix at r0 = k0: tile
+// (ti, tj) covers rows r0 + 16 ti .. and columns r0 + 16 tj ..;
+// A[r][c] -= sum_t L[r][kp+t] L[c][kp+t] for c <= r, c < n, r <= n, as four
+// 16x16x4 FP64 matrix-core steps per sub-block, first sub-block first.  A
+// sub-block is skipped for a tile whose row blocks below it are zero
+// (nzb_a: flags of the first sub-block, row blocks from k0 - 16; nzb_b: the
+// second, from k0).  The wave takes tiles t_beg, t_beg + NWAVES, .. below
+// t_end, TU at a time; tile_of maps an index to (ti, tj).
 template <int TU, typename TileOf>
-__device__ __forceinline__ void apply_panel(double* A, int ld, int n, int kp, int t_beg, int t_end, TileOf tile_of,
-                                            const int* nzb) {
+__device__ __forceinline__ void apply_panel(double* A, int ld, int n, int k0, int t_beg, int t_end, TileOf tile_of,
+                                            const int* nzb_a, const int* nzb_b) {
   const int lane = lane_id(), l16 = lane & 15, g = lane >> 4;
-  const int r0 = kp + CB, m = n + 1 - r0;
+  const int kp = k0 - PW, m = n + 1 - k0;
   for (int t0 = t_beg; t0 < t_end; t0 += TU * NWAVES) {
     f64x4 acc[TU];
-    double pa[TU][4], pb[TU][4];
+    double pa[TU][8], pb[TU][8];
     int ti[TU], tj[TU];
-    bool has[TU];
+    bool ha[TU], hb[TU];
 #pragma unroll
     for (int u = 0; u < TU; ++u) {
       const int t = t0 + u * NWAVES;
       ti[u] = 0;
       tj[u] = 0;
       if (t < t_end) tile_of(t, ti[u], tj[u]);
-      has[u] = t < t_end && nzb[ti[u]] && nzb[tj[u]];
+      ha[u] = t < t_end && nzb_a[ti[u] + 1] && nzb_a[tj[u] + 1];
+      hb[u] = t < t_end && nzb_b[ti[u]] && nzb_b[tj[u]];
       const int ra = 16 * ti[u] + l16, ca = 16 * tj[u] + l16;
 #pragma unroll
       for (int kq = 0; kq < 4; ++kq) {
-        pa[u][kq] = (has[u] && ra < m) ? A[(int64_t)(r0 + ra) * ld + kp + g + 4 * kq] : 0.0;
-        pb[u][kq] = (has[u] && ca < m) ? A[(int64_t)(r0 + ca) * ld + kp + g + 4 * kq] : 0.0;
+        pa[u][kq] = (ha[u] && ra < m) ? A[(int64_t)(k0 + ra) * ld + kp + g + 4 * kq] : 0.0;
+        pb[u][kq] = (ha[u] && ca < m) ? A[(int64_t)(k0 + ca) * ld + kp + g + 4 * kq] : 0.0;
+        pa[u][4 + kq] = (hb[u] && ra < m) ? A[(int64_t)(k0 + ra) * ld + kp + CB + g + 4 * kq] : 0.0;
+        pb[u][4 + kq] = (hb[u] && ca < m) ? A[(int64_t)(k0 + ca) * ld + kp + CB + g + 4 * kq] : 0.0;
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * ti[u] + acc_row(0.0, g, r), col = 16 * tj[u] + l16;
-        const bool ok = has[u] && row < m && col <= row && r0 + col < n;
-        acc[u][r] = ok ? A[(int64_t)(r0 + row) * ld + r0 + col] : 0.0;
+        const bool ok = (ha[u] || hb[u]) && row < m && col <= row && k0 + col < n;
+        acc[u][r] = ok ? A[(int64_t)(k0 + row) * ld + k0 + col] : 0.0;
       }
     }
 #pragma unroll
     for (int u = 0; u < TU; ++u) {
-      if (has[u]) {
+      if (ha[u]) {
 #pragma unroll
         for (int kq = 0; kq < 4; ++kq) acc[u] = mfma16(-pa[u][kq], pb[u][kq], acc[u]);
       }
+      if (hb[u]) {
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) acc[u] = mfma16(-pa[u][4 + kq], pb[u][4 + kq], acc[u]);
+      }
     }
 #pragma unroll
     for (int u = 0; u < TU; ++u) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * ti[u] + acc_row(0.0, g, r), col = 16 * tj[u] + l16;
-        if (has[u] && row < m && col <= row && r0 + col < n) A[(int64_t)(r0 + row) * ld + r0 + col] = acc[u][r];
+        if ((ha[u] || hb[u]) && row < m && col <= row && k0 + col < n)
+          A[(int64_t)(k0 + row) * ld + k0 + col] = acc[u][r];
       }
     }
   }
 }
 
-// Launch j of the factorisation of window w (k0 = 16 j): workgroup b = 0
-// brings column block j up to date with panel j-1 (in LDS), factorises its
-// diagonal block and forms the rows below it; workgroups b >= 1 apply panel j-1 to
-// their share of the tiles right of column block j.  The two sets of
-// entries are disjoint, and both only read panel j-1, which launch j-1
-// finished.  Pivot problems accumulate BA_W_* bits in the side data.
+// Launch j of the factorisation of window w (k0 = 32 j).  Workgroup b = 0
+// brings column block j (32 columns) up to date with panel j-1 in LDS, then
+// per 16-column sub-block: one wave factorises and inverts the diagonal
+// block, the rows below become A L^{-T} (written to A), and after the first
+// sub-block the second one's columns receive its update in LDS.
+// Workgroups b >= 1 apply panel j-1 to their share of the tiles right of
+// column block j.  The two sets of entries are disjoint, and both only read
+// panel j-1, which launch j-1 finished.  Pivot problems accumulate BA_W_*
+// bits in the side data.
 __device__ __forceinline__ void wg_chol_panel(const Params& P, int w, int j, int b, char* smem) {
   const WinDesc W = P.win[w];
   const int n = 6 * (W.n_frames - W.n_fixed);
   // the status word is not written during the factorisation
   if (n <= NCHOL_MAX || P.status[w] != 0) return;
-  const int k0 = CB * j;
+  const int k0 = PW * j;
   if (k0 >= n) return;   // a window with fewer panels
   const int ld = P.ld_big;
   double* A = P.s_big + (int64_t)w * ld * ld;
   const BigAux ax = big_aux(P, w);
-  const int* nzb_prev = ax.nzb + 32 * ((j + 1) & 1);
+  const int* pa_prev = ax.nzb + 64 * ((j + 1) & 1);   // panel j-1, first sub-block
+  const int* pb_prev = pa_prev + 32;                  // and second
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  const int l16 = lane & 15, g = lane >> 4;
   if (b > 0) {
     const int t_end = min(b * UPD_TILES, upd_tiles(n, j));
-    apply_panel<TU_UPD>(A, ld, n, k0 - CB, (b - 1) * UPD_TILES + wv, t_end,
+    apply_panel<TU_UPD>(A, ld, n, k0, (b - 1) * UPD_TILES + wv, t_end,
                         [](int t, int& ti, int& tj) {
                           int a = 0;
                           while (((a + 1) * (a + 2)) / 2 <= t) ++a;
-                          ti = a + 1;
-                          tj = t - (a * (a + 1)) / 2 + 1;
+                          ti = a + 2;
+                          tj = t - (a * (a + 1)) / 2 + 2;
                         },
-                        nzb_prev);
+                        pa_prev, pb_prev);
     return;
   }
   double* Linv = (double*)(smem + 64);
-  int* nzb = (int*)(Linv + CB * PLD);
-  double* Cb = (double*)(nzb + 32);   // column block j, rows k0 .. n (LDS, stride PLD)
+  int* nzb = (int*)(Linv + CB * PLD);   // 32 + 32 flags
+  double* Cb = (double*)(nzb + 64);     // column block j, rows k0 .. n (LDS, stride CLD)
   const int mc = n + 1 - k0;
+  const int kw = min(PW, n - k0);
   {
-    // column block j with panel j-1 applied (tiles (ti, 0) of apply_panel),
-    // kept in LDS for the factorisation and the rows below
-    const int l16 = lane & 15, g = lane >> 4;
-    const int T = (mc + 15) / 16, kp = k0 - CB;
-    double pb[4];
-    const bool col_nz = j > 0 && nzb_prev[0];
+    // column block j with panel j-1 applied: row tiles ti, column tiles tc
+    // = 0, 1 (the entries and order of apply_panel)
+    const int T = (mc + 15) / 16, kp = k0 - PW;
+    double qa[2][4], qb[2][4];
+    bool ca[2], cb[2];
 #pragma unroll
-    for (int kq = 0; kq < 4; ++kq) pb[kq] = (col_nz && l16 < mc) ? A[(int64_t)(k0 + l16) * ld + kp + g + 4 * kq] : 0.0;
+    for (int tc = 0; tc < 2; ++tc) {
+      ca[tc] = j > 0 && pa_prev[tc + 1];
+      cb[tc] = j > 0 && pb_prev[tc];
+      const int rr = 16 * tc + l16;
+#pragma unroll
+      for (int kq = 0; kq < 4; ++kq) {
+        qa[tc][kq] = (ca[tc] && rr < mc) ? A[(int64_t)(k0 + rr) * ld + kp + g + 4 * kq] : 0.0;
+        qb[tc][kq] = (cb[tc] && rr < mc) ? A[(int64_t)(k0 + rr) * ld + kp + CB + g + 4 * kq] : 0.0;
+      }
+    }
     for (int t0 = wv; t0 < T; t0 += TU_PANEL * NWAVES) {
-      f64x4 acc[TU_PANEL];
-      double pa[TU_PANEL][4];
-      bool has[TU_PANEL];
+      f64x4 acc[TU_PANEL][2];
+      double pa[TU_PANEL][8];
+      bool ra_nz[TU_PANEL], rb_nz[TU_PANEL];
 #pragma unroll
       for (int u = 0; u < TU_PANEL; ++u) {
         const int ti = t0 + u * NWAVES;
-        has[u] = ti < T && col_nz && nzb_prev[ti];
+        ra_nz[u] = ti < T && j > 0 && pa_prev[ti + 1];
+        rb_nz[u] = ti < T && j > 0 && pb_prev[ti];
         const int ra = 16 * ti + l16;
 #pragma unroll
-        for (int kq = 0; kq < 4; ++kq)
-          pa[u][kq] = (has[u] && ra < mc) ? A[(int64_t)(k0 + ra) * ld + kp + g + 4 * kq] : 0.0;
+        for (int kq = 0; kq < 4; ++kq) {
+          pa[u][kq] = (ra_nz[u] && ra < mc) ? A[(int64_t)(k0 + ra) * ld + kp + g + 4 * kq] : 0.0;
+          pa[u][4 + kq] = (rb_nz[u] && ra < mc) ? A[(int64_t)(k0 + ra) * ld + kp + CB + g + 4 * kq] : 0.0;
+        }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * ti + acc_row(0.0, g, r), col = l16;
-          const bool ok = ti < T && row < mc && col <= row && k0 + col < n;
-          acc[u][r] = ok ? A[(int64_t)(k0 + row) * ld + k0 + col] : 0.0;
+        for (int tc = 0; tc < 2; ++tc) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * ti + acc_row(0.0, g, r), col = 16 * tc + l16;
+            const bool ok = ti < T && row < mc && col <= row && k0 + col < n;
+            acc[u][tc][r] = ok ? A[(int64_t)(k0 + row) * ld + k0 + col] : 0.0;
+          }
         }
       }
 #pragma unroll
       for (int u = 0; u < TU_PANEL; ++u) {
-        if (has[u]) {
 #pragma unroll
-          for (int kq = 0; kq < 4; ++kq) acc[u] = mfma16(-pa[u][kq], pb[kq], acc[u]);
+        for (int tc = 0; tc < 2; ++tc) {
+          if (ra_nz[u] && ca[tc]) {
+#pragma unroll
+            for (int kq = 0; kq < 4; ++kq) acc[u][tc] = mfma16(-pa[u][kq], qa[tc][kq], acc[u][tc]);
+          }
+          if (rb_nz[u] && cb[tc]) {
+#pragma unroll
+            for (int kq = 0; kq < 4; ++kq) acc[u][tc] = mfma16(-pa[u][4 + kq], qb[tc][kq], acc[u][tc]);
+          }
         }
       }
 #pragma unroll
@@ -259,35 +300,75 @@ __device__ __forceinline__ void wg_chol_panel(const Params& P, int w, int j, int
         const int ti = t0 + u * NWAVES;
         if (ti < T) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = 16 * ti + acc_row(0.0, g, r), col = l16;
-            const bool ok = row < mc && col <= row && k0 + col < n;
-            Cb[row * PLD + col] = ok ? acc[u][r] : 0.0;
+          for (int tc = 0; tc < 2; ++tc) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * ti + acc_row(0.0, g, r), col = 16 * tc + l16;
+              const bool ok = row < mc && col <= row && k0 + col < n;
+              Cb[row * CLD + col] = ok ? acc[u][tc][r] : 0.0;
+            }
           }
         }
       }
     }
   }
   __syncthreads();
-  const int kb = min(CB, n - k0);
-  if (wv == 0) {
-    double Lr[CB];
+  int bad = 0;
+  const int nsub = (kw + CB - 1) / CB;
+  for (int sb = 0; sb < nsub; ++sb) {
+    const int c0 = CB * sb;              // sub-block's first column within the panel
+    const int kb = min(CB, kw - c0);
+    if (sb == 1) {
+      // second sub-block's columns (rows from 16) minus the first's products,
+      // tiles (ti, 0) at r0 = k0 + 16 as in a 16-column factorisation
+      const int m1 = mc - CB, T1 = (m1 + 15) / 16;
+      const int* nz1 = nzb;
+      double qb1[4];
 #pragma unroll
-    for (int t = 0; t < CB; ++t) Lr[t] = (lane < kb && t <= lane) ? Cb[lane * PLD + t] : (t == lane ? 1.0 : 0.0);
-    int bad = 0;
-    wave_factor_invert(Lr, kb, A + (int64_t)k0 * ld + k0, ld, Linv, ax.dinv + k0, bad);
-    if (lane == 0) *ax.bad = (j == 0 ? 0 : *ax.bad) | bad;
+      for (int kq = 0; kq < 4; ++kq) qb1[kq] = (nz1[0] && l16 < m1) ? Cb[(CB + l16) * CLD + g + 4 * kq] : 0.0;
+      for (int ti = wv; ti < T1; ti += NWAVES) {
+        const bool has = nz1[ti] && nz1[0];
+        const int ra = 16 * ti + l16;
+        f64x4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * ti + acc_row(0.0, g, r);
+          acc[r] = (row < m1 && l16 <= row) ? Cb[(CB + row) * CLD + CB + l16] : 0.0;
+        }
+        if (has) {
+#pragma unroll
+          for (int kq = 0; kq < 4; ++kq) {
+            const double av = ra < m1 ? Cb[(CB + ra) * CLD + g + 4 * kq] : 0.0;
+            acc = mfma16(-av, qb1[kq], acc);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * ti + acc_row(0.0, g, r);
+            if (row < m1 && l16 <= row && k0 + CB + l16 < n) Cb[(CB + row) * CLD + CB + l16] = acc[r];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (wv == 0) {
+      double Lr[CB];
+#pragma unroll
+      for (int t = 0; t < CB; ++t)
+        Lr[t] = (lane < kb && t <= lane) ? Cb[(c0 + lane) * CLD + c0 + t] : (t == lane ? 1.0 : 0.0);
+      wave_factor_invert(Lr, kb, A + (int64_t)(k0 + c0) * ld + k0 + c0, ld, Linv, ax.dinv + k0 + c0, bad);
+    }
+    __syncthreads();
+    const int r0 = k0 + c0 + kb, m = n + 1 - r0;
+    {
+      auto rows = [&](int r) { return (const double*)(Cb + (c0 + kb + r) * CLD + c0); };
+      auto dst = [&](int r) { return Cb + (c0 + kb + r) * CLD + c0; };
+      auto dst2 = [&](int r, int c, double v) { A[(int64_t)(r0 + r) * ld + k0 + c0 + c] = v; };
+      panel_trsm_mfma(m, kb, Linv, rows, dst, dst2, nzb + 32 * sb);
+    }
+    __syncthreads();
+    if (tid < (m + 15) / 16) ax.nzb[64 * (j & 1) + 32 * sb + tid] = nzb[32 * sb + tid];
   }
-  __syncthreads();
-  const int r0 = k0 + kb, m = n + 1 - r0;
-  {
-    auto rows = [&](int r) { return (const double*)(Cb + (kb + r) * PLD); };
-    auto dst = [&](int r) { return A + (int64_t)(r0 + r) * ld + k0; };
-    auto none = [](int, int, double) {};
-    panel_trsm_mfma(m, kb, Linv, rows, dst, none, nzb);
-  }
-  __syncthreads();
-  if (tid < (m + 15) / 16) ax.nzb[32 * (j & 1) + tid] = nzb[tid];
+  if (wv == 0 && lane == 0) *ax.bad = (j == 0 ? 0 : *ax.bad) | bad;
 }
 
 // L^T x = y, L in A (lower, ld), y = row n of A; x into LDS `x` (n entries).
