@@ -3,17 +3,18 @@
 // the LDS of one workgroup, so it is summed into an (n+1) x (n+1) FP64 matrix
 // in device memory (row n carries the right-hand side -s) by many
 // workgroups, then factorised in place by a blocked right-looking Cholesky
-// with one launch per 16-column panel j:
-//   * one workgroup per window applies panel j-1 to column block j, then
-//     factorises and inverts the 16 x 16 diagonal block (one wave) and turns
-//     the rows below it (the right-hand-side row included, which folds the
-//     forward substitution L y = -s into the factorisation) into A L^{-T}
-//     with matrix-core products;
+// with one launch per 32-column panel j (two 16-column sub-blocks):
+//   * one workgroup per window applies panel j-1 to column block j in LDS;
+//     per sub-block it factorises and inverts the 16 x 16 diagonal block
+//     (one wave) and turns the rows below it (the right-hand-side row
+//     included, which folds the forward substitution L y = -s into the
+//     factorisation) into A L^{-T} with matrix-core products, the first
+//     sub-block's rows updating the second's columns in between;
 //   * in the same launch, many more workgroups apply panel j-1 to the rest
 //     of the trailing lower triangle (16x16x4 FP64 matrix-core products),
 //     so the update of a window is spread over the chip instead of one CU.
 // Every entry receives the same products in the same order as in a
-// one-workgroup factorisation.  The back substitution L^T dxi = y runs by
+// one-workgroup factorisation with 16-column panels.  The back substitution L^T dxi = y runs by
 // 16-row blocks from the bottom, then the free poses are retracted as in the
 // small-window solve.
 #pragma once
@@ -22,8 +23,8 @@
 namespace dpba {
 
 constexpr int NBIG_MAX = 6 * RMAX;   // reduced system size of a 64-frame window
-constexpr int CB = CBS;              // panel width
-constexpr int PLD = CB + 1;          // LDS row stride of the panel
+constexpr int CB = CBS;              // sub-block width
+constexpr int PLD = CB + 1;          // LDS row stride of a diagonal block's inverse
 constexpr int GT = 64;               // gather tile
 
 // 64 x 64 lower tiles of the augmented (n+1) square.
