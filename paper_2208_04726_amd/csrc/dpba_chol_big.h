@@ -376,31 +376,25 @@ __device__ __forceinline__ void wg_chol_panel(const Params& P, int w, int j, int
 // By 16-row blocks from the bottom: the rows of block b (columns up to its
 // diagonal) are staged in LDS while block b+1 is solved, so each step waits
 // on LDS only.  buf: 2 x 16 rows of n + 1 doubles; dv: n doubles.
-constexpr int BS_PF = (CB * NBIG_MAX + WG - 1) / WG;   // staged entries per thread
+static_assert(NBIG_MAX < WG, "a row of the reduced system is staged one entry per thread");
 __device__ __forceinline__ void wg_backsolve_big(const double* A, int ld, int n, const double* dinv, double* x,
                                         double* z, double* dv, double* buf) {
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   const int ldb = n + 1;
-  double pf[BS_PF];
-  // block b's rows b0 .. b0+bs-1, columns 0 .. b0+bs-1, into registers
+  double pf[CB];
+  // block b's rows b0 .. b0+bs-1, columns 0 .. b0+bs-1 (thread = column),
+  // into registers
   auto fetch = [&](int b) {
     const int b0 = b * CB, bs = min(CB, n - b0), cols = b0 + bs;
 #pragma unroll
-    for (int u = 0; u < BS_PF; ++u) {
-      const int e = tid + u * WG;
-      const int r = e / cols, c = e - r * cols;
-      pf[u] = r < bs ? A[(int64_t)(b0 + r) * ld + c] : 0.0;
-    }
+    for (int r = 0; r < CB; ++r) pf[r] = (r < bs && tid < cols) ? A[(int64_t)(b0 + r) * ld + tid] : 0.0;
   };
   auto stash = [&](int b) {
     const int b0 = b * CB, bs = min(CB, n - b0), cols = b0 + bs;
     double* dst = buf + (b & 1) * CB * ldb;
 #pragma unroll
-    for (int u = 0; u < BS_PF; ++u) {
-      const int e = tid + u * WG;
-      const int r = e / cols, c = e - r * cols;
-      if (r < bs) dst[r * ldb + c] = pf[u];
-    }
+    for (int r = 0; r < CB; ++r)
+      if (r < bs && tid < cols) dst[r * ldb + tid] = pf[r];
   };
   const int nb = (n + CB - 1) / CB;
   fetch(nb - 1);
