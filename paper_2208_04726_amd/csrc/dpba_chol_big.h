@@ -71,12 +71,15 @@ __host__ __device__ inline int upd_groups(int n, int j) { return (upd_tiles(n, j
 
 // LDS of a panel launch: flags, the diagonal block's inverse, row-block
 // flags, the column block ((n+1) rows padded to 16, stride CLD).
-__host__ __device__ inline int chol_panel_lds_bytes(int n) {
+__host__ __device__ constexpr int chol_panel_lds_bytes(int n) {
   return 64 + CB * PLD * 8 + 64 * 4 + ((n + 1 + 15) / 16) * 16 * CLD * 8;
 }
 // LDS of the back substitution: flags, the solution, the running right-hand
 // side, the reciprocal diagonal, two staged 16-row blocks of L.
-__host__ __device__ inline int chol_big_lds_bytes(int n) { return 64 + 3 * (n + 8) * 8 + 2 * CB * (n + 1) * 8; }
+__host__ __device__ constexpr int chol_big_lds_bytes(int n) { return 64 + 3 * (n + 8) * 8 + 2 * CB * (n + 1) * 8; }
+static_assert((NBIG_MAX + 1 + 15) / 16 <= 32, "row-block flags of a sub-block hold 32 entries");
+static_assert(chol_panel_lds_bytes(NBIG_MAX) <= 160 * 1024 && chol_big_lds_bytes(NBIG_MAX) <= 160 * 1024,
+              "the largest reduced system fits the LDS of a workgroup");
 
 // One 64 x 64 tile of the augmented system of window w, summed from the chunk
 // partials in chunk order (the order of the small-window gather):
