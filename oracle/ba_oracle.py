@@ -368,23 +368,15 @@ def normal_blocks(poses, depth, P: Dict, lam: float, z_min: float = 0.1):
     return Hpp, Hpd_full[fr], hdd, gfull[fr], gd, lin
 
 
-def gn_step_schur(poses, depth, P: Dict, lam: float = 1e-4, z_min: float = 0.1,
-                  round_system=None):
+def gn_step_schur(poses, depth, P: Dict, lam: float = 1e-4, z_min: float = 0.1):
     """The Gauss-Newton step of `gn_step`, with the depths eliminated first
     (the Schur complement of Sec. 3.1, an exact identity since the depth block
     is diagonal):
       S = Hpp - Hpd diag(hdd)^-1 Hpd^T,   s = gp - Hpd (gd / hdd),
-      dxi = -S^-1 s (library Cholesky),   dd = -(gd + Hpd^T dxi) / hdd.
-    `round_system` (a torch dtype, e.g. torch.float32) rounds S and s once to
-    that precision before the solve: the step of a pipeline whose reduced
-    system is exact up to one rounding, which measures how strongly the
-    window's conditioning amplifies the rounding of the assembly."""
+      dxi = -S^-1 s (library Cholesky),   dd = -(gd + Hpd^T dxi) / hdd."""
     Hpp, Hpd, hdd, gp, gd, lin = normal_blocks(poses, depth, P, lam, z_min)
     S = Hpp - (Hpd / hdd) @ Hpd.T
     s = gp - Hpd @ (gd / hdd)
-    if round_system is not None:
-        S = S.to(round_system).to(DT)
-        s = s.to(round_system).to(DT)
     nf = P["n_fixed"]
     N = poses.shape[0]
     if S.shape[0] > 0:
@@ -398,13 +390,12 @@ def gn_step_schur(poses, depth, P: Dict, lam: float = 1e-4, z_min: float = 0.1,
     return poses, depth + dd, dict(S=S, s=s)
 
 
-def solve_schur(w, iterations: int = 2, lam: float = 1e-4, z_min: float = 0.1,
-                round_system=None):
+def solve_schur(w, iterations: int = 2, lam: float = 1e-4, z_min: float = 0.1):
     """K steps of `gn_step_schur` (for windows too large for the dense H).
     Returns (poses [N,7] numpy, inverse depths [M] numpy)."""
     P = to_problem(w)
     with torch.no_grad():
         poses, depth = P["poses"], P["depth"]
         for _ in range(iterations):
-            poses, depth, _ = gn_step_schur(poses, depth, P, lam, z_min, round_system)
+            poses, depth, _ = gn_step_schur(poses, depth, P, lam, z_min)
     return poses.numpy(), depth.numpy()

@@ -8,6 +8,7 @@ import torch
 from oracle import ba_oracle as O
 from paper_2208_04726_amd import synth
 from tests.gpu_util import compare, need_gpu, solve_gpu
+from tests.rounding import solve_schur_rounded
 
 pytestmark = pytest.mark.gpu
 
@@ -23,7 +24,7 @@ def fp32_tolerance(w, iterations=2, factor=10.0):
     numbers near 1e7 (scale drift along the trajectory), where FP32 rounding of
     S alone moves the poses by more than 1e-4 m."""
     pr, dr = O.solve_schur(w, iterations=iterations)
-    p32, d32 = O.solve_schur(w, iterations=iterations, round_system=torch.float32)
+    p32, d32 = solve_schur_rounded(w, iterations=iterations)
     dc, drot, dd = compare(p32, d32, pr, dr)
     return (max(FP32_TOL[0], factor * dc), max(FP32_TOL[1], factor * drot), max(FP32_TOL[2], factor * dd))
 

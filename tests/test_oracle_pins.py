@@ -347,9 +347,17 @@ def test_visible_edges_stay_in_front_of_camera():
 
 
 # ---------------------------------------------------------------- gradients
+def _fd_floor(magnitude, h):
+    """Absolute error floor of a central difference of a function whose terms
+    sum to `magnitude` in absolute value: the FP64 rounding of each of the two
+    evaluations, over the step 2h, with a margin of 10."""
+    return 10.0 * np.finfo(np.float64).eps * magnitude / h
+
+
 def test_gradient_vs_central_differences():
     """Autograd of the K-step map against FP64 central differences (step 1e-6)
-    on the 6 x 8 sub-window, for a spread of targets and weights."""
+    on the 6 x 8 sub-window, entry by entry: relative 1e-5 above the rounding
+    floor of the difference quotient."""
     w = synth.gradient_subwindow(0)
     L0, gy, gw = O.translation_loss_grad(w)
     rng = np.random.default_rng(0)
@@ -360,17 +368,18 @@ def test_gradient_vs_central_differences():
     def loss(wx):
         p, _ = O.solve(wx)
         c = synth.camera_centres(p[wx.n_fixed:]) - synth.camera_centres(wx.poses_gt[wx.n_fixed:])
-        return float((c ** 2).sum())
+        return float((c ** 2).sum()), float(np.abs(synth.camera_centres(p)).sum())
 
-    scale_y, scale_w = np.abs(gy).max(), np.abs(gw).max()
+    _, mag = loss(w)
+    floor = _fd_floor(4 * mag * np.sqrt(L0), h)
     for e in picks:
         for c in range(2):
-            for which, g, scale in (("targets", gy, scale_y), ("weights", gw, scale_w)):
+            for which, g in (("targets", gy), ("weights", gw)):
                 wp, wm = w.copy(), w.copy()
                 getattr(wp, which)[e, c] += h
                 getattr(wm, which)[e, c] -= h
-                fd = (loss(wp) - loss(wm)) / (2 * h)
-                assert abs(fd - g[e, c]) < 1e-4 * scale + 1e-4 * abs(fd), (which, e, c, fd, g[e, c])
+                fd = (loss(wp)[0] - loss(wm)[0]) / (2 * h)
+                assert abs(fd - g[e, c]) < 1e-5 * abs(fd) + floor, (which, e, c, fd, g[e, c], floor)
 
 
 def test_gradient_directional_at_method_scale():
@@ -435,13 +444,125 @@ def test_schur_depth_only_equals_dense():
     assert np.array_equal(pd, ps) and np.abs(dd - ds).max() < 1e-12
 
 
-def test_schur_rounded_system_is_a_perturbation():
-    """Rounding the reduced system to FP32 moves a well-conditioned solve by
-    little, and leaves FP64 rounding an identity."""
+# ---------------------------------------------------------------- reduced system and VJP
+@pytest.mark.parametrize("shape", [(4, 3, 2, 2), (5, 4, 3, 2), (6, 3, 5, 3)])
+def test_reduced_system_vs_bruteforce(shape):
+    """S and s against the brute-force normal equations (finite-difference
+    Jacobians over every unknown, numpy): by the block-inverse identity the
+    pose block of H^-1 is S^-1, and the pose part of the step solves
+    S dxi = -s."""
+    N, ppf, r, nf = shape
+    w = synth.make_window(N, ppf, r, seed=[12, N], n_fixed=nf, outlier_frac=0.2)
+    delta_bf, H_bf, _ = _bruteforce_step(w)
+    n_pose = 6 * (N - nf)
+    S_bf = np.linalg.inv(np.linalg.inv(H_bf)[:n_pose, :n_pose])
+    s_bf = -S_bf @ delta_bf[:n_pose]
+    S, s = O.reduced_system(w)
+    assert np.abs(S - S_bf).max() < 1e-8 * np.abs(S_bf).max()
+    assert np.abs(s - s_bf).max() < 1e-8 * np.abs(s_bf).max()
+    assert np.allclose(S, S.T, rtol=0, atol=1e-14 * np.abs(S).max())
+
+
+@pytest.mark.parametrize("which", ["small", "method"])
+def test_reduced_system_equals_block_elimination(which):
+    """The two routes to the reduced system agree: the explicit inverse of the
+    dense depth block (reduced_system) and the diagonal depth block of the
+    block-eliminated step (gn_step_schur); and -S^-1 s is the pose part of the
+    dense Gauss-Newton step."""
+    w = synth.plain_fp64_window(2) if which == "small" else synth.method_scale_window(3)
+    S, s = O.reduced_system(w)
+    P = O.to_problem(w)
+    _, _, info = O.gn_step_schur(P["poses"], P["depth"], P)
+    assert np.abs(S - info["S"].numpy()).max() < 1e-12 * np.abs(S).max()
+    assert np.abs(s - info["s"].numpy()).max() < 1e-12 * np.abs(s).max()
+    if which == "small":
+        _, _, dense = O.gn_step(P["poses"], P["depth"], P)
+        dx = -np.linalg.solve(S, s)
+        ref = dense["delta"].numpy()[:S.shape[0]]
+        assert np.abs(dx - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_cotangent_grad_vs_central_differences():
+    """The vector-Jacobian product of the K-step map for random cotangents of
+    the output poses and depths, against FP64 central differences (step 1e-6)
+    of f = <poses_out, g_p> + <depth_out, g_d> on the 6 x 8 sub-window: entry
+    by entry (relative 1e-6 above the rounding floor of f) and along a random
+    direction."""
+    w = synth.gradient_subwindow(0)
+    rng = np.random.default_rng(3)
+    gp = rng.normal(size=(w.n_frames, 7))
+    gd = rng.normal(size=w.n_patches)
+    gy, gw = O.cotangent_grad(w, gp, gd)
+    h = 1e-6
+
+    def f(wx):
+        p, d = O.solve(wx)
+        return float((p * gp).sum() + (d * gd).sum()), float(np.abs(p * gp).sum() + np.abs(d * gd).sum())
+
+    _, mag = f(w)
+    floor = _fd_floor(mag, h)
+    act = np.nonzero((w.anchor[w.kk] != w.jj) & (w.weights[:, 0] > 0))[0]
+    for e in rng.choice(act, 16, replace=False):
+        for c in range(2):
+            for which, g in (("targets", gy), ("weights", gw)):
+                wp, wm = w.copy(), w.copy()
+                getattr(wp, which)[e, c] += h
+                getattr(wm, which)[e, c] -= h
+                fd = (f(wp)[0] - f(wm)[0]) / (2 * h)
+                assert abs(fd - g[e, c]) < 1e-6 * abs(fd) + floor, (which, e, c, fd, g[e, c], floor)
+    # entries of hidden (zero-weight) edges: the targets do not enter the cost
+    hidden = np.nonzero(w.weights[:, 0] == 0)[0]
+    assert len(hidden) == 0 or np.abs(gy[hidden]).max() == 0.0
+    uy = rng.normal(size=gy.shape) * (w.weights > 0)
+    uw = rng.normal(size=gw.shape) * (w.weights > 0) * 0.01
+
+    def along(s):
+        wx = w.copy()
+        wx.targets = w.targets + s * uy
+        wx.weights = w.weights + s * uw
+        return f(wx)[0]
+
+    fd = (along(h) - along(-h)) / (2 * h)
+    an = float((gy * uy).sum() + (gw * uw).sum())
+    assert abs(fd - an) < 1e-6 * abs(an) + floor, (fd, an)
+
+
+def test_cotangent_grad_of_the_loss_is_the_loss_gradient():
+    """cotangent_grad with the cotangent dL/d(poses) of the translation loss
+    (formed by finite differences of L in each pose entry) reproduces the
+    loss gradient of translation_loss_grad."""
+    w = synth.gradient_subwindow(1)
+    L0, gy_ref, gw_ref = O.translation_loss_grad(w)
+    p, _ = O.solve(w)
+    nf = w.n_fixed
+    c_gt = synth.camera_centres(w.poses_gt[nf:])
+
+    def L(pp):
+        return float(((synth.camera_centres(pp[nf:]) - c_gt) ** 2).sum())
+
+    gp = np.zeros_like(p)
+    h = 1e-7
+    for a in range(nf, w.n_frames):
+        for m in range(7):
+            pp, pm = p.copy(), p.copy()
+            pp[a, m] += h
+            pm[a, m] -= h
+            gp[a, m] = (L(pp) - L(pm)) / (2 * h)
+    gy, gw = O.cotangent_grad(w, gp, np.zeros(w.n_patches))
+    assert np.abs(gy - gy_ref).max() < 1e-6 * np.abs(gy_ref).max()
+    assert np.abs(gw - gw_ref).max() < 1e-6 * np.abs(gw_ref).max()
+
+
+def test_rounding_aid_without_rounding_is_the_oracle():
+    """The FP32 tests' tolerance aid (tests/rounding.py) reproduces the
+    oracle's block-eliminated solve bit for bit when it rounds to FP64, and
+    rounding the reduced system to FP32 moves a well-conditioned 22 x 96
+    solve by a small, non-zero amount."""
+    from tests.rounding import solve_schur_rounded
     w = synth.method_scale_window(1)
     p0, d0 = O.solve_schur(w)
-    p1, d1 = O.solve_schur(w, round_system=torch.float64)
+    p1, d1 = solve_schur_rounded(w, dtype=torch.float64)
     assert np.array_equal(p0, p1) and np.array_equal(d0, d1)
-    p2, d2 = O.solve_schur(w, round_system=torch.float32)
+    p2, _ = solve_schur_rounded(w, dtype=torch.float32)
     dc, dr = synth.pose_errors(p2, p0)
     assert 0 < dc < 1e-4 and dr < 1e-2
