@@ -213,7 +213,8 @@ void ba_destroy(ba_handle* h);
 /* Inspection entry point for tests: the depth-eliminated pose system of
  * window `window` at the input state, S (n x n, full symmetric, row-major)
  * and s (n), n = 6 (frames - n_fixed), written to dev f64 buffers.  It runs
- * the same linearisation and Schur kernels as ba_solve. */
+ * the same linearisation and Schur kernel variant that ba_solve selects for
+ * the batch. */
 int ba_debug_reduced_system(ba_handle* h, const ba_problem* p, int32_t window,
                             double* S_out, double* s_out, void* stream);
 

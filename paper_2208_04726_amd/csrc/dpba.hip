@@ -938,9 +938,17 @@ int ba_debug_reduced_system(ba_handle* h, const ba_problem* p, int32_t window, d
   else hipLaunchKernelGGL(k_prep<double>, dim3(pl.W), dim3(WG), 0, s, P);
   HIPCHK(h, hipGetLastError());
   if (pl.C > 0) {
-    const int al = asm_layout(pl.Rcap, esz, 8).total;
-    if (f32) hipLaunchKernelGGL((k_assemble<float, 8>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
-    else hipLaunchKernelGGL((k_assemble<double, 8>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
+    // the accumulator-tile variant ba_solve selects for this batch
+    const int al = asm_layout(pl.Rcap, esz, pl.maxt).total;
+    if (f32) {
+      if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<float, 4>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
+      else if (pl.maxt == 5) hipLaunchKernelGGL((k_assemble<float, 5>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
+      else hipLaunchKernelGGL((k_assemble<float, 8>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
+    } else {
+      if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<double, 4>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
+      else if (pl.maxt == 5) hipLaunchKernelGGL((k_assemble<double, 5>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
+      else hipLaunchKernelGGL((k_assemble<double, 8>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
+    }
     HIPCHK(h, hipGetLastError());
   }
   const int nw = 6 * (int)(p->frame_off[window + 1] - p->frame_off[window] - p->n_fixed[window]);

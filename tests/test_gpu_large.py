@@ -72,7 +72,8 @@ def test_reduced_system_372_matches_oracle():
     rel_S = np.abs(S - S_ref).max() / np.abs(S_ref).max()
     rel_s = np.abs(sv - s_ref).max() / np.abs(s_ref).max()
     print(f"S rel {rel_S:.2e} s rel {rel_s:.2e}")
-    assert rel_S < 2e-4 and rel_s < 2e-4
+    # 16 patches per source frame: n <= 48 FP32 roundings, gamma_n = 2.9e-6 (see test_gpu_parity)
+    assert rel_S < 1e-5 and rel_s < 1e-5
 
 
 def test_372_solve_is_the_solution_of_its_system():

@@ -13,6 +13,12 @@ pytestmark = pytest.mark.gpu
 # FP32 assembly with FP64 Cholesky: 1e-4 m / 1e-2 deg; inverse depth relative.
 FP64_TOL = (1e-6, 1e-4, 1e-6)
 FP32_TOL = (1e-4, 1e-2, 1e-3)
+# FP32 reduced system, relative to its largest entry: the longest FP32
+# summation before the per-source-frame FP64 fold adds one term per patch of
+# the source frame (96) plus the 16-lane segment tree and the table folds, so
+# n <= 128 roundings and the bound gamma_n = n u / (1 - n u) (u = 2^-24) is
+# 7.6e-6 of the summed magnitudes, rounded up to 1e-5.
+FP32_SYSTEM_REL = 1e-5
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -42,7 +48,7 @@ def test_reduced_system_matches_oracle(precision, win):
     torch.cuda.synchronize()
     S_ref, s_ref = O.reduced_system(w)
     S, sv = S.cpu().numpy(), sv.cpu().numpy()
-    rel = 1e-10 if precision == "fp64" else 2e-4
+    rel = 1e-10 if precision == "fp64" else FP32_SYSTEM_REL
     print("S rel err", np.abs(S - S_ref).max() / np.abs(S_ref).max(),
           "s rel err", np.abs(sv - s_ref).max() / np.abs(s_ref).max())
     assert np.abs(S - S_ref).max() <= rel * np.abs(S_ref).max()
