@@ -173,6 +173,30 @@ int ba_backward(ba_handle* h, const ba_problem* p, const double* grad_poses,
 int ba_prepare(ba_handle* h, const ba_problem* p, void* stream);
 int ba_launch(ba_handle* h, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ba_solve
+ * without a handle.  Same problem, same kernels and the same results as
+ * ba_solve with a handle created from *cfg (bitwise, when the chunking below
+ * is the same).  The capacity fields of *cfg (max_*) are ignored: the
+ * workspace is sized for this batch and carved from a static device array of
+ * 64 MiB that each GPU the library runs on holds until the process ends
+ * (about 16 windows of 22 frames x 96 patches, or one of 64 frames x 256
+ * patches).  A batch beyond it, more than 256 windows, more than 64 frames in
+ * a window (24 in BA_PREC_FP64) or more than 4096 chunks returns
+ * BA_E_CAPACITY before anything is enqueued; with chunk_frames = 0 the
+ * chunking is that of ba_solve, coarsened until the chunk partials fit.
+ * Nothing is allocated: no hipMalloc, hipFree, or host allocation.  Argument
+ * errors return BA_E_INVAL as for ba_solve; there is no handle, so no
+ * message is kept.
+ * status_out: dev [W] int32, may be NULL: the per-window BA_W_* bits, written
+ * on `stream` after the solve.
+ * Every call on a GPU uses that GPU's one workspace, which keeps the last
+ * call's contents: calls whose device work overlaps on one GPU (different
+ * streams, or host threads) race and give undefined results; calls in
+ * sequence on one stream are safe.  The host part of concurrent calls is
+ * serialised per device. */
+int ba_solve_noalloc(const ba_config* cfg, const ba_problem* p, int32_t* status_out, void* stream);
+
 /* Kernel stages, for ba_kernel_times. */
 enum {
   BA_STAGE_PREP = 0,      /* graph validation and ordering                       */

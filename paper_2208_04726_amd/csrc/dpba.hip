@@ -3,9 +3,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/dpba.h"
@@ -173,6 +174,28 @@ __global__ void k_debug_mfma(const T* A, const T* B, T* D) {
   for (int r = 0; r < 4; ++r) D[acc_row(T(0), l >> 4, r) * 16 + (l & 15)] = acc[r];
 }
 
+// Allocation-free path: descriptor words carried in the kernel arguments
+// (copied by the runtime at launch, so no host buffer has to outlive the
+// call) and stored into the static workspace.
+constexpr int UPLOAD_WORDS = 992;
+struct UploadBlock {
+  int64_t dst;   // byte offset from the workspace base
+  int32_t n;     // words
+  int32_t pad;
+  uint32_t w[UPLOAD_WORDS];
+};
+static_assert(sizeof(UploadBlock) + sizeof(char*) <= 4096, "kernel arguments must stay within 4 KB");
+static_assert(sizeof(WinDesc) % 4 == 0 && sizeof(ChunkDesc) % 4 == 0, "descriptors are uploaded as 32-bit words");
+
+__global__ void __launch_bounds__(256) k_upload(char* base, UploadBlock b) {
+  uint32_t* d = (uint32_t*)(base + b.dst);
+  for (int i = threadIdx.x; i < b.n; i += 256) d[i] = b.w[i];
+}
+
+__global__ void __launch_bounds__(256) k_copy_status(const int32_t* status, int32_t* out, int n) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) out[i] = status[i];
+}
+
 // ---------------------------------------------------------------------------
 // handle
 struct ba_handle {
@@ -212,13 +235,20 @@ struct ba_handle {
   int timing = 0;   // mask of timed stages
   std::vector<hipEvent_t> ev_pool;
   std::vector<TimedLaunch> timed;
-  std::string err;
+  char err[256] = {0};
 };
 
 namespace {
 
-int fail(ba_handle* h, int code, const std::string& msg) {
-  if (h) h->err = msg;
+// Records the message of an error on the handle (formatted into its fixed
+// buffer: no host allocation on any path) and returns `code`.
+int fail(ba_handle* h, int code, const char* fmt, ...) {
+  if (h) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(h->err, sizeof(h->err), fmt, ap);
+    va_end(ap);
+  }
   return code;
 }
 
@@ -226,7 +256,7 @@ int fail(ba_handle* h, int code, const std::string& msg) {
   do {                                                                                \
     hipError_t _e = (call);                                                           \
     if (_e != hipSuccess)                                                             \
-      return fail(h, BA_E_HIP, std::string(#call) + ": " + hipGetErrorString(_e));    \
+      return fail(h, BA_E_HIP, "%s: %s", #call, hipGetErrorString(_e));                 \
   } while (0)
 
 template <typename T>
@@ -288,6 +318,86 @@ struct KernelTimer {
   }
 };
 
+// Chunk and partial-block capacities of a handle from its configuration.
+// Chunks per call: the split schedule's chunking gives at most n_cu + W
+// (about n_cu groups of source frames, plus one partial group per window),
+// or F / chunk_frames + W with fixed chunking; the fused schedule one per
+// window.  The capacity-sized launches of ba_launch use this bound.
+void set_capacities(ba_handle* h) {
+  const ba_config* cfg = &h->cfg;
+  const int64_t W = cfg->max_windows, F = cfg->max_frames;
+  const int64_t Dmax = 6LL * cfg->max_frames_per_window;
+  int64_t cap_c = std::min<int64_t>(F, (int64_t)h->n_cu + W);
+  if (cfg->chunk_frames > 0) cap_c = std::min<int64_t>(F, (F + cfg->chunk_frames - 1) / cfg->chunk_frames + W);
+  h->cap_chunks = std::max<int64_t>(cap_c, W);
+  // partial blocks: one chunk per window, and about two chunks per CU across
+  // the batch (or the fixed chunking)
+  int64_t blocks = std::max<int64_t>(W, std::min<int64_t>(F, 2LL * h->n_cu));
+  if (cfg->chunk_frames > 0)
+    blocks = std::max(blocks, std::min<int64_t>(F, W * ((cfg->max_frames_per_window + cfg->chunk_frames - 1) /
+                                                          cfg->chunk_frames)));
+  h->cap_partial = blocks * (Dmax * Dmax + 2 * Dmax);
+}
+
+// Every device buffer of a handle's workspace except the chunk partials,
+// sized from its capacities; `take(&ptr, bytes)` provides each one.
+template <class Take>
+void carve_workspace(ba_handle* h, Take take) {
+  const ba_config* cfg = &h->cfg;
+  const int64_t W = cfg->max_windows, F = cfg->max_frames, Pn = std::max<int64_t>(cfg->max_patches, 1),
+                E = std::max<int64_t>(cfg->max_edges, 1);
+  const size_t esz = cfg->precision == BA_PREC_FP32 ? 4 : 8;
+  take((void**)&h->d_win, sizeof(WinDesc) * W);
+  take((void**)&h->d_chunk, sizeof(ChunkDesc) * h->cap_chunks);
+  take((void**)&h->d_counts, 16);
+  take((void**)&h->status, 4 * W);
+  take((void**)&h->wmeta, 16 * W);
+  take((void**)&h->cnt, 4 * Pn);
+  take((void**)&h->ptr, 4 * Pn);
+  take((void**)&h->fill, 4 * Pn);
+  take((void**)&h->acnt, 4 * (F + W));
+  take((void**)&h->afill, 4 * F);
+  take((void**)&h->plist, 4 * Pn);
+  take((void**)&h->csr, 4 * E);
+  take((void**)&h->arange, 8 * F);
+  take((void**)&h->cstate, 8 * h->cap_chunks);
+  if (6 * cfg->max_frames_per_window > NCHOL_MAX) {
+    h->ld_big = big_ld(cfg->max_frames_per_window);
+    take((void**)&h->s_big, 8 * (size_t)W * h->ld_big * h->ld_big);
+    take((void**)&h->big_aux, 8 * (size_t)W * big_aux_stride(h->ld_big));
+  }
+  take((void**)&h->dxi, 8 * 6 * F);
+  const int64_t slots = cfg->iterations + 1;
+  take((void**)&h->pose_buf, 8 * slots * 7 * F);
+  take((void**)&h->depth_buf, 8 * slots * Pn);
+  take((void**)&h->gidx, 4 * E);
+  take((void**)&h->xib, 8 * 6 * F);
+  take((void**)&h->xid, 8 * 6 * F);
+  take((void**)&h->qxi, 8 * 6 * F);
+  take((void**)&h->dbar, 8 * 2 * Pn);
+  take((void**)&h->fcot, 8 * RMAX * 6 * h->cap_chunks);
+  h->cap_sb = Pn / 16 + F + 2 * W;
+  take((void**)&h->estart, 4 * (Pn + W));
+  take((void**)&h->sbstart, 4 * (F + W));
+  take((void**)&h->sbd, 16 * h->cap_sb);
+  take(&h->pxy, 16 * Pn);
+  take((void**)&h->gj, 4 * E);
+  take(&h->gt, 2 * esz * E);
+  take(&h->gw, 2 * esz * E);
+}
+
+// Host-side checks of a configuration shared by ba_create and
+// ba_solve_noalloc (capacities excepted).
+int check_config_numerics(const ba_config* cfg) {
+  if (!cfg) return BA_E_INVAL;
+  if (cfg->precision != BA_PREC_FP64 && cfg->precision != BA_PREC_FP32) return BA_E_INVAL;
+  if (cfg->iterations < 0 || cfg->iterations > 64) return BA_E_INVAL;
+  if (!(cfg->lambda >= 0.0) || !std::isfinite(cfg->lambda) || !std::isfinite(cfg->z_min)) return BA_E_INVAL;
+  if (cfg->schedule < 0 || cfg->schedule > 2) return BA_E_INVAL;
+  if (cfg->chunk_frames < 0) return BA_E_INVAL;
+  return BA_OK;
+}
+
 // Accumulator tiles per wave: the smallest instantiated count that holds a
 // chunk's lower-triangle tiles in one pass (larger chunks take several passes
 // with 8).
@@ -323,14 +433,14 @@ int validate_and_plan(ba_handle* h, const ba_problem* p, Plan& pl) {
     const int64_t E = p->edge_off[w + 1] - p->edge_off[w];
     if (N < 0 || M < 0 || E < 0) return fail(h, BA_E_INVAL, "offsets must be non-decreasing");
     if (N > cfg.max_frames_per_window)
-      return fail(h, BA_E_CAPACITY, "window " + std::to_string(w) + " has more frames than max_frames_per_window");
+      return fail(h, BA_E_CAPACITY, "window %d has more frames than max_frames_per_window", w);
     if (M > INT32_MAX / 2 || E > INT32_MAX / 2) return fail(h, BA_E_CAPACITY, "window too large");
     const int nf = p->n_fixed[w];
-    if (nf < 0 || nf > N) return fail(h, BA_E_INVAL, "n_fixed outside [0, frames] in window " + std::to_string(w));
+    if (nf < 0 || nf > N) return fail(h, BA_E_INVAL, "n_fixed outside [0, frames] in window %d", w);
     const int n = 6 * (int)(N - nf);
     if (n > NCHOL_MAX) {
       if (!h->s_big)
-        return fail(h, BA_E_CAPACITY, "window " + std::to_string(w) + ": more than 21 free frames");
+        return fail(h, BA_E_CAPACITY, "window %d: more than 21 free frames", w);
       pl.big = true;
     }
     pl.nmax = std::max(pl.nmax, n);
@@ -623,6 +733,67 @@ int launch_backward(ba_handle* h, const ba_problem* p, const Plan& pl, const dou
   return BA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free solve.  The workspace of ba_solve_noalloc is carved, per
+// call, from `scratch`, a device array of fixed size: each GPU the library
+// runs on holds its own copy until the process ends.  Host code never uses
+// the array's name as an address: its device address is taken once per device
+// with hipGetSymbolAddress and kept in `NoallocDevice::base`.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;   // 64 MiB per GPU
+constexpr int NOALLOC_MAX_DEVICES = 16;
+constexpr int NOALLOC_MAX_WINDOWS = 256;
+constexpr int NOALLOC_MAX_CHUNKS = 4096;
+
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+struct NoallocDevice {
+  std::mutex mu;                 // one call at a time per device on the host side
+  bool ready = false;
+  char* base = nullptr;          // device address of `scratch` on this device
+  ba_handle h;                   // workspace pointers into `scratch`, no allocation
+  WinDesc hwin[NOALLOC_MAX_WINDOWS];
+  ChunkDesc hchunk[NOALLOC_MAX_CHUNKS];
+  int32_t hcounts[4];
+};
+
+NoallocDevice g_noalloc[NOALLOC_MAX_DEVICES];
+
+// Once per device, with the device current: the address of its copy of
+// `scratch`, the CU count, the kernels' LDS limits.
+int noalloc_init(NoallocDevice& D, int dev) {
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) return BA_E_HIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return BA_E_HIP;
+  if (set_kernel_attrs<float>() != 0 || set_kernel_attrs<double>() != 0) return BA_E_HIP;
+  D.base = (char*)ptr;
+  D.h.device = dev;
+  D.h.n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  D.h.h_win = D.hwin;
+  D.h.h_chunk = D.hchunk;
+  D.h.h_counts = D.hcounts;
+  D.ready = true;
+  return BA_OK;
+}
+
+// Stores `bytes` (a multiple of 4) from host `src` at device `dst` inside the
+// workspace, through the arguments of k_upload launches on `s`.
+int noalloc_upload(ba_handle* h, char* base, void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const size_t words = bytes / 4;
+  const int64_t off = (int64_t)((char*)dst - base);
+  UploadBlock b;
+  for (size_t w0 = 0; w0 < words; w0 += UPLOAD_WORDS) {
+    const int n = (int)std::min<size_t>(UPLOAD_WORDS, words - w0);
+    b.dst = off + 4 * (int64_t)w0;
+    b.n = n;
+    b.pad = 0;
+    memcpy(b.w, (const char*)src + 4 * w0, 4 * (size_t)n);
+    hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, s, base, b);
+    HIPCHK(h, hipGetLastError());
+  }
+  return BA_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -632,16 +803,11 @@ extern "C" {
 int ba_create(const ba_config* cfg, ba_handle** out) {
   if (!out) return BA_E_INVAL;
   *out = nullptr;
-  if (!cfg) return BA_E_INVAL;
-  if (cfg->precision != BA_PREC_FP64 && cfg->precision != BA_PREC_FP32) return BA_E_INVAL;
-  if (cfg->iterations < 0 || cfg->iterations > 64) return BA_E_INVAL;
-  if (!(cfg->lambda >= 0.0) || !std::isfinite(cfg->lambda) || !std::isfinite(cfg->z_min)) return BA_E_INVAL;
-  if (cfg->schedule < 0 || cfg->schedule > 2) return BA_E_INVAL;
+  if (check_config_numerics(cfg) != BA_OK) return BA_E_INVAL;
   if (cfg->max_windows < 1 || cfg->max_frames_per_window < 1 || cfg->max_frames_per_window > RMAX)
     return BA_E_INVAL;
   if (cfg->precision == BA_PREC_FP64 && cfg->max_frames_per_window > 24) return BA_E_INVAL;
   if (cfg->max_frames < 1 || cfg->max_patches < 0 || cfg->max_edges < 0) return BA_E_INVAL;
-  if (cfg->chunk_frames < 0) return BA_E_INVAL;
 
   ba_handle* h = new ba_handle();
   h->cfg = *cfg;
@@ -653,85 +819,28 @@ int ba_create(const ba_config* cfg, ba_handle** out) {
   const int r = cfg->precision == BA_PREC_FP32 ? set_kernel_attrs<float>() : set_kernel_attrs<double>();
   if (r != 0) return cleanup(BA_E_HIP);
 
-  const int64_t W = cfg->max_windows, F = cfg->max_frames, Pn = std::max<int64_t>(cfg->max_patches, 1),
-                E = std::max<int64_t>(cfg->max_edges, 1);
-  const int64_t Dmax = 6LL * cfg->max_frames_per_window;
-  const size_t esz = cfg->precision == BA_PREC_FP32 ? 4 : 8;
-  // chunks per call: the split schedule's chunking gives at most n_cu + W
-  // (about n_cu groups of source frames, plus one partial group per window),
-  // or F / chunk_frames + W with fixed chunking; the fused schedule one per
-  // window.  The capacity-sized launches of ba_launch use this bound.
-  {
-    int64_t cap_c = std::min<int64_t>(F, (int64_t)h->n_cu + W);
-    if (cfg->chunk_frames > 0) cap_c = std::min<int64_t>(F, (F + cfg->chunk_frames - 1) / cfg->chunk_frames + W);
-    h->cap_chunks = std::max<int64_t>(cap_c, W);
-  }
-  {
-    // partial blocks: one chunk per window, and about two chunks per CU
-    // across the batch (or the fixed chunking)
-    int64_t blocks = std::max<int64_t>(W, std::min<int64_t>(F, 2LL * h->n_cu));
-    if (cfg->chunk_frames > 0)
-      blocks = std::max(blocks, std::min<int64_t>(F, W * ((cfg->max_frames_per_window + cfg->chunk_frames - 1) /
-                                                            cfg->chunk_frames)));
-    h->cap_partial = blocks * (Dmax * Dmax + 2 * Dmax);
-  }
+  set_capacities(h);
   h->launch_fused = cfg->schedule == BA_SCHED_FUSED;
   bool ok = true;
   auto dmalloc = [&](void** ptr, size_t bytes) {
     if (!ok) return;
     if (hipMalloc(ptr, std::max<size_t>(bytes, 256)) != hipSuccess) ok = false;
   };
-  dmalloc((void**)&h->d_win, sizeof(WinDesc) * W);
-  dmalloc((void**)&h->d_chunk, sizeof(ChunkDesc) * h->cap_chunks);
-  dmalloc((void**)&h->d_counts, 16);
-  dmalloc((void**)&h->status, 4 * W);
-  dmalloc((void**)&h->wmeta, 16 * W);
-  dmalloc((void**)&h->cnt, 4 * Pn);
-  dmalloc((void**)&h->ptr, 4 * Pn);
-  dmalloc((void**)&h->fill, 4 * Pn);
-  dmalloc((void**)&h->acnt, 4 * (F + W));
-  dmalloc((void**)&h->afill, 4 * F);
-  dmalloc((void**)&h->plist, 4 * Pn);
-  dmalloc((void**)&h->csr, 4 * E);
-  dmalloc((void**)&h->arange, 8 * F);
-  dmalloc((void**)&h->cstate, 8 * h->cap_chunks);
+  carve_workspace(h, dmalloc);
   dmalloc((void**)&h->partial, 8 * h->cap_partial);
-  if (6 * cfg->max_frames_per_window > NCHOL_MAX) {
-    h->ld_big = big_ld(cfg->max_frames_per_window);
-    dmalloc((void**)&h->s_big, 8 * (size_t)W * h->ld_big * h->ld_big);
-    dmalloc((void**)&h->big_aux, 8 * (size_t)W * big_aux_stride(h->ld_big));
-  }
-  dmalloc((void**)&h->dxi, 8 * 6 * F);
-  const int64_t slots = cfg->iterations + 1;
-  dmalloc((void**)&h->pose_buf, 8 * slots * 7 * F);
-  dmalloc((void**)&h->depth_buf, 8 * slots * Pn);
-  dmalloc((void**)&h->gidx, 4 * E);
-  dmalloc((void**)&h->xib, 8 * 6 * F);
-  dmalloc((void**)&h->xid, 8 * 6 * F);
-  dmalloc((void**)&h->qxi, 8 * 6 * F);
-  dmalloc((void**)&h->dbar, 8 * 2 * Pn);
-  dmalloc((void**)&h->fcot, 8 * RMAX * 6 * h->cap_chunks);
-  h->cap_sb = Pn / 16 + F + 2 * W;
-  dmalloc((void**)&h->estart, 4 * (Pn + W));
-  dmalloc((void**)&h->sbstart, 4 * (F + W));
-  dmalloc((void**)&h->sbd, 16 * h->cap_sb);
-  dmalloc(&h->pxy, 16 * Pn);
-  dmalloc((void**)&h->gj, 4 * E);
-  dmalloc(&h->gt, 2 * esz * E);
-  dmalloc(&h->gw, 2 * esz * E);
   if (!ok) return cleanup(BA_E_HIP);
-  if (hipHostMalloc((void**)&h->h_win, sizeof(WinDesc) * W) != hipSuccess) return cleanup(BA_E_HIP);
+  if (hipHostMalloc((void**)&h->h_win, sizeof(WinDesc) * cfg->max_windows) != hipSuccess) return cleanup(BA_E_HIP);
   if (hipHostMalloc((void**)&h->h_chunk, sizeof(ChunkDesc) * h->cap_chunks) != hipSuccess) return cleanup(BA_E_HIP);
   if (hipHostMalloc((void**)&h->h_counts, 16) != hipSuccess) return cleanup(BA_E_HIP);
   if (hipEventCreateWithFlags(&h->staging_ev, hipEventDisableTiming) != hipSuccess) return cleanup(BA_E_HIP);
-  if (hipMemset(h->status, 0, 4 * W) != hipSuccess) return cleanup(BA_E_HIP);
+  if (hipMemset(h->status, 0, 4 * cfg->max_windows) != hipSuccess) return cleanup(BA_E_HIP);
   *out = h;
   return BA_OK;
 }
 
 int ba_solve(ba_handle* h, const ba_problem* p, void* stream) {
   if (!h) return BA_E_INVAL;
-  h->err.clear();
+  h->err[0] = 0;
   Plan pl;
   int r = validate_and_plan(h, p, pl);
   if (r != BA_OK) return r;
@@ -753,10 +862,92 @@ int ba_solve(ba_handle* h, const ba_problem* p, void* stream) {
                                           : launch_solve<double>(h, p, pl, s);
 }
 
+int ba_solve_noalloc(const ba_config* cfg, const ba_problem* p, int32_t* status_out, void* stream) {
+  if (check_config_numerics(cfg) != BA_OK || !p || p->n_windows < 0) return BA_E_INVAL;
+  const int W = p->n_windows;
+  if (W == 0) return BA_OK;
+  if (W > NOALLOC_MAX_WINDOWS) return BA_E_CAPACITY;
+  if (!p->frame_off || !p->patch_off || !p->edge_off || !p->n_fixed || !p->intrinsics) return BA_E_INVAL;
+  if (p->frame_off[0] != 0 || p->patch_off[0] != 0 || p->edge_off[0] != 0) return BA_E_INVAL;
+  int64_t rmax = 1;
+  for (int w = 0; w < W; ++w) {
+    const int64_t N = p->frame_off[w + 1] - p->frame_off[w];
+    if (N < 0 || p->patch_off[w + 1] < p->patch_off[w] || p->edge_off[w + 1] < p->edge_off[w]) return BA_E_INVAL;
+    rmax = std::max(rmax, N);
+  }
+  if (rmax > RMAX || (cfg->precision == BA_PREC_FP64 && rmax > 24)) return BA_E_CAPACITY;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return BA_E_HIP;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return BA_E_CAPACITY;
+  NoallocDevice& D = g_noalloc[dev];
+  std::lock_guard<std::mutex> lock(D.mu);
+  if (!D.ready) {
+    const int r = noalloc_init(D, dev);
+    if (r != BA_OK) return r;
+  }
+  ba_handle* h = &D.h;
+  h->err[0] = 0;
+  // capacities: exactly this batch
+  h->cfg = *cfg;
+  h->cfg.max_windows = W;
+  h->cfg.max_frames_per_window = (int32_t)rmax;
+  h->cfg.max_frames = std::max<int64_t>(1, p->frame_off[W]);
+  h->cfg.max_patches = p->patch_off[W];
+  h->cfg.max_edges = p->edge_off[W];
+  set_capacities(h);
+  h->cap_chunks = std::min<int64_t>(h->cap_chunks, NOALLOC_MAX_CHUNKS);
+  h->s_big = nullptr;
+  h->big_aux = nullptr;
+  h->ld_big = 0;
+  size_t off = 0;
+  bool fits = true;
+  auto take = [&](void** ptr, size_t bytes) {
+    const size_t b = (std::max<size_t>(bytes, 256) + 255) & ~size_t(255);
+    if (!fits || b > NOALLOC_SCRATCH_BYTES - off) {
+      fits = false;
+      *ptr = nullptr;
+      return;
+    }
+    *ptr = D.base + off;
+    off += b;
+  };
+  carve_workspace(h, take);
+  if (!fits) return fail(h, BA_E_CAPACITY, "batch exceeds the %zu-byte static workspace", NOALLOC_SCRATCH_BYTES);
+  // the chunk partials take the rest; the chunking grows when they do not fit
+  h->partial = (double*)(D.base + off);
+  h->cap_partial = (int64_t)((NOALLOC_SCRATCH_BYTES - off) / 8);
+  Plan pl;
+  int r = validate_and_plan(h, p, pl);
+  if (r != BA_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  int sched = cfg->schedule;
+  if (pl.big) {
+    if (sched == BA_SCHED_FUSED)
+      return fail(h, BA_E_CAPACITY, "the fused schedule holds at most 21 free frames per window");
+    sched = BA_SCHED_SPLIT;
+  }
+  r = build_descriptors(h, p, pl, sched);
+  if (r != BA_OK) return r;
+  h->h_counts[0] = pl.W;
+  h->h_counts[1] = pl.C;
+  h->h_counts[2] = h->h_counts[3] = 0;
+  r = noalloc_upload(h, D.base, h->d_counts, h->h_counts, 16, s);
+  if (r == BA_OK) r = noalloc_upload(h, D.base, h->d_win, h->h_win, sizeof(WinDesc) * pl.W, s);
+  if (r == BA_OK && pl.C > 0) r = noalloc_upload(h, D.base, h->d_chunk, h->h_chunk, sizeof(ChunkDesc) * pl.C, s);
+  if (r != BA_OK) return r;
+  r = cfg->precision == BA_PREC_FP32 ? launch_solve<float>(h, p, pl, s) : launch_solve<double>(h, p, pl, s);
+  if (r != BA_OK) return r;
+  if (status_out) {
+    hipLaunchKernelGGL(k_copy_status, dim3((W + 255) / 256), dim3(256), 0, s, (const int32_t*)h->status, status_out, W);
+    HIPCHK(h, hipGetLastError());
+  }
+  return BA_OK;
+}
+
 int ba_backward(ba_handle* h, const ba_problem* p, const double* grad_poses,
                 const double* grad_depth, void* grad_targets, void* grad_weights, void* stream) {
   if (!h) return BA_E_INVAL;
-  h->err.clear();
+  h->err[0] = 0;
   Plan pl;
   int r = validate_and_plan(h, p, pl);
   if (r != BA_OK) return r;
@@ -778,7 +969,7 @@ int ba_backward(ba_handle* h, const ba_problem* p, const double* grad_poses,
 
 int ba_prepare(ba_handle* h, const ba_problem* p, void* stream) {
   if (!h) return BA_E_INVAL;
-  h->err.clear();
+  h->err[0] = 0;
   h->prepared = false;
   Plan pl;
   int r = validate_and_plan(h, p, pl);
@@ -800,7 +991,7 @@ int ba_prepare(ba_handle* h, const ba_problem* p, void* stream) {
 int ba_launch(ba_handle* h, void* stream) {
   if (!h) return BA_E_INVAL;
   if (!h->prepared) return fail(h, BA_E_STATE, "ba_launch without ba_prepare");
-  h->err.clear();
+  h->err[0] = 0;
   hipStream_t s = (hipStream_t)stream;
   h->last_stream = s;
   Plan pl;
@@ -841,7 +1032,7 @@ int ba_kernel_times(ba_handle* h, double* ms_out, int32_t* launches_out) {
     if (rc == BA_OK) {
       hipError_t e = hipEventSynchronize(t.b);
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.a, t.b);
-      if (e != hipSuccess) rc = fail(h, BA_E_HIP, std::string("kernel timing: ") + hipGetErrorString(e));
+      if (e != hipSuccess) rc = fail(h, BA_E_HIP, "kernel timing: %s", hipGetErrorString(e));
     }
     if (rc == BA_OK && t.stage >= 0 && t.stage < BA_STAGE_COUNT) {
       ms_out[t.stage] += ms;
@@ -863,7 +1054,7 @@ int ba_status(ba_handle* h, int32_t* host_flags) {
   return BA_OK;
 }
 
-const char* ba_last_error(const ba_handle* h) { return h ? h->err.c_str() : "null handle"; }
+const char* ba_last_error(const ba_handle* h) { return h ? h->err : "null handle"; }
 
 void ba_destroy(ba_handle* h) {
   if (!h) return;
@@ -916,7 +1107,7 @@ void ba_destroy(ba_handle* h) {
 int ba_debug_reduced_system(ba_handle* h, const ba_problem* p, int32_t window, double* S_out,
                             double* s_out, void* stream) {
   if (!h) return BA_E_INVAL;
-  h->err.clear();
+  h->err[0] = 0;
   Plan pl;
   int r = validate_and_plan(h, p, pl);
   if (r != BA_OK) return r;

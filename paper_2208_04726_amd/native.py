@@ -19,7 +19,7 @@ BA_W_OK, BA_W_NOT_SPD, BA_W_NONFINITE, BA_W_BAD_INDEX, BA_W_DEGREE = 0, 1, 2, 4,
 
 EXPORTED = ("ba_create", "ba_solve", "ba_backward", "ba_prepare", "ba_launch", "ba_set_timing",
             "ba_kernel_times", "ba_status", "ba_last_error", "ba_destroy",
-            "ba_debug_reduced_system", "ba_debug_mfma")
+            "ba_debug_reduced_system", "ba_debug_mfma", "ba_solve_noalloc")
 STAGES = ("prep", "assemble", "chol", "backsub", "finalize", "fused")
 
 
@@ -79,6 +79,8 @@ def lib() -> ctypes.CDLL:
         L.ba_debug_reduced_system.restype = ctypes.c_int
         L.ba_debug_mfma.argtypes = [i32, vp, vp, vp, vp]
         L.ba_debug_mfma.restype = ctypes.c_int
+        L.ba_solve_noalloc.argtypes = [ctypes.POINTER(BAConfig), ctypes.POINTER(BAProblem), vp, vp]
+        L.ba_solve_noalloc.restype = ctypes.c_int
         _LIB = L
     return _LIB
 

@@ -270,3 +270,44 @@ class BAFunction(torch.autograd.Function):
             grad_depth = torch.zeros((ctx.batch.totals[1],), dtype=torch.float64, device=ctx.batch.poses.device)
         gt, gw = ctx.solver.backward(ctx.batch, grad_poses, grad_depth)
         return gt, gw, None, None
+
+
+def solve_noalloc(b: Batch, precision: str = "fp32", iterations: int = 2, lam: float = 1e-4,
+                  z_min: float = 0.1, schedule: str = "auto", chunk_frames: int = 0,
+                  poses_out: Optional[torch.Tensor] = None, depth_out: Optional[torch.Tensor] = None,
+                  status_out: Optional[torch.Tensor] = None, stream: Optional[torch.cuda.Stream] = None):
+    """ba_solve_noalloc: the solve without a handle, its workspace carved from
+    the library's static device array.  The output tensors must be supplied by
+    a caller that cannot allocate; when None they are allocated here (argument
+    marshalling only).  Returns (poses_out, depth_out, status_out [W] int32)."""
+    lib = native.lib()
+    cfg = BAConfig()
+    cfg.precision = PRECISIONS[precision]
+    cfg.iterations = iterations
+    cfg.lambda_ = lam
+    cfg.z_min = z_min
+    cfg.schedule = SCHEDULES[schedule]
+    cfg.chunk_frames = chunk_frames
+    F, P, _ = b.totals
+    dev = b.poses.device
+    if poses_out is None:
+        poses_out = torch.empty((F, 7), dtype=torch.float64, device=dev)
+    if depth_out is None:
+        depth_out = torch.empty((P,), dtype=torch.float64, device=dev)
+    if status_out is None:
+        status_out = torch.empty((max(b.n_windows, 1),), dtype=torch.int32, device=dev)
+    keep = [np.ascontiguousarray(b.frame_off, np.int64), np.ascontiguousarray(b.patch_off, np.int64),
+            np.ascontiguousarray(b.edge_off, np.int64), np.ascontiguousarray(b.n_fixed, np.int32),
+            np.ascontiguousarray(b.intrinsics, np.float64)]
+    p = BAProblem()
+    p.n_windows = b.n_windows
+    p.frame_off, p.patch_off, p.edge_off, p.n_fixed, p.intrinsics = [_host(a) for a in keep]
+    p.poses_in, p.patches_in = _ptr(b.poses), _ptr(b.patches)
+    p.anchor, p.kk, p.jj = _ptr(b.anchor), _ptr(b.kk), _ptr(b.jj)
+    p.targets, p.weights = _ptr(b.targets), _ptr(b.weights)
+    p.poses_out, p.depth_out = _ptr(poses_out), _ptr(depth_out)
+    s = (stream or torch.cuda.current_stream(dev)).cuda_stream
+    r = lib.ba_solve_noalloc(ctypes.byref(cfg), ctypes.byref(p), _ptr(status_out), ctypes.c_void_p(s))
+    if r != native.BA_OK:
+        raise BAError(r, "ba_solve_noalloc failed")
+    return poses_out, depth_out, status_out
