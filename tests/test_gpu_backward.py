@@ -58,30 +58,32 @@ def test_vjp_method_scale_matches_oracle(precision, tol):
     assert rel_err(gwt, gw_ref) < tol
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_translation_loss_grad_method_scale(precision):
-    """End to end through BAFunction: L = sum of squared camera-centre errors.
-    FP64 matches the oracle to rounding.  FP32: the forward state differs from
-    the FP64 one by ~2e-5 m while the centre errors are ~4e-3 m, so L and the
-    cotangent reaching the solve differ from the FP64 ones by a few percent.
-    L is held to the bound that state difference implies, and the gradient to
-    the oracle's vector-Jacobian product of the cotangent the solve received
-    (the adjoint's own precision, as in the fixed-cotangent test)."""
+def _fd_floor(magnitude, h):
+    """Absolute error floor of an FP64 central difference of a function whose
+    terms sum to `magnitude` in absolute value (both evaluations rounded, over
+    the step 2h, margin 10)."""
+    return 10.0 * np.finfo(np.float64).eps * magnitude / h
+
+
+@pytest.mark.parametrize("precision,win", [("fp64", 0), ("fp32", 0), ("fp32", 2), ("fp32", 3)])
+def test_translation_loss_grad_method_scale(precision, win):
+    """End to end through BAFunction on 22 x 96 windows: L = sum of squared
+    free camera-centre errors, gradient with respect to targets and weights
+    against the oracle's autograd.  FP64 assembly: 1e-8.  FP32 assembly: the
+    loss sits near its minimum (centre errors of a few mm), so its gradient
+    moves with the forward state; the bound is the change the oracle's own
+    gradient shows when its reduced system is rounded once to FP32, times the
+    summation factor sqrt(patches per source frame), and at least 1e-4."""
     need_gpu()
     from paper_2208_04726_amd.solver import BAFunction, Solver, make_batch, capacities_for
-    w = synth.method_scale_window(2)
+    from tests.rounding import fp32_assembly_factor, translation_loss_grad_rounded
+    w = synth.method_scale_window(win)
     L_ref, gy_ref, gw_ref = O.translation_loss_grad(w)
     s = Solver(precision=precision, **capacities_for([w]))
     b = make_batch([w], precision)
     tg = b.targets.clone().requires_grad_(True)
     wt = b.weights.clone().requires_grad_(True)
     poses, depth = BAFunction.apply(tg, wt, s, b)
-    seen = {}
-
-    def keep(g):
-        seen["gp"] = g.detach().double().cpu().numpy()
-
-    poses.register_hook(keep)
     q = poses[:, 3:]
     x, y, z, qw = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
     Rm = torch.stack([
@@ -96,31 +98,33 @@ def test_translation_loss_grad_method_scale(precision):
     gy = tg.grad.double().cpu().numpy()
     gwt = wt.grad.double().cpu().numpy()
     eg, ew = rel_err(gy, gy_ref), rel_err(gwt, gw_ref)
-    print(precision, "loss", float(L), L_ref, "rel err targets", eg, "weights", ew)
+    Lv = float(L.detach())
     if precision == "fp64":
-        assert abs(float(L) - L_ref) < 1e-8 * L_ref
+        print(f"fp64 window {win}: L {Lv:.6e} (oracle {L_ref:.6e}), gradient rel err targets {eg:.2e} weights {ew:.2e}")
+        assert abs(Lv - L_ref) < 1e-8 * L_ref
         assert eg < 1e-8 and ew < 1e-8
         return
-    # L = |e + dc|^2 with e the oracle's centre errors and dc the difference of
-    # the FP32 centres from the oracle's: |L - L_ref| <= 2 |e| |dc| + |dc|^2
-    pr, _ = O.solve(w)
-    nf = w.n_fixed
-    c_ref = O.camera_centres(torch.as_tensor(pr)).numpy()[nf:]
-    e = c_ref - synth.camera_centres(w.poses_gt)[nf:]
-    dc = np.linalg.norm(c.detach().double().cpu().numpy()[nf:] - c_ref)
-    bound = 2.0 * np.linalg.norm(e) * dc + dc * dc
-    print("fp32 |L - L_ref|", abs(float(L) - L_ref), "bound", bound)
-    assert abs(float(L) - L_ref) <= 1.01 * bound + 1e-12 * L_ref
-    gy2, gw2 = O.cotangent_grad(w, seen["gp"], np.zeros(w.n_patches))
-    e2, w2 = rel_err(gy, gy2), rel_err(gwt, gw2)
-    print("fp32 gradient vs oracle VJP of the received cotangent: targets", e2, "weights", w2)
-    # the weight gradient carries the residuals at the linearisation points,
-    # which the ~2e-5 m state difference moves by ~f * 2e-5 / Z ~ 3e-3 px
-    # against ~1 px of noise; the target gradient does not
-    assert e2 < 1e-3 and w2 < 5e-3
+    _, gy32, gw32 = translation_loss_grad_rounded(w)
+    f = fp32_assembly_factor(w)
+    tol_y = max(1e-4, f * rel_err(gy32, gy_ref))
+    tol_w = max(1e-4, f * rel_err(gw32, gw_ref))
+    print(f"fp32 window {win}: L {Lv:.6e} (oracle {L_ref:.6e}), gradient rel err targets {eg:.2e} "
+          f"(bound {tol_y:.1e}) weights {ew:.2e} (bound {tol_w:.1e})")
+    assert eg < tol_y and ew < tol_w
 
 
-def test_vjp_fp64_subwindow_vs_central_differences():
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_vjp_subwindow_vs_central_differences(precision):
+    """ba_backward on the 6 x 8 sub-window (targets and weights FP32-exact)
+    against FP64 central differences (step 1e-6) of f = <poses_out, g_p> +
+    <depth_out, g_d> through the oracle, entry by entry over every active edge
+    and both coordinates.  FP64 assembly: relative 1e-4 above the rounding
+    floor of the difference quotient.  FP32 assembly: its iterates carry the
+    FP32 forward state (about 1e-6 relative), which moves the residuals the
+    weight gradient is made of by ~1e-3 px against ~1 px, so entries are held
+    to relative 1e-2 above that floor plus 2^-20 of the largest entry (a few
+    FP32 roundings of the per-edge products), and the whole gradient to 1e-3
+    in norm."""
     need_gpu()
     w = synth.gradient_subwindow(0)
     gp = np.zeros((w.n_frames, 7))
@@ -128,21 +132,37 @@ def test_vjp_fp64_subwindow_vs_central_differences():
     rng = np.random.default_rng(3)
     gp[w.n_fixed:] = rng.normal(size=(w.n_frames - w.n_fixed, 7))
     gd[:] = rng.normal(size=w.n_patches)
-    gy, gwt, st = gpu_vjp(w, gp, gd, "fp64")
+    gy, gwt, st = gpu_vjp(w, gp, gd, precision)
     assert st[0] == 0
 
     def f(wx):
         p, d = O.solve(wx)
-        return float((p * gp).sum() + (d * gd).sum())
+        return float((p * gp).sum() + (d * gd).sum()), float(np.abs(p * gp).sum() + np.abs(d * gd).sum())
 
     h = 1e-6
+    _, mag = f(w)
+    floor = _fd_floor(mag, h)
     act = np.nonzero((w.anchor[w.kk] != w.jj) & (w.weights[:, 0] > 0))[0]
-    for e in act[::7]:
-        for c in range(2):
-            for arr, g in (("targets", gy), ("weights", gwt)):
+    rel = 1e-4 if precision == "fp64" else 1e-2
+    ratio, norm_err, bad = {}, {}, []
+    for arr, g in (("targets", gy), ("weights", gwt)):
+        fl = floor + (2.0 ** -20 * np.abs(g).max() if precision == "fp32" else 0.0)
+        r, fds = [], []
+        for e in act:
+            for c in range(2):
                 wp, wm = w.copy(), w.copy()
                 getattr(wp, arr)[e, c] += h
                 getattr(wm, arr)[e, c] -= h
-                fd = (f(wp) - f(wm)) / (2 * h)
-                scale = np.abs(g).max()
-                assert abs(fd - g[e, c]) < 1e-4 * scale, (arr, e, c, fd, g[e, c])
+                fd = (f(wp)[0] - f(wm)[0]) / (2 * h)
+                fds.append(fd)
+                r.append(abs(fd - g[e, c]) / (rel * abs(fd) + fl))
+                if r[-1] >= 1.0:
+                    bad.append((arr, int(e), c, fd, float(g[e, c]), fl))
+        ratio[arr] = max(r)
+        ga = g[act].reshape(-1)
+        norm_err[arr] = float(np.linalg.norm(ga - np.asarray(fds)) / np.linalg.norm(fds))
+    print(f"{precision} FD check over {len(act)} active edges: worst error / ({rel:g} |fd| + floor): "
+          f"targets {ratio['targets']:.3f} weights {ratio['weights']:.3f}; {len(bad)} entries over; "
+          f"norm rel err targets {norm_err['targets']:.2e} weights {norm_err['weights']:.2e}")
+    assert not bad, bad[:5]
+    assert max(norm_err.values()) < (1e-4 if precision == "fp64" else 1e-3)

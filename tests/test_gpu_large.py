@@ -8,7 +8,7 @@ import torch
 from oracle import ba_oracle as O
 from paper_2208_04726_amd import synth
 from tests.gpu_util import compare, need_gpu, solve_gpu
-from tests.rounding import solve_schur_rounded
+from tests.rounding import check_depths, depth_sensitivity, fp32_assembly_factor, solve_schur_rounded
 
 pytestmark = pytest.mark.gpu
 
@@ -16,42 +16,19 @@ FP64_TOL = (1e-6, 1e-4, 1e-6)
 FP32_TOL = (1e-4, 1e-2, 1e-3)
 
 
-def fp32_tolerance(w, iterations=2, factor=10.0):
-    """Tolerance of FP32 assembly for window w: the fixed FP32 bounds, or
-    `factor` times the change the FP64 oracle itself shows when its reduced
-    system is rounded once to FP32 per iteration, whichever is larger.  Long
-    windows with few patches per frame have reduced systems with condition
-    numbers near 1e7 (scale drift along the trajectory), where FP32 rounding of
-    S alone moves the poses by more than 1e-4 m."""
+def fp32_tolerance(w, iterations=2):
+    """Pose tolerance of FP32 assembly for window w: the fixed FP32 bounds, or
+    the change the FP64 oracle itself shows when its reduced system is rounded
+    once to FP32 per iteration, times the probabilistic summation factor
+    sqrt(patches per source frame) (`fp32_assembly_factor`), whichever is
+    larger.  Long windows with few patches per frame have reduced systems with
+    condition numbers near 1e7 (scale drift along the trajectory), where one
+    FP32 rounding of S alone moves the poses by more than 1e-4 m."""
     pr, dr = O.solve_schur(w, iterations=iterations)
     p32, d32 = solve_schur_rounded(w, iterations=iterations)
-    dc, drot, dd = compare(p32, d32, pr, dr)
-    return (max(FP32_TOL[0], factor * dc), max(FP32_TOL[1], factor * drot), max(FP32_TOL[2], factor * dd))
-
-
-def depth_tolerance(w, iterations=2, eps=2.0 ** -18, factor=10.0, floor=1e-3):
-    """Per-patch relative tolerance of FP32-assembled inverse depths: `floor`
-    plus `factor` times the relative change of the FP64 oracle's depth when
-    every target and weight is perturbed by a random relative `eps` (2^-18,
-    about 32 FP32 ulps: the rounding of the few dozen FP32 operations that form
-    each patch's sums).  Patches the Gauss-Newton steps move far from their
-    start (weakly observed, outlier-dominated) amplify rounding by orders of
-    magnitude; this scales their tolerance accordingly."""
-    _, d0 = O.solve_schur(w, iterations=iterations)
-    rng = np.random.default_rng(5)
-    w2 = w.copy()
-    w2.targets = w.targets * (1 + eps * rng.uniform(-1, 1, w.targets.shape))
-    w2.weights = w.weights * (1 + eps * rng.uniform(-1, 1, w.weights.shape))
-    _, d1 = O.solve_schur(w2, iterations=iterations)
-    return floor + factor * np.abs(d1 - d0) / np.abs(d0)
-
-
-def _depth_ok(d_gpu, d_ref, tol):
-    rel = np.abs(d_gpu - d_ref) / np.abs(d_ref)
-    worst = int(np.argmax(rel / tol))
-    print(f"  depth: max rel {rel.max():.2e}, worst vs tolerance at patch {worst}: "
-          f"{rel[worst]:.2e} <= {tol[worst]:.2e}")
-    return bool(np.all(rel <= tol))
+    dc, drot, _ = compare(p32, d32, pr, dr)
+    f = fp32_assembly_factor(w)
+    return max(FP32_TOL[0], f * dc), max(FP32_TOL[1], f * drot)
 
 
 def _wide(n_frames, ppf, r, seed, fp32=True, n_fixed=2):
@@ -111,7 +88,7 @@ def test_fp32_wide_window_matches_oracle(shape):
     tol = fp32_tolerance(w)
     print(f"{shape}: {dc:.2e} m {drot:.2e} deg depth {dd:.2e} (tolerance {tol[0]:.1e} m {tol[1]:.1e} deg)")
     assert dc < tol[0] and drot < tol[1]
-    assert _depth_ok(out[0][1], dr, depth_tolerance(w))
+    check_depths(out[0][1], dr, depth_sensitivity(w), label=str(shape))
 
 
 def test_fp64_24_frames_matches_oracle():
@@ -153,11 +130,10 @@ def test_large_windows_64x256_k4_batch_of_8():
     wins = [synth.large_window(i) for i in range(8)]
     out, st = solve_gpu(wins, "fp32", "auto", iterations=4)
     assert (st == 0).all(), st
-    for i in (0, 5):
+    for i in range(8):
         pr, dr = O.solve_schur(wins[i], iterations=4)
         dc, drot, dd = compare(out[i][0], out[i][1], pr, dr)
-        tol = fp32_tolerance(wins[i], iterations=4)
-        print(f"large window {i}: {dc:.2e} m {drot:.2e} deg depth {dd:.2e} "
-              f"(tolerance {tol[0]:.1e} m {tol[1]:.1e} deg)")
-        assert dc < tol[0] and drot < tol[1]
-        assert _depth_ok(out[i][1], dr, depth_tolerance(wins[i], iterations=4))
+        print(f"large window {i}: {dc:.2e} m {drot:.2e} deg depth {dd:.2e}")
+        # the 64 x 256 windows meet the fixed FP32 pose bounds
+        assert dc < FP32_TOL[0] and drot < FP32_TOL[1]
+        check_depths(out[i][1], dr, depth_sensitivity(wins[i], iterations=4), label=f"large window {i}")
