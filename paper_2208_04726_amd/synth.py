@@ -320,3 +320,80 @@ def pose_errors(pa: np.ndarray, pb: np.ndarray):
     """(max centre distance in m, max rotation angle in deg) between two pose sets."""
     dc = np.linalg.norm(camera_centres(pa) - camera_centres(pb), axis=1)
     return float(dc.max()) if dc.size else 0.0, float(rotation_error_deg(pa, pb).max()) if len(pa) else 0.0
+
+
+# ---------------------------------------------------------------- correlation workloads
+FEATURE_STRIDE = 4      # the matching features are at 1/4 of the image resolution
+FEATURE_DIM = 128       # matching-feature channels
+
+
+def bf16_exact(a: np.ndarray) -> np.ndarray:
+    """float32 values representable in bfloat16 (round to nearest even), so
+    the same numbers feed a bf16 buffer and a float64 reference."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def bf16_bits(a: np.ndarray) -> np.ndarray:
+    """The bfloat16 bit patterns (uint16) of bf16-exact float32 values."""
+    return (np.ascontiguousarray(a, np.float32).view(np.uint32) >> 16).astype(np.uint16)
+
+
+@dataclasses.dataclass
+class CorrWorkload:
+    """Inputs of the correlation features of one window's patch graph."""
+    fmap0: np.ndarray     # [F, H0, W0, D] float32, bf16-exact: first-level matching features
+    fmap1: np.ndarray     # [F, H1, W1, D] float32, bf16-exact: second level (independent draw)
+    gmap: np.ndarray      # [M, p*p, D] float32, bf16-exact: patch features
+    coords: np.ndarray    # [E, p*p, 2] float32: reprojected pixels, first-level pixel units
+    kk: np.ndarray        # [E] int32
+    jj: np.ndarray        # [E] int32
+    scale1: int           # second-level coordinate divisor
+
+    @property
+    def n_edges(self) -> int:
+        return int(self.kk.shape[0])
+
+
+def correlation_workload(n_frames: int, ppf: int, radius: int, *, seed: Sequence[int],
+                         p: int = 3, dim: int = FEATURE_DIM, scale1: int = 4,
+                         noise_px: float = 1.0, feature_hw=None) -> CorrWorkload:
+    """Random N(0,1) features and a simulated patch graph: frame maps at 1/4
+    of the 640x480 image, p x p patches of first-level pixels (spacing 1 =
+    4 image pixels) around random centres, every patch joined to every frame
+    within `radius` of its source frame.  Each patch pixel is back-projected
+    at the patch's true depth (a fronto-parallel plane in its source frame),
+    seen by the target camera and perturbed by N(0, noise_px) image pixels,
+    so coordinates leave the map where the scene does.  `feature_hw` shrinks
+    the first-level map (coordinates scale with it) for small cases."""
+    w = make_window(n_frames, ppf, radius, seed=list(seed) + [77])
+    rng = np.random.default_rng(list(seed) + [78])
+    s0 = FEATURE_STRIDE
+    H0, W0 = feature_hw if feature_hw is not None else (HEIGHT // s0, WIDTH // s0)
+    H1, W1 = H0 // scale1, W0 // scale1
+    fmap0 = bf16_exact(rng.normal(size=(n_frames, H0, W0, dim)).astype(np.float32))
+    fmap1 = bf16_exact(rng.normal(size=(n_frames, H1, W1, dim)).astype(np.float32))
+    M = w.n_patches
+    gmap = bf16_exact(rng.normal(size=(M, p * p, dim)).astype(np.float32))
+    sx, sy = WIDTH / W0, HEIGHT / H0              # image pixels per first-level pixel
+    r = (p - 1) / 2.0
+    offs = [((v - r) * sx, (u - r) * sy) for u in range(p) for v in range(p)]   # (dx, dy), row-major
+    E = w.n_edges
+    coords = np.empty((E, p * p, 2), np.float32)
+    for q, (dx, dy) in enumerate(offs):
+        px = np.stack([w.patches[:, 0] + dx, w.patches[:, 1] + dy, w.depth_gt], 1)
+        Xw = scene_points(w.poses_gt, px, w.anchor, w.intrinsics)
+        uv, _ = camera_observation(w.poses_gt, Xw[w.kk], w.jj, w.intrinsics)
+        uv = uv + rng.normal(0.0, noise_px, uv.shape)
+        coords[:, q, 0] = (uv[:, 0] / sx).astype(np.float32)
+        coords[:, q, 1] = (uv[:, 1] / sy).astype(np.float32)
+    return CorrWorkload(fmap0=fmap0, fmap1=fmap1, gmap=gmap, coords=coords,
+                        kk=w.kk.copy(), jj=w.jj.copy(), scale1=scale1)
+
+
+def method_scale_correlation(window_id: int = 0) -> CorrWorkload:
+    """The 22-frame x 96-patch, radius-13 patch graph (39,552 edges, self-edges
+    included) over 160 x 120 first-level and 40 x 30 second-level maps of 128
+    channels, 3 x 3 patches."""
+    return correlation_workload(22, 96, 13, seed=[2208, 5, window_id])
