@@ -1,10 +1,11 @@
-"""Builds the gfx950 HIP library libdpba.so in the package directory."""
+"""Builds the gfx950 HIP library libdpba.so (bundle adjustment and the
+correlation features) in the package directory."""
 import os
 import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "dpba.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("dpba.hip", "dpcorr.hip")]
 OUT = os.path.join(HERE, "libdpba.so")
 ARCH = os.environ.get("DPBA_OFFLOAD_ARCH", "gfx950")
 
@@ -25,7 +26,7 @@ def build(verbose: bool = False) -> str:
            # arithmetic of a window does not depend on which kernel variant ran
            "-ffp-contract=on",
            "-Wno-unused-command-line-argument",
-           SRC, "-o", OUT + ".tmp"]
+           *SRCS, "-o", OUT + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

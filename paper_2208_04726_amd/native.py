@@ -19,7 +19,8 @@ BA_W_OK, BA_W_NOT_SPD, BA_W_NONFINITE, BA_W_BAD_INDEX, BA_W_DEGREE = 0, 1, 2, 4,
 
 EXPORTED = ("ba_create", "ba_solve", "ba_backward", "ba_prepare", "ba_launch", "ba_set_timing",
             "ba_kernel_times", "ba_status", "ba_last_error", "ba_destroy",
-            "ba_debug_reduced_system", "ba_debug_mfma", "ba_solve_noalloc")
+            "ba_debug_reduced_system", "ba_debug_mfma", "ba_solve_noalloc",
+            "dpc_correlation", "dpc_avg_pool", "dpc_debug_mfma_bf16")
 STAGES = ("prep", "assemble", "chol", "backsub", "finalize", "fused")
 
 
@@ -41,6 +42,17 @@ class BAProblem(ctypes.Structure):
                 ("anchor", ctypes.c_void_p), ("kk", ctypes.c_void_p), ("jj", ctypes.c_void_p),
                 ("targets", ctypes.c_void_p), ("weights", ctypes.c_void_p),
                 ("poses_out", ctypes.c_void_p), ("depth_out", ctypes.c_void_p)]
+
+
+class DPCProblem(ctypes.Structure):
+    _fields_ = [("n_frames", ctypes.c_int32), ("channels", ctypes.c_int32),
+                ("height0", ctypes.c_int32), ("width0", ctypes.c_int32),
+                ("height1", ctypes.c_int32), ("width1", ctypes.c_int32),
+                ("scale1", ctypes.c_float), ("patch_pixels", ctypes.c_int32),
+                ("n_patches", ctypes.c_int64), ("n_edges", ctypes.c_int64),
+                ("level0", ctypes.c_void_p), ("level1", ctypes.c_void_p), ("gmap", ctypes.c_void_p),
+                ("coords", ctypes.c_void_p), ("kk", ctypes.c_void_p), ("jj", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("status", ctypes.c_void_p)]
 
 
 _LIB = None
@@ -81,6 +93,12 @@ def lib() -> ctypes.CDLL:
         L.ba_debug_mfma.restype = ctypes.c_int
         L.ba_solve_noalloc.argtypes = [ctypes.POINTER(BAConfig), ctypes.POINTER(BAProblem), vp, vp]
         L.ba_solve_noalloc.restype = ctypes.c_int
+        L.dpc_correlation.argtypes = [ctypes.POINTER(DPCProblem), vp]
+        L.dpc_correlation.restype = ctypes.c_int
+        L.dpc_avg_pool.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]
+        L.dpc_avg_pool.restype = ctypes.c_int
+        L.dpc_debug_mfma_bf16.argtypes = [vp, vp, vp, vp]
+        L.dpc_debug_mfma_bf16.restype = ctypes.c_int
         _LIB = L
     return _LIB
 
