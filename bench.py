@@ -14,6 +14,10 @@ Also measured in the same run:
     streams, served by continuous batching with graph replays, against the
     plain one-window-at-a-time solve on the same trace (p50/p99/p99.9 latency
     from arrival to result on the host), plus closed-loop throughput of both;
+  * parity of reported results against the FP64 oracle (pose m / deg and
+    relative inverse depth, per record);
+  * the plain FP64 8x16 windows, the adjoint (ba_backward) per window, and
+    the correlation features (Eq. 4) of the method-scale patch graph;
   * the FP64 CPU oracle on a bounded sample, on the host cores.
 
 Prints one JSON line on stdout; progress goes to stderr.
@@ -68,22 +72,47 @@ def source_digest(paths):
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per assembly launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel sources; else None."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None, "no counter summary"
+LARGE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_assemble_fp32_64x256_b8_hbm_traffic.txt")
+MIX_FILE = os.path.join(ROOT, "profiles", "k_assemble_fp32_22x96_b256_instruction_mix.txt")
+
+
+def _summary(path):
+    """key = value lines of a committed counter summary, or None when it is
+    missing or was taken on other assembly sources than the current ones."""
+    if not os.path.exists(path):
+        return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
-            kv[k.strip()] = v.strip()
-    if kv.get("source_digest") != source_digest(ASSEMBLY_SOURCES):
+            kv[k.strip()] = v.split("(")[0].strip()
+    return kv if kv.get("source_digest") == source_digest(ASSEMBLY_SOURCES) else None
+
+
+def measured_traffic(path=TRAFFIC_FILE):
+    """HBM bytes per assembly launch from a committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources; else None."""
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    kv = _summary(path)
+    if kv is None:
         return None, "kernel changed since the counters were taken"
     try:
         return float(kv["bytes_per_launch"]), "rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated"
     except (KeyError, ValueError):
         return None, "malformed counter summary"
+
+
+def assembly_bound():
+    """The unit the assembly is priced against, from the committed
+    instruction-mix counters of the current sources."""
+    kv = _summary(MIX_FILE)
+    if kv is None:
+        return "alu", "no instruction-mix counters of the current sources"
+    return "alu", (f"rocprofv3 SQ counters: {float(kv['valu_to_mfma_insts']):.1f} VALU per MFMA instruction, "
+                   f"VALU issue {float(kv['valu_issue_fraction']):.3f} and MFMA busy "
+                   f"{float(kv['mfma_busy_fraction']):.3f} of the cycles per SIMD: VALU-dominated and "
+                   f"latency-bound, priced against the FP32 arithmetic peak")
 
 
 COPY_BYTES = 256 * 2 ** 20
@@ -101,13 +130,24 @@ def pmc_workload(args):
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
-    windows = [synth.method_scale_window(i) for i in range(args.batch)]
-    solver = Solver(precision="fp32", iterations=2, schedule=args.schedule, **capacities_for(windows))
+    if args.pmc_target == "corr":
+        for _ in range(args.warmup + args.steps):
+            run_correlation_launch(torch)
+        torch.cuda.synchronize()
+        log(f"pmc workload done: {args.steps + args.warmup} correlation launches")
+        return
+    if args.pmc_target == "large":
+        windows = [synth.large_window(i) for i in range(args.large_windows)]
+        iters = 4
+    else:
+        windows = [synth.method_scale_window(i) for i in range(args.batch)]
+        iters = 2
+    solver = Solver(precision="fp32", iterations=iters, schedule=args.schedule, **capacities_for(windows))
     batch = make_batch(windows, "fp32")
     for _ in range(args.warmup + args.steps):
         solver.solve(batch)
     torch.cuda.synchronize()
-    log(f"pmc workload done: {args.steps + args.warmup} solves of {args.batch} windows")
+    log(f"pmc workload done: {args.steps + args.warmup} solves of {len(windows)} windows")
 
 
 def _pmc_rows(path):
@@ -160,20 +200,89 @@ def pmc_summarize(fetch_csv, write_csv, command):
     print("\n".join(lines))
 
 
-def cpu_oracle_baseline(windows, budget_s):
-    """The FP64 oracle as it stands, one window after another on the host,
-    for about `budget_s` seconds."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_job(job):
+    """One oracle solve in a worker process (one thread): (kind, id) -> s."""
     import torch
+    torch.set_num_threads(1)
     from oracle import ba_oracle as O
-    n = 0
+    from paper_2208_04726_amd import synth
+    kind, i = job
+    w = {"cfg1": synth.method_scale_window, "cfg0": synth.plain_fp64_window}[kind](i)
+    t = time.perf_counter()
+    O.solve(w)
+    return time.perf_counter() - t
+
+
+def cpu_oracle_baseline(budget_s):
+    """The FP64 oracle as it stands, on the host cores, before the GPU is
+    touched: all-core throughput on 22x96 windows (one window per process,
+    one thread each, every core of the affinity mask, for about `budget_s`
+    seconds), and one-thread latency per window of the 22x96, 8x16 and
+    64x256 windows (the last by the oracle's block-eliminated solve)."""
+    import multiprocessing as mp
+    import torch
+    cores = len(os.sched_getaffinity(0))
+    ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and n < len(windows):
-        O.solve(windows[n])
-        n += 1
-    dt = time.perf_counter() - t0
-    return dict(value=round(n / dt, 3), unit="windows/s", cores=int(torch.get_num_threads()), kind="oracle",
-                sample=f"first {n} windows of the batch (22x96, r=13), FP64 dense normal equations "
-                       f"over all unknowns, 2 iterations each, {dt:.1f} s")
+    done = 0
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_job, [("cfg0", i) for i in range(cores)])     # start-up outside the clock
+        t0 = time.perf_counter()
+        it = pool.imap_unordered(_oracle_job, [("cfg1", i) for i in range(100000)])
+        for _ in it:
+            done += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        dt = time.perf_counter() - t0
+        pool.terminate()
+    from oracle import ba_oracle as O
+    from paper_2208_04726_amd import synth
+    nthreads = torch.get_num_threads()
+    torch.set_num_threads(1)
+    lat = {}
+    for name, make, solve, n in (("cfg1_22x96", synth.method_scale_window, lambda w: O.solve(w), 3),
+                                 ("cfg0_8x16", synth.plain_fp64_window, lambda w: O.solve(w), 20),
+                                 ("cfg4_64x256_k4", synth.large_window,
+                                  lambda w: O.solve_schur(w, iterations=4), 1)):
+        ws = [make(i) for i in range(n)]
+        t = time.perf_counter()
+        for w in ws:
+            solve(w)
+        lat[name] = round((time.perf_counter() - t) * 1e3 / n, 2)
+    torch.set_num_threads(nthreads)
+    log(f"cpu oracle: {done} windows in {dt:.1f}s on {cores} processes; 1-thread ms/window {lat}")
+    return dict(value=round(done / dt, 3), unit="windows/s", cores=cores, kind="oracle",
+                sample=f"{done} windows of 22x96 (r=13) in {dt:.1f} s, one window per process, one thread "
+                       f"each, on every core of the affinity mask; FP64 dense normal equations over all "
+                       f"unknowns, 2 iterations",
+                cpu_model=_cpu_model(), single_thread_ms_per_window=lat)
+
+
+def pose_depth_errors(po, do, pr, dr):
+    """Max camera-centre error (m), rotation error (deg) and relative inverse-
+    depth error of a solved window against the oracle's."""
+    from paper_2208_04726_amd import synth
+    dc, drot = synth.pose_errors(po, pr)
+    dd = float(np.max(np.abs(do - dr) / np.abs(dr))) if len(dr) else 0.0
+    return dc, drot, dd
+
+
+def parity_record(pairs, label):
+    """{worst pose m, deg, depth rel} over (gpu poses, gpu depth, oracle poses,
+    oracle depth) tuples."""
+    e = np.array([pose_depth_errors(*p) for p in pairs])
+    return {"windows": len(pairs), "max_pose_m": float(e[:, 0].max()), "max_rot_deg": float(e[:, 1].max()),
+            "max_depth_rel": float(e[:, 2].max()), "reference": label}
 
 
 def run_large(args, torch):
@@ -212,7 +321,15 @@ def run_large(args, torch):
         fl += f_
         by += b_
     asm_ms = kt["assemble"][0] / max(kt["assemble"][1], 1)
+    large_traffic, _ = measured_traffic(LARGE_TRAFFIC_FILE)
+    po, do = solver.solve(batch, stream=stream)
+    torch.cuda.synchronize()
+    f1, p1 = int(batch.frame_off[1]), int(batch.patch_off[1])
+    out0 = (po[:f1].cpu().numpy(), do[:p1].cpu().numpy())
     solver.close()
+    from oracle import ba_oracle as O
+    pr, dr = O.solve_schur(wins[0], iterations=iters)
+    parity = parity_record([(out0[0], out0[1], pr, dr)], "oracle block-eliminated FP64 solve, window 0")
     return {"workload": f"{len(wins)} windows of 64 frames x 256 patches/frame, radius 16, 10% outliers, "
                         "4 GN iterations, FP32 assembly + FP64 372x372 Cholesky",
             "ms_per_solve_batch": round(ms, 4), "windows_per_s": round(len(wins) / (ms / 1e3), 2),
@@ -222,7 +339,10 @@ def run_large(args, torch):
                         for k, v in kt.items() if v[1] > 0},
             "assembly_tflops": round(fl / (asm_ms / 1e3) / 1e12, 3),
             "assembly_algorithmic_hbm_gbs": round(by / (asm_ms / 1e3) / 1e9, 1),
-            "status_failures": bad}
+            "assembly_counter_hbm_gbs": (round(large_traffic / (asm_ms / 1e3) / 1e9, 1) if large_traffic else None),
+            "assembly_counter_bytes_per_launch": large_traffic,
+            "assembly_algorithmic_bytes_per_launch": by,
+            "status_failures": bad, "parity": parity}
 
 
 def run_serving(args, torch):
@@ -258,8 +378,34 @@ def run_serving(args, torch):
     b["closed_loop_mean_batch"] = round(float(np.mean(srv.batch_sizes)), 2)
     b["slot_footprint_mb"] = round(srv.footprint_bytes / 2 ** 20, 1)
     out["batched"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in b.items()}
-    out["batched"].update(schedule=args.serve_schedule, slots=args.serve_slots, graph=True)
+    out["batched"].update(schedule=args.serve_schedule, slots=len(srv.slots), graph=True)
     log(f"batched serving: {out['batched']}")
+    # parity of served results: the first request of four pool windows
+    from oracle import ba_oracle as O
+    where = {id(p.poses): i for i, p in enumerate(pool)}
+    seen, pairs = set(), []
+    for r in trace[args.serve_warmup:]:
+        pi = where[id(r.poses)]
+        if pi in seen:
+            continue
+        seen.add(pi)
+        pr, dr = O.solve(synth.serving_window(pi))
+        pairs.append((res[r.rid].poses, res[r.rid].depth, pr, dr))
+        if len(pairs) == 4:
+            break
+    out["parity"] = parity_record(pairs, "oracle dense FP64 solve of four served requests")
+    # a rate at which continuous batching engages
+    fast = serve.poisson_trace(pool, args.serve_fast_requests, rate=args.serve_fast_rate, n_streams=64, seed=2210)
+    srv.batch_sizes.clear()
+    t = time.perf_counter()
+    res_f = srv.run(fast)
+    wall = time.perf_counter() - t
+    f = serve.latency_summary(res_f, skip=args.serve_fast_requests // 10)
+    f.update(rate_per_s=args.serve_fast_rate, requests=args.serve_fast_requests,
+             solves_per_s=round(len(fast) / wall, 1), mean_batch=round(float(np.mean(srv.batch_sizes)), 2),
+             status_failures=sum(1 for r in res_f.values() if r.status != 0))
+    out["batched_fast"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in f.items()}
+    log(f"batched serving at {args.serve_fast_rate:.0f}/s: {out['batched_fast']}")
 
     plain = serve.PlainServer(serve.Capacity(1, 22, 22 * 96, 22 * 96 * 27, 22))
     plain.run(closed[:32])
@@ -274,6 +420,167 @@ def run_serving(args, torch):
     out["plain"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in p.items()}
     log(f"plain serving: {out['plain']}")
     return out
+
+
+def run_plain_fp64(args, torch):
+    """8-frame x 16-patch FP64 windows: batched solves/s, one-window latency,
+    and parity of four windows against the dense oracle."""
+    from oracle import ba_oracle as O
+    from paper_2208_04726_amd import synth
+    from paper_2208_04726_amd.solver import Solver, make_batch, capacities_for
+    wins = [synth.plain_fp64_window(i) for i in range(args.batch)]
+    solver = Solver(precision="fp64", iterations=2, schedule="split", **capacities_for(wins))
+    batch = make_batch(wins, "fp64")
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        po, do = solver.solve(batch, stream=stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        solver.solve(batch, po, do, stream=stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / args.steps
+    bad = int((solver.status() != 0).sum())
+    pairs = []
+    pn, dn = po.cpu().numpy(), do.cpu().numpy()
+    for i in range(4):
+        f0, f1 = batch.frame_off[i], batch.frame_off[i + 1]
+        p0, p1 = batch.patch_off[i], batch.patch_off[i + 1]
+        pr, dr = O.solve(wins[i])
+        pairs.append((pn[f0:f1], dn[p0:p1], pr, dr))
+    solver.close()
+    one = Solver(precision="fp64", iterations=2, schedule="split", **capacities_for(wins[:1]))
+    b1 = make_batch(wins[:1], "fp64")
+    for _ in range(3):
+        o1 = one.solve(b1, stream=stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(50):
+        one.solve(b1, *o1, stream=stream)
+        torch.cuda.synchronize()
+    ms1 = (time.perf_counter() - t) * 1e3 / 50
+    one.close()
+    return {"workload": f"{args.batch} windows of 8 frames x 16 patches, radius 3, FP64, 2 GN iterations",
+            "ms_per_solve_batch": round(ms, 4), "windows_per_s": round(args.batch / (ms / 1e3), 1),
+            "single_window_ms": round(ms1, 4), "status_failures": bad,
+            "parity": parity_record(pairs, "oracle dense FP64 solve, windows 0-3")}
+
+
+def run_backward(args, torch):
+    """ba_backward (recomputed iterates, adjoint) of 22x96 windows in FP32 and
+    FP64, 32 windows per call, fixed random cotangents; parity of window 0
+    against the oracle's vector-Jacobian product."""
+    from oracle import ba_oracle as O
+    from paper_2208_04726_amd import synth
+    from paper_2208_04726_amd.solver import Solver, make_batch, capacities_for
+    n = 32
+    wins = [synth.method_scale_window(i) for i in range(n)]
+    rng = np.random.default_rng(11)
+    out = {"workload": f"{n} windows of 22 frames x 96 patches, 2 GN iterations, VJP to targets and weights"}
+    w0 = wins[0]
+    gp0 = rng.normal(size=(w0.n_frames, 7))
+    gd0 = rng.normal(size=w0.n_patches)
+    gy_ref, gw_ref = O.cotangent_grad(w0, gp0, gd0)
+    for prec in ("fp32", "fp64"):
+        solver = Solver(precision=prec, iterations=2, schedule="split", **capacities_for(wins))
+        batch = make_batch(wins, prec)
+        F, P, _ = batch.totals
+        gp = torch.as_tensor(np.concatenate([gp0, rng.normal(size=(F - w0.n_frames, 7))]), device="cuda")
+        gd = torch.as_tensor(np.concatenate([gd0, rng.normal(size=P - w0.n_patches)]), device="cuda")
+        for _ in range(2):
+            gt, gw = solver.backward(batch, gp, gd)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            gt, gw = solver.backward(batch, gp, gd)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / 5
+        E0 = w0.n_edges
+        g_t = gt[:E0].double().cpu().numpy()
+        g_w = gw[:E0].double().cpu().numpy()
+        rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        out[prec] = {"ms_per_call": round(ms, 4), "ms_per_window": round(ms / n, 5),
+                     "vjp_rel_err_targets": rel(g_t, gy_ref), "vjp_rel_err_weights": rel(g_w, gw_ref),
+                     "status_failures": int((solver.status() != 0).sum())}
+        solver.close()
+    return out
+
+
+_CORR = {}
+
+
+def run_correlation_launch(torch):
+    """One correlation launch (and one pooling launch) on the method-scale
+    correlation workload, its device buffers made on first use."""
+    from paper_2208_04726_amd import corr, synth
+    if not _CORR:
+        wl = synth.method_scale_correlation(0)
+        dev = lambda a, d: torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=d).contiguous()
+        _CORR.update(wl=wl, f0=dev(wl.fmap0, torch.bfloat16), f1=dev(wl.fmap1, torch.bfloat16),
+                     g=dev(wl.gmap, torch.bfloat16), c=dev(wl.coords, torch.float32),
+                     kk=dev(wl.kk, torch.int32), jj=dev(wl.jj, torch.int32))
+        _CORR["out"] = torch.empty((wl.n_edges, 2, 9, 7, 7), dtype=torch.float32, device="cuda")
+        _CORR["pooled"] = torch.empty_like(_CORR["f1"])
+    d = _CORR
+    corr.correlation(d["f0"], d["f1"], d["wl"].scale1, d["g"], d["c"], d["kk"], d["jj"], out=d["out"])
+    corr.avg_pool(d["f0"], d["wl"].scale1, out=d["pooled"])
+
+
+def run_correlation(args, torch):
+    """Correlation features (Eq. 4) of the 22 x 96, radius-13 patch graph:
+    39,552 edges, 3x3 patches, 128 channels, 160x120 and 40x30 maps in bf16;
+    the second level made by the pooling kernel; HIP events around each
+    launch; parity of 64 sampled edges against the oracle."""
+    from oracle import corr_oracle as C
+    from paper_2208_04726_amd import corr, synth
+    wl = synth.method_scale_correlation(0)
+    dev = lambda a, d: torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=d).contiguous()
+    f0 = dev(wl.fmap0, torch.bfloat16)
+    f1 = dev(wl.fmap1, torch.bfloat16)
+    g = dev(wl.gmap, torch.bfloat16)
+    c = dev(wl.coords, torch.float32)
+    kk, jj = dev(wl.kk, torch.int32), dev(wl.jj, torch.int32)
+    out = torch.empty((wl.n_edges, 2, 9, 7, 7), dtype=torch.float32, device="cuda")
+    pooled = torch.empty_like(f1)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        corr.correlation(f0, f1, wl.scale1, g, c, kk, jj, out=out)
+        corr.avg_pool(f0, wl.scale1, out=pooled)
+    torch.cuda.synchronize()
+    reps = 20
+    mk = lambda: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    ev, evp = mk(), mk()
+    for (a, b), (pa, pb) in zip(ev, evp):
+        a.record(stream)
+        corr.correlation(f0, f1, wl.scale1, g, c, kk, jj, out=out)
+        b.record(stream)
+        pa.record(stream)
+        corr.avg_pool(f0, wl.scale1, out=pooled)
+        pb.record(stream)
+    torch.cuda.synchronize()
+    avg = lambda evs: float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    ms, ms_pool = avg(ev), avg(evp)
+    E = wl.n_edges
+    nbytes = lambda a: int(np.prod(a.shape))
+    by = (2 * nbytes(wl.fmap0) + 2 * nbytes(wl.fmap1) + 2 * nbytes(wl.gmap) + 4 * nbytes(wl.coords)
+          + 8 * E + 4 * E * 2 * 9 * 49)
+    by_pool = 2 * nbytes(wl.fmap0) + 2 * nbytes(wl.fmap1)
+    got = out.cpu().numpy().astype(np.float64)
+    sel = np.sort(np.random.default_rng(3).choice(E, 64, replace=False))
+    args_ = ([wl.fmap0, wl.fmap1], [1, wl.scale1], wl.gmap, wl.coords[sel], wl.kk[sel], wl.jj[sel])
+    ref, mag = C.correlation(*args_), C.correlation_abs(*args_)
+    gam = 132 * 2.0 ** -24 / (1 - 132 * 2.0 ** -24)
+    gbs = by / (ms / 1e3) / 1e9
+    return {"workload": "correlation features, 22 frames x 96 patches, radius 13: 39,552 edges, 3x3 patches, "
+                        "D=128, 160x120 and 40x30 bf16 maps, 2 levels x 9 pixels x 7x7 per edge, FP32 out",
+            "ms_per_launch": round(ms, 4), "edges_per_s": round(E / (ms / 1e3), 1),
+            "algorithmic_bytes_per_launch": by, "achieved_hbm_gbs": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "pool_ms_per_launch": round(ms_pool, 4),
+            "pool_hbm_gbs": round(by_pool / (ms_pool / 1e3) / 1e9, 1),
+            "parity": {"edges": int(len(sel)), "max_abs_err": float(np.abs(got[sel] - ref).max()),
+                       "max_err_over_bound": float((np.abs(got[sel] - ref) / (gam * mag + 1e-300)).max()),
+                       "bound": "gamma_(D+4) x summed magnitudes"}}
 
 
 def main():
@@ -293,6 +600,11 @@ def main():
     ap.add_argument("--serve-slot-windows", type=int, default=32)
     ap.add_argument("--serve-schedule", default="split", choices=["fused", "split"])
     ap.add_argument("--serve-chunk", type=int, default=4)
+    ap.add_argument("--serve-fast-rate", type=float, default=20000.0)
+    ap.add_argument("--serve-fast-requests", type=int, default=20000)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the plain FP64, backward and correlation records")
+    ap.add_argument("--corr-only", action="store_true", help="run only the correlation record")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--large-only", action="store_true",
                     help="run only the 64x256 large-window batch (for its profile) and print its record")
@@ -302,6 +614,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--pmc-workload", action="store_true",
                     help="run only the calibration copy and the solves (for counter runs)")
+    ap.add_argument("--pmc-target", default="assemble", choices=["assemble", "large", "corr"],
+                    help="what --pmc-workload runs after the calibration copy")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--pmc-command", default="python3 bench.py --pmc-workload --steps 3 --warmup 1")
     args = ap.parse_args()
@@ -325,6 +639,12 @@ def main():
     import torch
     from paper_2208_04726_amd import synth
     from paper_2208_04726_amd.solver import Solver, make_batch, capacities_for
+
+    if args.corr_only:
+        print(json.dumps(run_correlation(args, torch)), flush=True)
+        return
+    # the CPU baseline runs first, in processes started before the GPU is used
+    cpu = None if args.no_cpu_baseline else cpu_oracle_baseline(args.cpu_budget)
 
     iters = 2
     t0 = time.perf_counter()
@@ -381,6 +701,7 @@ def main():
     launch_ms = asm_ms / max(asm_n, 1)
     achieved = fl / (launch_ms / 1e3) / 1e12
     traffic, traffic_note = measured_traffic()
+    bound, bound_note = assembly_bound()
     kernels = {k: {"ms_per_launch": round(v[0] / v[1], 4), "launches_per_step": v[1] / n_bd}
                for k, v in kt_all.items() if v[1] > 0}
 
@@ -403,7 +724,8 @@ def main():
                    "schedule": args.schedule},
         "edges_per_s": round(Ea_total * iters / (ms_per_step / 1e3), 1),
         "kernels": kernels,
-        "roofline": {"bound": "mfma", "kernel": "k_assemble", "achieved": round(achieved, 3),
+        "roofline": {"bound": bound, "bound_evidence": bound_note, "kernel": "k_assemble",
+                     "achieved": round(achieved, 3),
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 5),
                      "traffic": traffic, "traffic_note": traffic_note,
                      "flops_per_launch": fl, "algorithmic_bytes_per_launch": by,
@@ -414,20 +736,40 @@ def main():
     if traffic:
         out["roofline"]["achieved_hbm_gbs"] = round(traffic / (launch_ms / 1e3) / 1e9, 1)
         out["roofline"]["hbm_frac"] = round(traffic / (launch_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 5)
+    # parity of the timed batch's own results: four windows against the oracle
+    from oracle import ba_oracle as O
+    pn, dn = poses_out.cpu().numpy(), depth_out.cpu().numpy()
+    pairs = []
+    for i in range(4):
+        f0, f1 = batch.frame_off[i], batch.frame_off[i + 1]
+        p0, p1 = batch.patch_off[i], batch.patch_off[i + 1]
+        pr, dr = O.solve(windows[i])
+        pairs.append((pn[f0:f1], dn[p0:p1], pr, dr))
+    out["parity"] = {"method_scale": parity_record(pairs, "oracle dense FP64 solve, windows 0-3 of the timed batch")}
     solver.close()
     del batch, poses_out, depth_out
     torch.cuda.empty_cache()
 
     if not args.no_large:
         out["large_window"] = run_large(args, torch)
+        out["parity"]["large_window"] = out["large_window"]["parity"]
         log(f"large windows: {out['large_window']}")
     if not args.no_serve:
         s = run_serving(args, torch)
         out["serving"] = s
+        out["parity"]["serving"] = s["parity"]
         out["latency_ms"] = {"batched_p50": s["batched"].get("p50_ms"), "batched_p99": s["batched"].get("p99_ms"),
                              "plain_p50": s["plain"].get("p50_ms"), "plain_p99": s["plain"].get("p99_ms")}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_oracle_baseline(windows, args.cpu_budget)
+    if not args.no_extra:
+        out["plain_fp64"] = run_plain_fp64(args, torch)
+        out["parity"]["plain_fp64"] = out["plain_fp64"]["parity"]
+        log(f"plain fp64: {out['plain_fp64']}")
+        out["backward"] = run_backward(args, torch)
+        log(f"backward: {out['backward']}")
+        out["correlation"] = run_correlation(args, torch)
+        log(f"correlation: {out['correlation']}")
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -88,40 +88,63 @@ struct Params {
 };
 
 // Products of the patch features (operand a: lane row l & 15, channels
-// 8*(l >> 4) .. + 7 of each 32-channel block) with the features of `n_pts`
-// lattice points starting at box index `t0`, box origin (bx0, by0), width
-// wb; rows < P2 of the result go to raw[row * NBMAX + col].
-template <int KB>
+// 8*(l >> 4) .. + 7 of each 32-channel block) with the features of the `nb`
+// lattice points of the box with origin (bx0, by0) and width wb; rows < P2
+// (only row `row_keep` when it is >= 0) go to raw[row * NBMAX + point].
+// Tiles are taken TG at a time, every load of the group issued before its
+// matrix-core products.
+template <int KB, int TG>
 __device__ __forceinline__ void box_products(const bf16x8 (&a)[KB], const uint16_t* fm, int H, int W, int bx0,
                                              int by0, int wb, int nb, int row_keep, float* raw, int P2) {
   const int l = threadIdx.x & 63;
   const int kq = l >> 4, col = l & 15;
   const int D = KB * 32;
-  for (int t0 = 0; t0 < nb; t0 += 16) {
-    const int n = t0 + col;
-    const int bx = bx0 + n % wb, by = by0 + n / wb;
-    const bool ok = n < nb && bx >= 0 && bx < W && by >= 0 && by < H;
-    const uint16_t* src = fm + ((int64_t)(ok ? by : 0) * W + (ok ? bx : 0)) * D + kq * 8;
-    bf16x8 b[KB];
+  for (int t0 = 0; t0 < nb; t0 += 16 * TG) {
+    bf16x8 b[TG][KB];
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb) b[kb] = ok ? load_bf16x8(src + kb * 32) : zero_bf16x8();
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int g = 0; g < TG; ++g) {
+      const int n = t0 + 16 * g + col;
+      const int bx = bx0 + n % wb, by = by0 + n / wb;
+      const bool ok = n < nb && bx >= 0 && bx < W && by >= 0 && by < H;
+      const uint16_t* src = fm + ((int64_t)(ok ? by : 0) * W + (ok ? bx : 0)) * D + kq * 8;
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kb], b[kb], acc, 0, 0, 0);
-    if (n < nb) {
+      for (int kb = 0; kb < KB; ++kb) b[g][kb] = ok ? load_bf16x8(src + kb * 32) : zero_bf16x8();
+    }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 4 * kq + r;
-        if (row < P2 && (row_keep < 0 || row == row_keep)) raw[row * NBMAX + n] = acc[r];
+    for (int g = 0; g < TG; ++g) {
+      const int n = t0 + 16 * g + col;
+      if (t0 + 16 * g >= nb) break;   // uniform: the group's remaining tiles are empty
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[kb], b[g][kb], acc, 0, 0, 0);
+      if (n < nb) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 4 * kq + r;
+          if (row < P2 && (row_keep < 0 || row == row_keep)) raw[row * NBMAX + n] = acc[r];
+        }
       }
     }
   }
 }
 
+// Tiles per load group.  Measured on MI355X for D = 128 (22 x 96 graph,
+// 39,552 edges): groups of 2 tiles with a 5-waves-per-SIMD register target,
+// 0.212 ms; groups of 4 (138 registers, 3 waves), 0.243 ms; one tile at a
+// time, 0.245 ms.
 template <int KB>
-__global__ void __launch_bounds__(64 * WAVES) k_corr(Params P) {
-  __shared__ float raw_s[WAVES][PMAX * NBMAX];
-  __shared__ PixelBox pix_s[WAVES][PMAX];
+struct TileGroup {
+  static constexpr int value = 2;
+};
+
+// LDS of a workgroup: per wave the lattice products of its P2 rows and the
+// pixel boxes.
+__host__ __device__ constexpr int corr_lds_bytes(int P2) {
+  return WAVES * (P2 * NBMAX * 4 + PMAX * (int)sizeof(PixelBox));
+}
+
+template <int KB>
+__device__ __forceinline__ void corr_edge(const Params& P, char* smem) {
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t e = (int64_t)blockIdx.x * WAVES + wave;
   if (e >= P.E) return;   // the whole wave leaves; no workgroup barrier follows
@@ -134,8 +157,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_corr(Params P) {
     if (l == 0 && P.status) atomicOr(P.status, BA_W_BAD_INDEX);
     return;
   }
-  float* raw = raw_s[wave];
-  PixelBox* pix = pix_s[wave];
+  float* raw = (float*)(smem + wave * (P2 * NBMAX * 4));
+  PixelBox* pix = (PixelBox*)(smem + WAVES * P2 * NBMAX * 4) + wave * PMAX;
   // operand a: patch feature rows (zero beyond the patch's pixels)
   bf16x8 a[KB];
   {
@@ -181,13 +204,13 @@ __global__ void __launch_bounds__(64 * WAVES) k_corr(Params P) {
       pix[l] = b;
     }
     if (united) {
-      box_products<KB>(a, fm, H, W, lo_x - RAD, lo_y - RAD, wb, wb * hb, -1, raw, P2);
+      box_products<KB, TileGroup<KB>::value>(a, fm, H, W, lo_x - RAD, lo_y - RAD, wb, wb * hb, -1, raw, P2);
     } else if (any) {
       for (int m = 0; m < P2; ++m) {
         const int lm = __shfl(live, m);
         if (!lm) continue;
         const int bx = __shfl(ix, m) - RAD, by = __shfl(iy, m) - RAD;
-        box_products<KB>(a, fm, H, W, bx, by, LAT, LAT * LAT, m, raw, P2);
+        box_products<KB, TileGroup<KB>::value>(a, fm, H, W, bx, by, LAT, LAT * LAT, m, raw, P2);
       }
     }
     wave_lds_sync();
@@ -208,6 +231,19 @@ __global__ void __launch_bounds__(64 * WAVES) k_corr(Params P) {
     }
     wave_lds_sync();
   }
+}
+
+// D = 64, 128: a register target of 5 waves per SIMD (measured faster, see
+// TileGroup); D = 256 keeps the default (the target would spill).
+template <int KB>
+__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(5))) k_corr(Params P) {
+  extern __shared__ __align__(16) char smem[];
+  corr_edge<KB>(P, smem);
+}
+
+__global__ void __launch_bounds__(64 * WAVES) k_corr_wide(Params P) {
+  extern __shared__ __align__(16) char smem[];
+  corr_edge<8>(P, smem);
 }
 
 // Average pooling: one thread per 8 channels of an output pixel.
@@ -282,7 +318,7 @@ int dpc_correlation(const dpc_corr_problem* p, void* stream) {
   if (!(p->scale1 > 0.0f) || !std::isfinite(p->scale1)) return BA_E_INVAL;
   if (p->n_frames < 1 || p->n_patches < 1) return BA_E_INVAL;
   if (!p->level0 || !p->level1 || !p->gmap || !p->coords || !p->kk || !p->jj || !p->out) return BA_E_INVAL;
-  Params P;
+  Params P{};   // every field zero unless set below
   P.D = D;
   P.P2 = P2;
   P.H0 = p->height0;
@@ -304,9 +340,10 @@ int dpc_correlation(const dpc_corr_problem* p, void* stream) {
   const int64_t blocks = (p->n_edges + WAVES - 1) / WAVES;
   if (blocks > 0x7fffffffLL) return BA_E_INVAL;
   hipStream_t s = (hipStream_t)stream;
-  if (D == 64) hipLaunchKernelGGL(k_corr<2>, dim3((unsigned)blocks), dim3(64 * WAVES), 0, s, P);
-  else if (D == 128) hipLaunchKernelGGL(k_corr<4>, dim3((unsigned)blocks), dim3(64 * WAVES), 0, s, P);
-  else hipLaunchKernelGGL(k_corr<8>, dim3((unsigned)blocks), dim3(64 * WAVES), 0, s, P);
+  const int lds = corr_lds_bytes(P2);
+  if (D == 64) hipLaunchKernelGGL(k_corr<2>, dim3((unsigned)blocks), dim3(64 * WAVES), lds, s, P);
+  else if (D == 128) hipLaunchKernelGGL(k_corr<4>, dim3((unsigned)blocks), dim3(64 * WAVES), lds, s, P);
+  else hipLaunchKernelGGL(k_corr_wide, dim3((unsigned)blocks), dim3(64 * WAVES), lds, s, P);
   return hipGetLastError() == hipSuccess ? BA_OK : BA_E_HIP;
 }
 

@@ -13,7 +13,9 @@ batched solve:
   * admission: requests are taken first-come first-served while the batch
     still fits the slot's footprint (continuous batching: a slot launches as
     soon as it is free and a request waits; a request never waits for a batch
-    to fill);
+    to fill); a request larger than a slot is answered at once with
+    BA_E_CAPACITY; slots are created while the measured footprint of one
+    slot still leaves a reserve of free HBM;
   * per batch: pack into pinned staging, one asynchronous copy per array,
     ba_prepare (descriptor upload) and the graph replay (or ba_launch), copies
     of the results back to pinned memory and an event; the host polls the
@@ -185,8 +187,14 @@ class Result:
     rid: int
     poses: np.ndarray      # f64 [N,7]
     depth: np.ndarray      # f64 [M]
-    status: int            # BA_W_* bits
+    status: int            # BA_W_* bits, or BA_E_CAPACITY for a request no slot can hold
     latency: float         # seconds, arrival to result on the host
+
+
+def rejected(r: Request, latency: float = 0.0) -> Result:
+    """The answer to a request larger than a slot: BA_E_CAPACITY, the inputs
+    unchanged."""
+    return Result(r.rid, r.poses.copy(), r.patches[:, 2].copy(), native.BA_E_CAPACITY, latency)
 
 
 class _Slot:
@@ -272,13 +280,23 @@ class BatchedServer:
 
     def __init__(self, cap: Capacity, n_slots: int = 2, precision: str = "fp32",
                  iterations: int = 2, schedule: str = "fused", chunk_frames: int = 11,
-                 use_graph: bool = True, device="cuda"):
+                 use_graph: bool = True, device="cuda", hbm_reserve: float = 0.1):
         if schedule not in ("fused", "split"):
             raise ValueError("schedule must be 'fused' or 'split'")
         self.cap = cap
+        total = torch.cuda.mem_get_info(device)[1]
         free0 = torch.cuda.mem_get_info(device)[0]
-        self.slots = [_Slot(cap, precision, iterations, schedule, chunk_frames, use_graph, device)
-                      for _ in range(n_slots)]
+        # slots are admitted by HBM footprint: the first slot's footprint is
+        # measured, and further slots are created while the free HBM after
+        # them stays above `hbm_reserve` of the device
+        self.slots = [_Slot(cap, precision, iterations, schedule, chunk_frames, use_graph, device)]
+        torch.cuda.synchronize(device)
+        self.slot_bytes = int(free0 - torch.cuda.mem_get_info(device)[0])
+        while len(self.slots) < n_slots:
+            free = torch.cuda.mem_get_info(device)[0]
+            if free - self.slot_bytes < hbm_reserve * total:
+                break
+            self.slots.append(_Slot(cap, precision, iterations, schedule, chunk_frames, use_graph, device))
         torch.cuda.synchronize(device)
         # device memory the slots hold (buffers, library workspace, graphs)
         self.footprint_bytes = int(free0 - torch.cuda.mem_get_info(device)[0])
@@ -287,10 +305,9 @@ class BatchedServer:
 
     def run(self, requests: Sequence[Request], clock=time.perf_counter) -> Dict[int, Result]:
         """Serve `requests` (sorted by arrival) in real time: a request becomes
-        visible at its arrival time.  Returns rid -> Result."""
-        for r in requests:
-            if not self.cap.fits(r):
-                raise ValueError(f"request {r.rid} exceeds the slot capacity")
+        visible at its arrival time.  A request no slot can hold is answered at
+        its arrival with BA_E_CAPACITY (`rejected`); the others are served.
+        Returns rid -> Result."""
         with _no_gc():
             return self._run(requests, clock)
 
@@ -303,7 +320,11 @@ class BatchedServer:
         while len(results) < n:
             now = clock() - t0
             while i < n and requests[i].arrival <= now:
-                pending.append(requests[i])
+                r = requests[i]
+                if self.cap.fits(r):
+                    pending.append(r)
+                else:
+                    results[r.rid] = rejected(r, clock() - t0 - r.arrival)
                 i += 1
             for s in self.slots:
                 if s.busy and s.done():
@@ -344,6 +365,9 @@ class PlainServer:
         for r in requests:
             while clock() - t0 < r.arrival:
                 pass
+            if not self.cap.fits(r):
+                results[r.rid] = rejected(r, clock() - t0 - r.arrival)
+                continue
             F, P, E = self.buf.pack([r])
             with torch.cuda.stream(self.stream):
                 self.buf.upload(F, P, E)

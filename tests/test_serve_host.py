@@ -74,3 +74,27 @@ def test_latency_summary():
     assert s["n"] == 100 and abs(s["p50_ms"] - 50.5) < 1e-9 and abs(s["mean_ms"] - 50.5) < 1e-9
     s = serve.latency_summary(res, skip=90)
     assert s["n"] == 10 and s["p99_ms"] <= 100.0
+
+
+class _FakeSlotless(serve.BatchedServer):
+    """BatchedServer without slots (no GPU): every fitting request stays
+    pending, so only the rejection path answers."""
+
+    def __init__(self, cap):
+        self.cap = cap
+        self.slots = []
+        self.batches = 0
+        self.batch_sizes = []
+
+
+def test_oversize_request_is_rejected_alone():
+    from paper_2208_04726_amd import native
+    cap = serve.Capacity(windows=4, frames=44, patches=200, edges=2000, frames_per_window=22)
+    big = _req(7, 23, 10, 10)          # more frames than a window may hold
+    wide = _req(8, 10, 500, 10)        # more patches than a slot holds
+    srv = _FakeSlotless(cap)
+    res = srv._run([big, wide], clock=iter(np.arange(0.0, 100.0, 0.01)).__next__)
+    assert set(res) == {7, 8}
+    for r in res.values():
+        assert r.status == native.BA_E_CAPACITY
+    assert res[7].poses.shape == (23, 7) and res[8].depth.shape == (500,)
