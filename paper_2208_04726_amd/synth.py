@@ -397,3 +397,51 @@ def method_scale_correlation(window_id: int = 0) -> CorrWorkload:
     included) over 160 x 120 first-level and 40 x 30 second-level maps of 128
     channels, 3 x 3 patches."""
     return correlation_workload(22, 96, 13, seed=[2208, 5, window_id])
+
+
+# ---------------------------------------------------------------- soft-aggregation workloads
+HIDDEN_DIM = 384        # hidden state of an edge in the update operator
+
+
+@dataclasses.dataclass
+class AggWorkload:
+    """Inputs of the soft aggregation over one window's patch graph."""
+    x: np.ndarray          # [E, dim] float32, bf16-exact: hidden state of each edge
+    kk: np.ndarray         # [E] int32
+    jj: np.ndarray         # [E] int32
+    anchor: np.ndarray     # [M] int32
+    n_frames: int
+    w: tuple               # 3 x [dim, dim] float32, bf16-exact: gate, value, output layers (out, in)
+    b: tuple               # 3 x [dim] float32: their biases
+
+    @property
+    def n_edges(self) -> int:
+        return int(self.kk.shape[0])
+
+
+def aggregation_workload(n_frames: int, ppf: int, radius: int, *, seed: Sequence[int],
+                         dim: int = HIDDEN_DIM) -> AggWorkload:
+    """Random N(0,1) hidden states over the patch graph of a window (every
+    patch joined to every frame within `radius` of its source frame) and
+    random linear layers, weights N(0, 1/dim) and biases N(0, 0.01)."""
+    rng = np.random.default_rng(list(seed))
+    M = n_frames * ppf
+    anchor = np.repeat(np.arange(n_frames, dtype=np.int32), ppf)
+    kk_l, jj_l = [], []
+    for k in range(M):
+        i = int(anchor[k])
+        for j in range(max(0, i - radius), min(n_frames - 1, i + radius) + 1):
+            kk_l.append(k)
+            jj_l.append(j)
+    kk = np.asarray(kk_l, np.int32)
+    jj = np.asarray(jj_l, np.int32)
+    x = bf16_exact(rng.normal(size=(len(kk), dim)).astype(np.float32))
+    w = tuple(bf16_exact((rng.normal(size=(dim, dim)) / np.sqrt(dim)).astype(np.float32)) for _ in range(3))
+    b = tuple((rng.normal(size=dim) * 0.1).astype(np.float32) for _ in range(3))
+    return AggWorkload(x=x, kk=kk, jj=jj, anchor=anchor, n_frames=n_frames, w=w, b=b)
+
+
+def method_scale_aggregation(window_id: int = 0) -> AggWorkload:
+    """The 22-frame x 96-patch, radius-13 patch graph (39,552 edges) with
+    384-channel hidden states."""
+    return aggregation_workload(22, 96, 13, seed=[2208, 10, window_id])
