@@ -20,7 +20,8 @@ BA_W_OK, BA_W_NOT_SPD, BA_W_NONFINITE, BA_W_BAD_INDEX, BA_W_DEGREE = 0, 1, 2, 4,
 EXPORTED = ("ba_create", "ba_solve", "ba_backward", "ba_prepare", "ba_launch", "ba_set_timing",
             "ba_kernel_times", "ba_status", "ba_last_error", "ba_destroy",
             "ba_debug_reduced_system", "ba_debug_mfma", "ba_solve_noalloc",
-            "dpc_correlation", "dpc_avg_pool", "dpc_debug_mfma_bf16")
+            "dpc_correlation", "dpc_avg_pool", "dpc_debug_mfma_bf16",
+            "dpa_softagg", "dpa_workspace_bytes")
 STAGES = ("prep", "assemble", "chol", "backsub", "finalize", "fused")
 
 
@@ -53,6 +54,17 @@ class DPCProblem(ctypes.Structure):
                 ("level0", ctypes.c_void_p), ("level1", ctypes.c_void_p), ("gmap", ctypes.c_void_p),
                 ("coords", ctypes.c_void_p), ("kk", ctypes.c_void_p), ("jj", ctypes.c_void_p),
                 ("out", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
+class DPAProblem(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("dim", ctypes.c_int32),
+                ("n_edges", ctypes.c_int64), ("n_patches", ctypes.c_int64),
+                ("n_frames", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("x", ctypes.c_void_p), ("kk", ctypes.c_void_p), ("jj", ctypes.c_void_p),
+                ("anchor", ctypes.c_void_p), ("w_gate", ctypes.c_void_p), ("b_gate", ctypes.c_void_p),
+                ("w_val", ctypes.c_void_p), ("b_val", ctypes.c_void_p), ("w_out", ctypes.c_void_p),
+                ("b_out", ctypes.c_void_p), ("out", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_int64), ("status", ctypes.c_void_p)]
 
 
 _LIB = None
@@ -99,6 +111,10 @@ def lib() -> ctypes.CDLL:
         L.dpc_avg_pool.restype = ctypes.c_int
         L.dpc_debug_mfma_bf16.argtypes = [vp, vp, vp, vp]
         L.dpc_debug_mfma_bf16.restype = ctypes.c_int
+        L.dpa_softagg.argtypes = [ctypes.POINTER(DPAProblem), vp]
+        L.dpa_softagg.restype = ctypes.c_int
+        L.dpa_workspace_bytes.argtypes = [i32, i32, ctypes.c_int64, ctypes.c_int64, i32]
+        L.dpa_workspace_bytes.restype = ctypes.c_int64
         _LIB = L
     return _LIB
 
