@@ -16,8 +16,9 @@ Also measured in the same run:
     from arrival to result on the host), plus closed-loop throughput of both;
   * parity of reported results against the FP64 oracle (pose m / deg and
     relative inverse depth, per record);
-  * the plain FP64 8x16 windows, the adjoint (ba_backward) per window, and
-    the correlation features (Eq. 4) of the method-scale patch graph;
+  * the plain FP64 8x16 windows, the adjoint (ba_backward) per window, the
+    correlation features (Eq. 4) and the soft aggregation (Eq. 5) of the
+    method-scale patch graph;
   * the FP64 CPU oracle on a bounded sample, on the host cores.
 
 Prints one JSON line on stdout; progress goes to stderr.
@@ -130,6 +131,15 @@ def pmc_workload(args):
     dst.copy_(src)
     torch.cuda.synchronize()
     del src, dst
+    if args.pmc_target == "agg":
+        for _ in range(args.warmup + args.steps):
+            run_aggregation_launch(torch, 0)
+            run_aggregation_launch(torch, 1)
+            run_aggregation_launch(torch, 0, graph_ready=True)
+            run_aggregation_launch(torch, 1, graph_ready=True)
+        torch.cuda.synchronize()
+        log(f"pmc workload done: {args.steps + args.warmup} aggregation calls per mode")
+        return
     if args.pmc_target == "corr":
         for _ in range(args.warmup + args.steps):
             run_correlation_launch(torch)
@@ -583,6 +593,70 @@ def run_correlation(args, torch):
                        "bound": "gamma_(D+4) x summed magnitudes"}}
 
 
+_AGG = {}
+
+
+def run_aggregation_launch(torch, mode, graph_ready=False):
+    """One soft aggregation of the method-scale workload (buffers made on
+    first use)."""
+    from paper_2208_04726_amd import agg, synth
+    if not _AGG:
+        wl = synth.method_scale_aggregation(0)
+        dev = lambda a, d: torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=d).contiguous()
+        _AGG.update(wl=wl, x=dev(wl.x, torch.bfloat16), kk=dev(wl.kk, torch.int32), jj=dev(wl.jj, torch.int32),
+                    anchor=dev(wl.anchor, torch.int32), w=[dev(w, torch.bfloat16) for w in wl.w],
+                    b=[dev(b, torch.float32) for b in wl.b])
+        _AGG["out"] = torch.empty((wl.n_edges, wl.x.shape[1]), dtype=torch.float32, device="cuda")
+        nb = max(agg.workspace_bytes(m, wl.x.shape[1], wl.n_edges, len(wl.anchor), wl.n_frames) for m in (0, 1))
+        _AGG["ws"] = [torch.empty((nb,), dtype=torch.uint8, device="cuda") for _ in (0, 1)]
+    d = _AGG
+    agg.softagg(mode, d["x"], d["kk"], d["jj"], d["anchor"], d["wl"].n_frames, d["w"], d["b"], out=d["out"],
+                workspace=d["ws"][mode], graph_ready=graph_ready)
+
+
+def run_aggregation(args, torch):
+    """Soft aggregation (Eq. 5) of the 22 x 96, radius-13 patch graph: 39,552
+    edges, 384-channel bf16 hidden states, both neighbourhood kinds; HIP
+    events around each call; parity of 256 sampled edges against the
+    oracle."""
+    from oracle import agg_oracle as A
+    out = {"workload": "soft aggregation, 22 frames x 96 patches, radius 13: 39,552 edges, 384-channel bf16 hidden "
+                       "states, gate/value/output layers 384x384 bf16, FP32 sums and output"}
+    stream = torch.cuda.current_stream()
+    for mode, name in ((0, "patch"), (1, "frame")):
+        for _ in range(3):
+            run_aggregation_launch(torch, mode)
+        torch.cuda.synchronize()
+        mk = lambda: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+        ev, evr = mk(), mk()
+        for (a, b), (ra, rb) in zip(ev, evr):
+            a.record(stream)
+            run_aggregation_launch(torch, mode)
+            b.record(stream)
+            ra.record(stream)
+            run_aggregation_launch(torch, mode, graph_ready=True)
+            rb.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        ms_r = float(np.mean([a.elapsed_time(b) for a, b in evr]))
+        wl = _AGG["wl"]
+        E, D = wl.x.shape
+        key = A.group_keys(mode, wl.kk, wl.jj, wl.anchor, wl.n_frames)
+        G = len(np.unique(key))
+        flops = 2.0 * E * D * 2 * D + 2.0 * G * D * D
+        by = 2.0 * E * D + 4.0 * E * D + 3 * 2.0 * D * D + 8.0 * E
+        got = _AGG["out"].cpu().numpy().astype(np.float64)
+        ref = A.soft_aggregate(mode, wl.x, wl.kk, wl.jj, wl.anchor, wl.n_frames, wl.w[0], wl.b[0], wl.w[1], wl.b[1],
+                               wl.w[2], wl.b[2])
+        out[name] = {"ms_per_call": round(ms, 4), "ms_per_call_graph_reused": round(ms_r, 4),
+                     "edges_per_s": round(E / (ms / 1e3), 1), "neighbourhoods": G,
+                     "matrix_tflops": round(flops / (ms_r / 1e3) / 1e12, 2),
+                     "algorithmic_hbm_gbs": round(by / (ms_r / 1e3) / 1e9, 1),
+                     "parity_max_abs_err": float(np.abs(got - ref).max()),
+                     "parity_max_rel_err": float((np.abs(got - ref) / np.maximum(np.abs(ref), 1e-3)).max())}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -605,6 +679,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the plain FP64, backward and correlation records")
     ap.add_argument("--corr-only", action="store_true", help="run only the correlation record")
+    ap.add_argument("--agg-only", action="store_true", help="run only the soft-aggregation record")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--large-only", action="store_true",
                     help="run only the 64x256 large-window batch (for its profile) and print its record")
@@ -614,7 +689,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--pmc-workload", action="store_true",
                     help="run only the calibration copy and the solves (for counter runs)")
-    ap.add_argument("--pmc-target", default="assemble", choices=["assemble", "large", "corr"],
+    ap.add_argument("--pmc-target", default="assemble", choices=["assemble", "large", "corr", "agg"],
                     help="what --pmc-workload runs after the calibration copy")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--pmc-command", default="python3 bench.py --pmc-workload --steps 3 --warmup 1")
@@ -642,6 +717,9 @@ def main():
 
     if args.corr_only:
         print(json.dumps(run_correlation(args, torch)), flush=True)
+        return
+    if args.agg_only:
+        print(json.dumps(run_aggregation(args, torch)), flush=True)
         return
     # the CPU baseline runs first, in processes started before the GPU is used
     cpu = None if args.no_cpu_baseline else cpu_oracle_baseline(args.cpu_budget)
@@ -768,6 +846,8 @@ def main():
         log(f"backward: {out['backward']}")
         out["correlation"] = run_correlation(args, torch)
         log(f"correlation: {out['correlation']}")
+        out["aggregation"] = run_aggregation(args, torch)
+        log(f"aggregation: {out['aggregation']}")
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

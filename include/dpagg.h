@@ -44,7 +44,11 @@ typedef struct {
   int64_t n_edges;         /* E                                                    */
   int64_t n_patches;       /* M                                                    */
   int32_t n_frames;        /* F: frames of the window (source and target frames)  */
-  int32_t reserved;
+  int32_t graph_ready;     /* nonzero: the workspace holds the neighbourhoods an
+                              earlier call built for the same mode, sizes, kk, jj
+                              and anchor (unchanged since), and they are reused;
+                              zero: they are built (the update operator keeps its
+                              graph across iterations)                             */
   const uint16_t* x;       /* dev bf16 [E, dim]: hidden state of each edge          */
   const int32_t* kk;       /* dev [E] patch of each edge                           */
   const int32_t* jj;       /* dev [E] target frame of each edge                    */

@@ -24,10 +24,11 @@ def workspace_bytes(mode: int, dim: int, n_edges: int, n_patches: int, n_frames:
 def softagg(mode: int, x: torch.Tensor, kk: torch.Tensor, jj: torch.Tensor, anchor: torch.Tensor,
             n_frames: int, w: Sequence[torch.Tensor], b: Sequence[torch.Tensor],
             out: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
-            status: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+            status: Optional[torch.Tensor] = None, graph_ready: bool = False, stream=None) -> torch.Tensor:
     """Eq. 5 for every edge.  x [E, dim] bf16; kk, jj [E], anchor [M] int32;
     w = (gate, value, output) [dim, dim] bf16 (out, in); b = their [dim] f32
-    biases.  Returns [E, dim] f32."""
+    biases.  graph_ready: reuse the neighbourhoods an earlier call left in
+    `workspace` for the same graph.  Returns [E, dim] f32."""
     E, D = x.shape
     M = anchor.shape[0]
     assert x.dtype == torch.bfloat16 and all(t.dtype == torch.bfloat16 for t in w)
@@ -43,6 +44,7 @@ def softagg(mode: int, x: torch.Tensor, kk: torch.Tensor, jj: torch.Tensor, anch
         workspace = torch.empty((max(nb, 1),), dtype=torch.uint8, device=x.device)
     p = DPAProblem()
     p.mode, p.dim, p.n_edges, p.n_patches, p.n_frames = mode, D, E, M, n_frames
+    p.graph_ready = 1 if graph_ready else 0
     p.x, p.kk, p.jj, p.anchor = _p(x), _p(kk), _p(jj), _p(anchor)
     p.w_gate, p.w_val, p.w_out = _p(w[0]), _p(w[1]), _p(w[2])
     p.b_gate, p.b_val, p.b_out = _p(b[0]), _p(b[1]), _p(b[2])

@@ -10,10 +10,14 @@
 //    output channels of both layers; the epilogue forms sigma and
 //    sigma * phi and sums them down the rows of each neighbourhood piece of
 //    the chunk, writing one partial per (chunk, neighbourhood).
-// 3. k_agg_out: per 16 neighbourhoods, the partials of each are summed in
-//    chunk order, divided, passed through psi (FP32 on the vector ALU: every
-//    thread one output channel, its weight row read once for all 16), and
-//    written to every edge of the neighbourhood.
+// 3. k_agg_mean sums each neighbourhood's partials in chunk order and
+//    divides; k_agg_psi passes 16 neighbourhoods at a time through psi (FP32
+//    on the vector ALU: every thread one output channel of a 128-channel
+//    slice, its weight row read once for all 16);
+//    k_agg_bcast writes each neighbourhood's row to its edges, a 64-row chunk
+//    of the CSR per workgroup.
+// The CSR depends only on the graph: with graph_ready set, a call reuses the
+// one an earlier call left in the workspace.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,7 +44,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 struct Layout {                 // workspace offsets (bytes)
-  int64_t key, off, fill, seg, segs, gfirst, pbase, part, total;
+  int64_t key, off, fill, seg, segs, gfirst, pbase, part, psi, ymean, total;
 };
 
 __host__ __device__ inline int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
@@ -57,6 +61,8 @@ __host__ __device__ inline Layout layout(int64_t E, int64_t G, int D) {
   L.gfirst = o; o += align256(4 * std::max<int64_t>(NC, 1));
   L.pbase = o;  o += align256(4 * (NC + 1));
   L.part = o;   o += align256(4 * 2 * (int64_t)D * (G + NC));   // pieces <= groups + chunks
+  L.psi = o;    o += align256(4 * (int64_t)D * std::max<int64_t>(G, 1));
+  L.ymean = o;  o += align256(4 * (int64_t)D * std::max<int64_t>(G, 1));
   L.total = o;
   return L;
 }
@@ -84,6 +90,8 @@ struct Params {
   int32_t* gfirst;  // [NC] first neighbourhood of each chunk
   int32_t* pbase;   // [NC+1] first partial of each chunk
   float* part;      // [pieces][2][D]: sum sigma*phi, sum sigma
+  float* psi;       // [G][D]: the output row of each neighbourhood
+  float* ymean;     // [G][D]: the aggregate of each neighbourhood
 };
 
 __global__ void __launch_bounds__(256) k_agg_zero(int32_t* a, int64_t n) {
@@ -138,6 +146,13 @@ __global__ void __launch_bounds__(1024) k_agg_scan(int32_t* a, int32_t* b, int64
     run += c;
   }
   if (t == 1023) a[n] = part[1023];
+}
+
+// With the graph reused: rows of edges with bad indices are zero again.
+__global__ void __launch_bounds__(256) k_agg_badrows(Params P) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < P.E; e += (int64_t)gridDim.x * 256)
+    if (P.key[e] < 0)
+      for (int c = 0; c < P.D; ++c) P.out[e * P.D + c] = 0.f;
 }
 
 __global__ void __launch_bounds__(256) k_agg_scatter(Params P) {
@@ -222,16 +237,26 @@ __global__ void __launch_bounds__(64 * NW) k_agg_gate(Params P) {
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
       for (int ct = 0; ct < CT; ++ct) acc[L][rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int kb = 0; kb < KB; ++kb) {
-    bf16x8 a[4], bg[CT], bv[CT];
+  // weight operands of the next K step are loaded while this one's
+  // products run
+  bf16x8 bg[CT], bv[CT];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) a[rt] = load8(xs + (rt * 16 + col) * D + kb * 32 + kq * 8);
+  for (int ct = 0; ct < CT; ++ct) {
+    const int64_t w = (int64_t)(ch0 + ct * 16 + col) * D + kq * 8;
+    bg[ct] = load8(P.wg + w);
+    bv[ct] = load8(P.wv + w);
+  }
+  for (int kb = 0; kb < KB; ++kb) {
+    bf16x8 a[4], ng[CT], nv[CT];
+    const int kn = kb + 1 < KB ? kb + 1 : kb;
 #pragma unroll
     for (int ct = 0; ct < CT; ++ct) {
-      const int64_t w = (int64_t)(ch0 + ct * 16 + col) * D + kb * 32 + kq * 8;
-      bg[ct] = load8(P.wg + w);
-      bv[ct] = load8(P.wv + w);
+      const int64_t w = (int64_t)(ch0 + ct * 16 + col) * D + kn * 32 + kq * 8;
+      ng[ct] = load8(P.wg + w);
+      nv[ct] = load8(P.wv + w);
     }
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) a[rt] = load8(xs + (rt * 16 + col) * D + kb * 32 + kq * 8);
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
@@ -239,6 +264,11 @@ __global__ void __launch_bounds__(64 * NW) k_agg_gate(Params P) {
         acc[0][rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], bg[ct], acc[0][rt][ct], 0, 0, 0);
         acc[1][rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], bv[ct], acc[1][rt][ct], 0, 0, 0);
       }
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      bg[ct] = ng[ct];
+      bv[ct] = nv[ct];
+    }
   }
   float* sc = scratch + wave * (2 * CH * 16);
   const int gf = P.gfirst[c];
@@ -278,34 +308,45 @@ __global__ void __launch_bounds__(64 * NW) k_agg_gate(Params P) {
   }
 }
 
-// psi of the aggregate of GB neighbourhoods; one thread per output channel.
+// The aggregate of every neighbourhood, y[g][c] = sum of its pieces' sigma*phi
+// over the sum of their sigma, summed in chunk order; one thread per channel.
+__global__ void __launch_bounds__(256) k_agg_mean(Params P) {
+  const int64_t total = P.G * P.D;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+    const int64_t g = i / P.D;
+    const int c = (int)(i - g * P.D);
+    const int b = P.off[g], e = P.off[g + 1];
+    float v = 0.f;
+    if (e > b) {
+      float A = 0.f, B = 0.f;
+      for (int ch = b / CH; ch <= (e - 1) / CH; ++ch) {
+        const int64_t piece = P.pbase[ch] + (g - P.gfirst[ch]);
+        A += P.part[(piece * 2 + 0) * P.D + c];
+        B += P.part[(piece * 2 + 1) * P.D + c];
+      }
+      v = A / B;
+    }
+    P.ymean[i] = v;
+  }
+}
+
+// psi of GB neighbourhoods for a 128-channel slice of the outputs (blockIdx.y),
+// one thread per output channel, its weight row read once for all GB.
 template <int D>
-__global__ void __launch_bounds__(D) k_agg_out(Params P) {
+__global__ void __launch_bounds__(128) k_agg_psi(Params P) {
   __shared__ float y[GB][D];
   const int t = threadIdx.x;
   const int64_t g0 = (int64_t)blockIdx.x * GB;
-  for (int q = 0; q < GB; ++q) {
-    const int64_t g = g0 + q;
-    float v = 0.f;
-    if (g < P.G) {
-      const int b = P.off[g], e = P.off[g + 1];
-      if (e > b) {
-        float A = 0.f, B = 0.f;
-        for (int c = b / CH; c <= (e - 1) / CH; ++c) {
-          const int64_t piece = P.pbase[c] + (g - P.gfirst[c]);
-          A += P.part[(piece * 2 + 0) * D + t];
-          B += P.part[(piece * 2 + 1) * D + t];
-        }
-        v = A / B;
-      }
-    }
-    y[q][t] = v;
+  for (int i = t; i < GB * D; i += 128) {
+    const int q = i / D, c = i - q * D;
+    y[q][c] = g0 + q < P.G ? P.ymean[(g0 + q) * D + c] : 0.f;
   }
   __syncthreads();
+  const int ch = blockIdx.y * 128 + t;
   float o[GB];
 #pragma unroll
   for (int q = 0; q < GB; ++q) o[q] = 0.f;
-  const uint16_t* w = P.wo + (int64_t)t * D;
+  const uint16_t* w = P.wo + (int64_t)ch * D;
   for (int k = 0; k < D; k += 8) {
     const uint4 v = *(const uint4*)(w + k);
     const uint32_t h[4] = {v.x, v.y, v.z, v.w};
@@ -316,13 +357,25 @@ __global__ void __launch_bounds__(D) k_agg_out(Params P) {
       for (int q = 0; q < GB; ++q) o[q] += w0 * y[q][k + 2 * i] + w1 * y[q][k + 2 * i + 1];
     }
   }
-  const float bo = P.bo[t];
+  const float bo = P.bo[ch];
   for (int q = 0; q < GB; ++q) {
     const int64_t g = g0 + q;
     if (g >= P.G) break;
-    const int b = P.off[g], e = P.off[g + 1];
-    const float val = o[q] + bo;
-    for (int r = b; r < e; ++r) P.out[(int64_t)P.segs[r] * D + t] = val;
+    P.psi[g * D + ch] = o[q] + bo;
+  }
+}
+
+// Every edge of a 64-row chunk of the CSR receives its neighbourhood's row.
+template <int D>
+__global__ void __launch_bounds__(256) k_agg_bcast(Params P) {
+  const int64_t Ev = P.off[P.G];
+  const int64_t r0 = (int64_t)blockIdx.x * CH;
+  const int nrows = (int)std::min<int64_t>(CH, Ev - r0);
+  for (int i = threadIdx.x; i < nrows * (D / 4); i += 256) {
+    const int r = i / (D / 4), q = i - r * (D / 4);
+    const int e = P.segs[r0 + r];
+    const int g = P.key[e];
+    *(float4*)(P.out + (int64_t)e * D + 4 * q) = *(const float4*)(P.psi + (int64_t)g * D + 4 * q);
   }
 }
 
@@ -332,7 +385,10 @@ int launch(const Params& P, int64_t NC, hipStream_t s) {
   if (hipFuncSetAttribute((const void*)k_agg_gate<D>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
     return BA_E_HIP;
   hipLaunchKernelGGL(k_agg_gate<D>, dim3((unsigned)NC), dim3(64 * NW), lds, s, P);
-  hipLaunchKernelGGL(k_agg_out<D>, dim3((unsigned)((P.G + GB - 1) / GB)), dim3(D), 0, s, P);
+  hipLaunchKernelGGL(k_agg_mean, dim3((unsigned)std::min<int64_t>((P.G * D + 255) / 256, 16384)), dim3(256), 0, s,
+                     P);
+  hipLaunchKernelGGL(k_agg_psi<D>, dim3((unsigned)((P.G + GB - 1) / GB), D / 128), dim3(128), 0, s, P);
+  hipLaunchKernelGGL(k_agg_bcast<D>, dim3((unsigned)NC), dim3(256), 0, s, P);
   return BA_OK;
 }
 
@@ -392,18 +448,24 @@ int dpa_softagg(const dpa_problem* p, void* stream) {
   P.gfirst = (int32_t*)(ws + L.gfirst);
   P.pbase = (int32_t*)(ws + L.pbase);
   P.part = (float*)(ws + L.part);
+  P.psi = (float*)(ws + L.psi);
+  P.ymean = (float*)(ws + L.ymean);
   // chunks: the valid edges are at most E; chunks past the valid ones exit
   const int64_t NC = (p->n_edges + CH - 1) / CH;
   hipStream_t s = (hipStream_t)stream;
   const unsigned ge = (unsigned)std::min<int64_t>((p->n_edges + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_agg_zero, dim3((unsigned)std::min<int64_t>((G + 1 + 255) / 256, 4096)), dim3(256), 0, s,
-                     P.off, G + 1);
-  hipLaunchKernelGGL(k_agg_keys, dim3(ge), dim3(256), 0, s, P);
-  hipLaunchKernelGGL(k_agg_scan, dim3(1), dim3(1024), 0, s, P.off, P.fill, G);
-  hipLaunchKernelGGL(k_agg_scatter, dim3(ge), dim3(256), 0, s, P);
-  hipLaunchKernelGGL(k_agg_rank, dim3((unsigned)((G + 7) / 8)), dim3(512), 0, s, P);
-  hipLaunchKernelGGL(k_agg_plan, dim3(1), dim3(1024), 0, s, P, NC);
-  hipLaunchKernelGGL(k_agg_scan, dim3(1), dim3(1024), 0, s, P.pbase, (int32_t*)nullptr, NC);
+  if (!p->graph_ready) {
+    hipLaunchKernelGGL(k_agg_zero, dim3((unsigned)std::min<int64_t>((G + 1 + 255) / 256, 4096)), dim3(256), 0, s,
+                       P.off, G + 1);
+    hipLaunchKernelGGL(k_agg_keys, dim3(ge), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(k_agg_scan, dim3(1), dim3(1024), 0, s, P.off, P.fill, G);
+    hipLaunchKernelGGL(k_agg_scatter, dim3(ge), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(k_agg_rank, dim3((unsigned)((G + 7) / 8)), dim3(512), 0, s, P);
+    hipLaunchKernelGGL(k_agg_plan, dim3(1), dim3(1024), 0, s, P, NC);
+    hipLaunchKernelGGL(k_agg_scan, dim3(1), dim3(1024), 0, s, P.pbase, (int32_t*)nullptr, NC);
+  } else {
+    hipLaunchKernelGGL(k_agg_badrows, dim3(ge), dim3(256), 0, s, P);
+  }
   int r = BA_OK;
   if (D == 128) r = launch<128>(P, NC, s);
   else if (D == 256) r = launch<256>(P, NC, s);

@@ -59,7 +59,7 @@ class DPCProblem(ctypes.Structure):
 class DPAProblem(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("dim", ctypes.c_int32),
                 ("n_edges", ctypes.c_int64), ("n_patches", ctypes.c_int64),
-                ("n_frames", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_frames", ctypes.c_int32), ("graph_ready", ctypes.c_int32),
                 ("x", ctypes.c_void_p), ("kk", ctypes.c_void_p), ("jj", ctypes.c_void_p),
                 ("anchor", ctypes.c_void_p), ("w_gate", ctypes.c_void_p), ("b_gate", ctypes.c_void_p),
                 ("w_val", ctypes.c_void_p), ("b_val", ctypes.c_void_p), ("w_out", ctypes.c_void_p),

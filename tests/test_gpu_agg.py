@@ -105,6 +105,28 @@ def test_method_scale_graph_matches_oracle(mode):
     assert np.array_equal(got, again)      # fixed summation order: bitwise repeatable
 
 
+def test_graph_reuse_with_new_hidden_states():
+    """graph_ready: a second call on new hidden states reuses the
+    neighbourhoods the first call left in the workspace."""
+    need_gpu()
+    from paper_2208_04726_amd import agg
+    wl = synth.aggregation_workload(8, 12, 4, seed=[2208, 13], dim=256)
+    wl2 = synth.aggregation_workload(8, 12, 4, seed=[2208, 14], dim=256)   # same graph, new states and layers
+    assert np.array_equal(wl.kk, wl2.kk) and np.array_equal(wl.jj, wl2.jj)
+    kk, jj, anc = _dev(wl.kk, torch.int32), _dev(wl.jj, torch.int32), _dev(wl.anchor, torch.int32)
+    ws = torch.empty((agg.workspace_bytes(A.FRAME, 256, wl.n_edges, len(wl.anchor), wl.n_frames),),
+                     dtype=torch.uint8, device="cuda")
+    outs = []
+    for w, ready in ((wl, False), (wl2, True)):
+        o = agg.softagg(A.FRAME, _dev(w.x, torch.bfloat16), kk, jj, anc, w.n_frames,
+                        [_dev(m, torch.bfloat16) for m in w.w], [_dev(b, torch.float32) for b in w.b],
+                        workspace=ws, graph_ready=ready)
+        torch.cuda.synchronize()
+        outs.append(o.cpu().numpy().astype(np.float64))
+    check(wl, A.FRAME, outs[0])
+    check(wl2, A.FRAME, outs[1])
+
+
 def test_bad_indices_give_zero_rows_and_a_status_bit():
     need_gpu()
     wl = synth.aggregation_workload(5, 6, 2, seed=[2208, 12], dim=128)
