@@ -445,3 +445,79 @@ def method_scale_aggregation(window_id: int = 0) -> AggWorkload:
     """The 22-frame x 96-patch, radius-13 patch graph (39,552 edges) with
     384-channel hidden states."""
     return aggregation_workload(22, 96, 13, seed=[2208, 10, window_id])
+
+
+# ---------------------------------------------------------------- camera streams (sliding-window driver)
+@dataclasses.dataclass
+class Stream:
+    """A synthetic camera stream for the sliding-window driver.
+
+    The update operator, which revises the targets and weights of every edge,
+    is replaced by a sensor table: for patch g (frame g // ppf) and frame f
+    with |f - g // ppf| <= R, the target (the true projection plus noise) and
+    the weight of edge (g, f)."""
+    poses_gt: np.ndarray     # [T,7] true world->camera poses
+    xy: np.ndarray           # [T, ppf, 2] patch centres of each frame (pixels)
+    depth_gt: np.ndarray     # [T, ppf] true inverse depths
+    table_t: np.ndarray      # [T*ppf, 2R+1, 2] targets of edge (g, g // ppf + o - R)
+    table_w: np.ndarray      # [T*ppf, 2R+1, 2] weights (0 outside the stream and for hidden edges)
+    init_poses: np.ndarray   # [2,7] poses of the first two frames (initialisation)
+    init_depth: float        # inverse depth of the first frame's patches
+    R: int
+    intrinsics: np.ndarray   # [4]
+
+    @property
+    def n_frames(self) -> int:
+        return int(self.poses_gt.shape[0])
+
+    @property
+    def ppf(self) -> int:
+        return int(self.xy.shape[1])
+
+
+def make_stream(n_frames: int, ppf: int, *, seed: Sequence[int], R: int = 40, outlier_frac: float = 0.1,
+                fp32: bool = False) -> Stream:
+    """Forward motion of 0.05 m per frame with a sideways component that
+    alternates every 5 frames between slow (0.03 m) and fast (0.25 m) motion,
+    0.5 degree rotation jitter; patches uniform over the image, inverse depth
+    U[0.2, 1]; targets = true projection + N(0, 1 px), weights U[0.1, 1], 10%
+    outliers (N(0, 20 px), weights U[0, 0.05]); edges whose true depth ratio is
+    below HIDE_RATIO get weight 0 and the source pixel as target."""
+    rng = np.random.default_rng(list(seed))
+    intr = np.array([FX, FY, CX, CY])
+    deg = np.pi / 180.0
+    steps = [np.array([0.25 if (a // 5) % 2 else 0.03, 0.0, 0.05]) for a in range(n_frames)]
+    centres = np.cumsum(np.stack(steps), 0) - steps[0]
+    R_cw = [_rotvec_to_matrix(rng.normal(0.0, 0.5 * deg, 3)) for _ in range(n_frames)]
+    poses_gt = np.stack([_camera(centres[a], R_cw[a]) for a in range(n_frames)])
+    xy = np.stack([np.stack([rng.uniform(0, WIDTH, ppf), rng.uniform(0, HEIGHT, ppf)], -1)
+                   for _ in range(n_frames)])
+    depth_gt = rng.uniform(0.2, 1.0, (n_frames, ppf))
+    G = n_frames * ppf
+    anchor = np.repeat(np.arange(n_frames), ppf)
+    patches = np.concatenate([xy.reshape(G, 2), depth_gt.reshape(G, 1)], 1)
+    Xw = scene_points(poses_gt, patches, anchor, intr)
+    table_t = np.zeros((G, 2 * R + 1, 2))
+    table_w = np.zeros((G, 2 * R + 1, 2))
+    for o in range(2 * R + 1):
+        f = anchor + o - R
+        ok = (f >= 0) & (f < n_frames)
+        idx = np.nonzero(ok)[0]
+        if len(idx) == 0:
+            continue
+        uv, depth = camera_observation(poses_gt, Xw[idx], f[idx], intr)
+        t = uv + rng.normal(0.0, 1.0, uv.shape)
+        w = rng.uniform(0.1, 1.0, uv.shape)
+        out = rng.uniform(size=len(idx)) < outlier_frac
+        t[out] = uv[out] + rng.normal(0.0, 20.0, (int(out.sum()), 2))
+        w[out] = rng.uniform(0.0, 0.05, (int(out.sum()), 2))
+        hidden = depth * depth_gt.reshape(G)[idx] < HIDE_RATIO
+        t[hidden] = patches[idx[hidden], :2]
+        w[hidden] = 0.0
+        table_t[idx, o] = t
+        table_w[idx, o] = w
+    if fp32:
+        table_t = table_t.astype(np.float32).astype(np.float64)
+        table_w = table_w.astype(np.float32).astype(np.float64)
+    return Stream(poses_gt=poses_gt, xy=xy, depth_gt=depth_gt, table_t=table_t, table_w=table_w,
+                  init_poses=poses_gt[:2].copy(), init_depth=0.5, R=R, intrinsics=intr)
