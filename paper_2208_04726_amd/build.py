@@ -1,11 +1,11 @@
 """Builds the gfx950 HIP library libdpba.so (bundle adjustment, the
-correlation features and the soft aggregation) in the package directory."""
+correlation features, the soft aggregation and the sliding-window driver) in the package directory."""
 import os
 import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "csrc", f) for f in ("dpba.hip", "dpcorr.hip", "dpagg.hip")]
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("dpba.hip", "dpcorr.hip", "dpagg.hip", "dpvo.hip")]
 OUT = os.path.join(HERE, "libdpba.so")
 ARCH = os.environ.get("DPBA_OFFLOAD_ARCH", "gfx950")
 

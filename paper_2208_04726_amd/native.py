@@ -21,7 +21,8 @@ EXPORTED = ("ba_create", "ba_solve", "ba_backward", "ba_prepare", "ba_launch", "
             "ba_kernel_times", "ba_status", "ba_last_error", "ba_destroy",
             "ba_debug_reduced_system", "ba_debug_mfma", "ba_solve_noalloc",
             "dpc_correlation", "dpc_avg_pool", "dpc_debug_mfma_bf16",
-            "dpa_softagg", "dpa_workspace_bytes")
+            "dpa_softagg", "dpa_workspace_bytes",
+            "vo_create", "vo_set_sensor", "vo_step", "vo_read", "vo_read_window", "vo_status", "vo_destroy")
 STAGES = ("prep", "assemble", "chol", "backsub", "finalize", "fused")
 
 
@@ -65,6 +66,15 @@ class DPAProblem(ctypes.Structure):
                 ("w_val", ctypes.c_void_p), ("b_val", ctypes.c_void_p), ("w_out", ctypes.c_void_p),
                 ("b_out", ctypes.c_void_p), ("out", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_int64), ("status", ctypes.c_void_p)]
+
+
+class VOConfig(ctypes.Structure):
+    _fields_ = [("n_streams", ctypes.c_int32), ("window", ctypes.c_int32),
+                ("patches_per_frame", ctypes.c_int32), ("radius", ctypes.c_int32),
+                ("n_free", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("iterations", ctypes.c_int32), ("table_radius", ctypes.c_int32),
+                ("flow_thresh", ctypes.c_double), ("lambda_", ctypes.c_double), ("z_min", ctypes.c_double),
+                ("intrinsics", ctypes.c_double * 4)]
 
 
 _LIB = None
@@ -115,6 +125,20 @@ def lib() -> ctypes.CDLL:
         L.dpa_softagg.restype = ctypes.c_int
         L.dpa_workspace_bytes.argtypes = [i32, i32, ctypes.c_int64, ctypes.c_int64, i32]
         L.dpa_workspace_bytes.restype = ctypes.c_int64
+        L.vo_create.argtypes = [ctypes.POINTER(VOConfig), ctypes.POINTER(vp)]
+        L.vo_create.restype = ctypes.c_int
+        L.vo_set_sensor.argtypes = [vp, vp, vp, vp, vp]
+        L.vo_set_sensor.restype = ctypes.c_int
+        L.vo_step.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.vo_step.restype = ctypes.c_int
+        L.vo_read.argtypes = [vp, vp, vp, vp, vp]
+        L.vo_read.restype = ctypes.c_int
+        L.vo_read_window.argtypes = [vp, i32, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64)]
+        L.vo_read_window.restype = ctypes.c_int
+        L.vo_status.argtypes = [vp, vp]
+        L.vo_status.restype = ctypes.c_int
+        L.vo_destroy.argtypes = [vp]
+        L.vo_destroy.restype = None
         _LIB = L
     return _LIB
 

@@ -1,5 +1,5 @@
 """The C-ABI library loads on the CPU and exports every function that
-include/dpba.h, include/dpcorr.h and include/dpagg.h declare (no compute calls without a GPU)."""
+include/dpba.h, dpcorr.h, dpagg.h and dpvo.h declare (no compute calls without a GPU)."""
 import ctypes
 import os
 import re
@@ -9,19 +9,19 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_functions(headers=("dpba.h", "dpcorr.h", "dpagg.h")):
+def declared_functions(headers=("dpba.h", "dpcorr.h", "dpagg.h", "dpvo.h")):
     names = set()
     for h in headers:
         src = open(os.path.join(ROOT, "include", h)).read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-        names |= set(re.findall(r"^\s*(?:int64_t|int|void|const char\s*\*)\s+((?:ba|dpc|dpa)_\w+)\s*\(", src, flags=re.M))
+        names |= set(re.findall(r"^\s*(?:int64_t|int|void|const char\s*\*)\s+((?:ba|dpc|dpa|vo)_\w+)\s*\(", src, flags=re.M))
     return sorted(names)
 
 
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("ba_create", "ba_solve", "ba_backward", "ba_status", "ba_last_error", "ba_destroy",
-              "ba_solve_noalloc", "dpc_correlation", "dpc_avg_pool", "dpa_softagg"):
+              "ba_solve_noalloc", "dpc_correlation", "dpc_avg_pool", "dpa_softagg", "vo_step"):
         assert n in names
 
 
@@ -45,3 +45,5 @@ def test_structs_match_header_layout():
     assert ctypes.sizeof(native.DPCProblem) == 24 + 8 + 16 + 8 * 8
     # dpa_problem: 2 int32, 2 int64, 2 int32, 12 pointers, int64, pointer
     assert ctypes.sizeof(native.DPAProblem) == 8 + 16 + 8 + 12 * 8 + 8 + 8
+    # vo_config: 8 int32, 3 double, 4 double
+    assert ctypes.sizeof(native.VOConfig) == 32 + 24 + 32
