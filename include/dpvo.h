@@ -32,12 +32,15 @@
  *     patch qualifies), in FP64;
  *   - the median of an even count is the mean of the two middle values.
  *
- * Device layout: stream s owns `window` keyframe slots, window *
- * patches_per_frame patch slots and window * patches_per_frame * (2 radius +
- * 1) edge slots; its keyframes fill the first slots in window order, unused
- * slots hold fixed-shape placeholders (identity poses, patches with only
- * self-edges) that contribute nothing, so every step solves all streams'
- * windows in one bundle adjustment on the state buffers themselves.
+ * Device layout: stream s owns `window` keyframe slots and window *
+ * patches_per_frame patch slots; its keyframes fill the first slots in window
+ * order, unused slots hold identity poses and patches without edges, which
+ * the solve leaves unchanged.  All patches of a keyframe enter and leave the
+ * window together and share one set of target frames, so the patch graph is
+ * one 64-bit row of target slots per keyframe slot.  Every step generates the
+ * edge list from these rows, packed across the streams in (patch, target
+ * frame) order, and solves all streams' windows in one bundle adjustment on
+ * the state buffers themselves.
  *
  * Errors: BA_OK (0) or BA_E_INVAL (-1) / BA_E_CAPACITY (-2) / BA_E_HIP (-3)
  * / BA_E_STATE (-4) of dpba.h.
@@ -58,9 +61,8 @@ typedef struct {
   int32_t window;             /* keyframes per window (paper: 22; at most 24 with
                                  BA_PREC_FP64, 64 with BA_PREC_FP32)                */
   int32_t patches_per_frame;  /* 1 .. 256 (paper: 96)                               */
-  int32_t radius;             /* edge radius r, 0 .. 15 (paper: 13): a patch slot
-                                 holds at most 2 r + 1 edges and as many
-                                 placeholders, within the solver's 64 per patch  */
+  int32_t radius;             /* edge radius r, 0 .. 31 (paper: 13): a patch has at
+                                 most 2 r + 1 edges, within the solver's 64       */
   int32_t n_free;             /* keyframes optimised (paper: 10)                    */
   int32_t precision;          /* BA_PREC_FP32 or BA_PREC_FP64                       */
   int32_t iterations;         /* Gauss-Newton iterations per step (paper: 2)        */
@@ -111,7 +113,9 @@ int vo_read_window(vo_handle* h, int32_t s, double* poses, double* depth, int32_
                    int32_t* edge_frame, int64_t* n_edges);
 
 /* BA status bits (dpba.h BA_W_*) of each stream's window in the last step
- * (host [S]); bit 16 marks an edge outside the stream's sensor table. */
+ * (host [S]); bit 16 marks an edge outside the stream's sensor table (its
+ * weight is 0), bit 17 an edge count that disagrees with the graph (an
+ * internal error: the step used the smaller count). */
 int vo_status(vo_handle* h, int32_t* flags);
 
 void vo_destroy(vo_handle* h);

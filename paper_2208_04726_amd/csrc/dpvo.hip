@@ -2,16 +2,26 @@
 // Sec. 3.3 "VO System" applied on the device to many camera streams at once,
 // around the batched bundle adjustment of include/dpba.h.
 //
+// The patch graph of a window is kept as one 64-bit row per keyframe slot:
+// every patch of a keyframe is added, and leaves, together with its frame, so
+// all patches of one keyframe share one set of target frames, and bit q of
+// row p says that the patches of slot p have an edge to the frame in slot q.
+// Removing a keyframe deletes its row and its bit column; the expansion sets
+// one column and one row.  The edge list the bundle adjustment reads is
+// generated from the rows in (patch, target frame) order, which is the order
+// the solver consumes without regrouping, and packed without gaps: after
+// every step the device predicts each stream's edge count after its next
+// expansion, and the host reads it back with the keyframe counts.
+//
 // Per vo_step:
 //   k_vo_expand   (one workgroup per stream): window advance, constant-
 //                 velocity pose, median depth of the new patches, new edges;
 //   k_vo_build    (many workgroups per stream): the bundle-adjustment arrays
-//                 of every edge slot (window-local indices, sensor lookups,
-//                 placeholder self-edges in the unused slots);
+//                 of every edge (window-local indices, sensor lookups);
 //   ba_solve      over all streams' windows, in place on the state buffers;
 //   k_vo_keyframe (one workgroup per stream): the solved depths into the
-//                 state, the flow magnitude between keyframes t-5 and t-3, and
-//                 the removal of keyframe t-4.
+//                 state, the flow magnitude between keyframes t-5 and t-3, the
+//                 removal of keyframe t-4, and the edge counts.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,24 +38,24 @@ namespace dpvo {
 
 constexpr int WG = 1024;
 constexpr int SORT_MAX = 1024;     // median sort: 3 keyframes' patches
+constexpr int MAXN = 64;           // keyframe slots per window
 constexpr int STATUS_TABLE = 1 << 16;
+constexpr int STATUS_COUNT = 1 << 17;
 
 struct State {
-  int S, N, ppf, P, Ecap, r, n_free, R;
+  int S, N, ppf, P, r, n_free, R;
   double thresh, z_min, fx, fy, cx, cy;
   int32_t* n_kf;        // [S]
   int32_t* kf_id;       // [S][N]
   double* poses;        // [S][N][7]
   double* patches;      // [S][P][3]  x, y, inverse depth
-  int32_t* e_g;         // [S][Ecap]  patch id (frame * ppf + i)
-  int32_t* e_f;         // [S][Ecap]  frame id
-  int32_t* e_g2;        // [S][Ecap]  compaction scratch
-  int32_t* e_f2;
-  int32_t* n_e;         // [S]
-  int32_t* kk;          // [S][Ecap]  bundle-adjustment arrays
+  uint64_t* adj;        // [S][N]     bit q of row p: patches of slot p -> frame of slot q
+  int32_t* e_next;      // [S]        edges after the stream's next expansion
+  int32_t* kk;          // bundle-adjustment arrays, packed by e_off
   int32_t* jj;
-  void* tgt;            // [S][Ecap][2] f32 or f64
+  void* tgt;            // [E][2] f32 or f64
   void* wgt;
+  const int64_t* e_off; // [S+1] this step's first edge of every stream
   double* depth_out;    // [S][P]
   double* flow;         // [S]
   int32_t* removed;     // [S]
@@ -56,6 +66,10 @@ struct State {
   const int64_t* tab_off;   // [S] device copy
   const int32_t* tab_frames;
 };
+
+__host__ __device__ __forceinline__ uint64_t bits_below(int q) { return q >= 64 ? ~0ull : ((1ull << q) - 1); }
+// bits lo .. hi inclusive
+__host__ __device__ __forceinline__ uint64_t bit_range(int lo, int hi) { return bits_below(hi + 1) & ~bits_below(lo); }
 
 // ---------------------------------------------------------------------------
 // FP64 pose algebra (7-vectors t, q): composition and inverse.
@@ -86,64 +100,33 @@ __device__ void inverse(const double* a, double* out) {
   out[6] = a[6];
 }
 
-__device__ __forceinline__ void set_placeholder(const State& st, int s, int p) {
-  double* pose = st.poses + ((int64_t)s * st.N + p) * 7;
-  for (int i = 0; i < 7; ++i) pose[i] = i == 6 ? 1.0 : 0.0;
-  st.kf_id[s * st.N + p] = -1;
-}
-
-// Workgroup exclusive scan of one int per thread; returns the total.
-__device__ int wg_scan(int v, int* lds, int* out_excl) {
+// Removes keyframe slot q of stream s (n keyframes): its row and bit column of
+// the graph, then the slots after it move down by one.  All threads call.
+__device__ void remove_slot(const State& st, int s, int q, int n) {
   const int t = threadIdx.x;
-  lds[t] = v;
-  __syncthreads();
-  for (int o = 1; o < WG; o <<= 1) {
-    const int x = t >= o ? lds[t - o] : 0;
-    __syncthreads();
-    lds[t] += x;
-    __syncthreads();
-  }
-  *out_excl = lds[t] - v;
-  const int total = lds[WG - 1];
-  __syncthreads();
-  return total;
-}
-
-// Removes keyframe slot q of stream s (n keyframes): its edges and those of
-// its patches, then the slots after it move down by one.  All threads call.
-__device__ void remove_slot(const State& st, int s, int q, int n, int* lds) {
-  const int t = threadIdx.x;
-  const int fid = st.kf_id[s * st.N + q];
-  // edges: order-preserving compaction through the scratch arrays
-  const int ne = st.n_e[s];
-  const int per = (ne + WG - 1) / WG;
-  const int lo = min(ne, t * per), hi = min(ne, lo + per);
-  int32_t* eg = st.e_g + (int64_t)s * st.Ecap;
-  int32_t* ef = st.e_f + (int64_t)s * st.Ecap;
-  int32_t* eg2 = st.e_g2 + (int64_t)s * st.Ecap;
-  int32_t* ef2 = st.e_f2 + (int64_t)s * st.Ecap;
-  int keep = 0;
-  for (int e = lo; e < hi; ++e) keep += (ef[e] != fid && eg[e] / st.ppf != fid) ? 1 : 0;
-  int off;
-  const int total = wg_scan(keep, lds, &off);
-  for (int e = lo; e < hi; ++e) {
-    if (ef[e] != fid && eg[e] / st.ppf != fid) {
-      eg2[off] = eg[e];
-      ef2[off] = ef[e];
-      ++off;
-    }
-  }
-  __syncthreads();
-  for (int e = t; e < total; e += WG) {
-    eg[e] = eg2[e];
-    ef[e] = ef2[e];
-  }
-  // slots q+1 .. n-1 move down: read everything first, then write
-  const int np = (n - 1 - q) * st.ppf * 3;       // patch doubles to move
-  const int nq = (n - 1 - q) * 7;                // pose doubles
+  uint64_t* adj = st.adj + (int64_t)s * st.N;
   double* pt = st.patches + (int64_t)s * st.P * 3;
   double* ps = st.poses + (int64_t)s * st.N * 7;
-  constexpr int MAXV = 24;                        // (64 slots * 256 patches * 3) / 1024 < 49; chunked below
+  int32_t* kid = st.kf_id + s * st.N;
+  // rows, poses and ids: read everything first, then write
+  uint64_t row = 0;
+  double pv = 0.0;
+  int id = -1;
+  const uint64_t lo = bits_below(q);
+  if (t < n && t != q) {
+    const uint64_t x = adj[t];
+    row = (x & lo) | ((x >> 1) & ~lo);
+  }
+  if (t < 7 * (n - 1 - q)) pv = ps[(q + 1) * 7 + t];
+  if (t < n - 1 - q) id = kid[q + 1 + t];
+  // patches of slots q+1 .. n-1, in chunks (the move goes down, so a chunk's
+  // writes never reach a later chunk's reads)
+  const int np = (n - 1 - q) * st.ppf * 3;
+  constexpr int MAXV = 24;
+  __syncthreads();
+  if (t < n && t != q) adj[t < q ? t : t - 1] = row;
+  if (t < 7 * (n - 1 - q)) ps[q * 7 + t] = pv;
+  if (t < n - 1 - q) kid[q + t] = id;
   for (int base = 0; base < np; base += WG * MAXV) {
     double v[MAXV];
 #pragma unroll
@@ -159,17 +142,12 @@ __device__ void remove_slot(const State& st, int s, int q, int n, int* lds) {
     }
     __syncthreads();
   }
-  {
-    double v = t < nq ? ps[(q + 1) * 7 + t] : 0.0;
-    const int id = t < n - 1 - q ? st.kf_id[s * st.N + q + 1 + t] : -1;
-    __syncthreads();
-    if (t < nq) ps[q * 7 + t] = v;
-    if (t < n - 1 - q) st.kf_id[s * st.N + q + t] = id;
-  }
   __syncthreads();
-  if (t == 0) {
-    st.n_e[s] = total;
-    set_placeholder(st, s, n - 1);
+  if (t == 0) {   // the freed slot: identity pose, no edges
+    double* pose = ps + (n - 1) * 7;
+    for (int i = 0; i < 7; ++i) pose[i] = i == 6 ? 1.0 : 0.0;
+    kid[n - 1] = -1;
+    adj[n - 1] = 0;
   }
   __syncthreads();
 }
@@ -181,18 +159,19 @@ __global__ void __launch_bounds__(256) k_vo_clear(int32_t* a, int n) {
 // Window advance and expansion of every active stream.
 __global__ void __launch_bounds__(WG) k_vo_expand(State st, const double* new_xy, const double* init_poses,
                                                   const double* init_depth) {
-  __shared__ int lds[WG];
   __shared__ double sortv[SORT_MAX];
   const int s = blockIdx.x, t = threadIdx.x;
   const int fid = st.active[s];
   if (fid < 0) return;
   int n = st.n_kf[s];
   if (n == st.N) {
-    remove_slot(st, s, 0, n, lds);
+    remove_slot(st, s, 0, n);
     --n;
   }
   // new keyframe at slot n
   double* ps = st.poses + (int64_t)s * st.N * 7;
+  uint64_t* adj = st.adj + (int64_t)s * st.N;
+  const int q0 = max(0, n - st.r);
   if (t == 0) {
     double* pn = ps + n * 7;
     if (n < 2) {
@@ -205,6 +184,10 @@ __global__ void __launch_bounds__(WG) k_vo_expand(State st, const double* new_xy
     }
     st.kf_id[s * st.N + n] = fid;
   }
+  // new edges: the patches of the last r keyframes to the new frame, the new
+  // patches to keyframes n-r .. n
+  if (t >= q0 && t < n) adj[t] |= 1ull << n;
+  if (t == n) adj[n] = bit_range(q0, n);
   // median inverse depth of the previous three keyframes' patches
   double d0;
   if (n == 0) {
@@ -242,85 +225,95 @@ __global__ void __launch_bounds__(WG) k_vo_expand(State st, const double* new_xy
     p[1] = new_xy[((int64_t)s * st.ppf + i) * 2 + 1];
     p[2] = d0;
   }
-  // new edges: patches of the last r keyframes -> the new frame, then the
-  // new patches -> keyframes n-r .. n
-  const int ne = st.n_e[s];
-  const int q0 = max(0, n - st.r);
-  const int nold = (n - q0) * st.ppf;
-  const int nnew = (n - q0 + 1) * st.ppf;
-  int32_t* eg = st.e_g + (int64_t)s * st.Ecap;
-  int32_t* ef = st.e_f + (int64_t)s * st.Ecap;
+  if (t == 0) st.n_kf[s] = n + 1;
+}
+
+// Bundle-adjustment arrays of every edge of the active streams: edge e of
+// stream s is patch i of slot p with the c-th set bit of row p, for
+// e = ppf * (edges of the rows before p) + i * popcount(row p) + c.
+template <typename T>
+__global__ void __launch_bounds__(256) k_vo_build(State st, int chunks) {
+  __shared__ int rowoff[MAXN + 1];
+  __shared__ int rowpop[MAXN];
+  __shared__ int8_t bitpos[MAXN * MAXN];
+  const int s = blockIdx.x / chunks;
+  const int c = blockIdx.x % chunks;
+  const int t = threadIdx.x;
+  if (st.active[s] < 0) return;
+  const int n = st.n_kf[s];
+  const uint64_t* adj = st.adj + (int64_t)s * st.N;
   const int32_t* kid = st.kf_id + s * st.N;
-  for (int i = t; i < nold + nnew; i += WG) {
-    int g, f;
-    if (i < nold) {
-      const int p = q0 + i / st.ppf;
-      g = kid[p] * st.ppf + i % st.ppf;
-      f = fid;
-    } else {
-      const int k = i - nold;
-      const int q = q0 + k / st.ppf;
-      g = fid * st.ppf + k % st.ppf;
-      f = q == n ? fid : kid[q];
-    }
-    eg[ne + i] = g;
-    ef[ne + i] = f;
+  if (t < n) {
+    uint64_t x = adj[t];
+    rowpop[t] = __popcll(x);
+    for (int k = 0; x; ++k, x &= x - 1) bitpos[t * MAXN + k] = (int8_t)__ffsll((long long)x) - 1;
   }
   __syncthreads();
   if (t == 0) {
-    st.n_e[s] = ne + nold + nnew;
-    st.n_kf[s] = n + 1;
-  }
-}
-
-// Bundle-adjustment arrays of every edge slot.
-template <typename T>
-__global__ void __launch_bounds__(256) k_vo_build(State st, int chunks) {
-  const int s = blockIdx.x / chunks;
-  const int c = blockIdx.x % chunks;
-  const int ne = st.active[s] >= 0 ? st.n_e[s] : 0;   // idle streams: placeholders only
-  const int n = st.n_kf[s];
-  const int32_t* kid = st.kf_id + s * st.N;
-  T* tg = (T*)st.tgt + (int64_t)s * st.Ecap * 2;
-  T* wg = (T*)st.wgt + (int64_t)s * st.Ecap * 2;
-  int32_t* kk = st.kk + (int64_t)s * st.Ecap;
-  int32_t* jj = st.jj + (int64_t)s * st.Ecap;
-  const int R = st.R;
-  int bad = 0;
-  for (int e = c * 256 + threadIdx.x; e < st.Ecap; e += chunks * 256) {
-    if (e < ne) {
-      const int g = st.e_g[(int64_t)s * st.Ecap + e], f = st.e_f[(int64_t)s * st.Ecap + e];
-      const int a = g / st.ppf;
-      int pa = 0, pf = 0;
-      for (int p = 0; p < n; ++p) {
-        if (kid[p] == a) pa = p;
-        if (kid[p] == f) pf = p;
-      }
-      kk[e] = pa * st.ppf + g % st.ppf;
-      jj[e] = pf;
-      const int o = f - a + R;
-      const bool ok = o >= 0 && o <= 2 * R && g < st.tab_frames[s] * st.ppf && f < st.tab_frames[s];
-      const int64_t row = (st.tab_off[s] + g) * (2 * R + 1) + o;
-      tg[2 * e] = ok ? (T)st.tab_t[2 * row] : T(0);
-      tg[2 * e + 1] = ok ? (T)st.tab_t[2 * row + 1] : T(0);
-      wg[2 * e] = ok ? (T)st.tab_w[2 * row] : T(0);
-      wg[2 * e + 1] = ok ? (T)st.tab_w[2 * row + 1] : T(0);
-      bad |= ok ? 0 : STATUS_TABLE;
-    } else {
-      // a self-edge of patch e % P: contributes exactly nothing
-      const int k = e % st.P;
-      kk[e] = k;
-      jj[e] = k / st.ppf;
-      tg[2 * e] = tg[2 * e + 1] = T(0);
-      wg[2 * e] = wg[2 * e + 1] = T(0);
+    int o = 0;
+    for (int p = 0; p < n; ++p) {
+      rowoff[p] = o;
+      o += st.ppf * rowpop[p];
     }
+    rowoff[n] = o;
+  }
+  __syncthreads();
+  const int64_t e0 = st.e_off[s];
+  const int ne = (int)(st.e_off[s + 1] - e0);
+  if (ne != rowoff[n]) {   // the host's edge count disagrees with the graph
+    if (c == 0 && t == 0) atomicOr(&st.vstatus[s], STATUS_COUNT);
+  }
+  const int nw = min(ne, rowoff[n]);
+  T* tg = (T*)st.tgt + 2 * e0;
+  T* wg = (T*)st.wgt + 2 * e0;
+  int32_t* kk = st.kk + e0;
+  int32_t* jj = st.jj + e0;
+  const int R = st.R;
+  const int64_t tab0 = st.tab_off[s];
+  const int tabf = st.tab_frames[s];
+  int bad = 0;
+  for (int e = c * 256 + t; e < nw; e += chunks * 256) {
+    int p = 0;
+    while (p + 1 < n && rowoff[p + 1] <= e) ++p;
+    const int local = e - rowoff[p], pc = rowpop[p];
+    const int i = local / pc, q = bitpos[p * MAXN + local % pc];
+    const int a = kid[p], f = kid[q];
+    const int g = a * st.ppf + i;
+    kk[e] = p * st.ppf + i;
+    jj[e] = q;
+    const int o = f - a + R;
+    const bool ok = o >= 0 && o <= 2 * R && a < tabf && f < tabf;
+    const int64_t row = (tab0 + g) * (2 * R + 1) + o;
+    tg[2 * e] = ok ? (T)st.tab_t[2 * row] : T(0);
+    tg[2 * e + 1] = ok ? (T)st.tab_t[2 * row + 1] : T(0);
+    wg[2 * e] = ok ? (T)st.tab_w[2 * row] : T(0);
+    wg[2 * e + 1] = ok ? (T)st.tab_w[2 * row + 1] : T(0);
+    bad |= ok ? 0 : STATUS_TABLE;
   }
   if (bad) atomicOr(&st.vstatus[s], bad);
 }
 
+// Edges of the stream after its next expansion: the window advance drops slot
+// 0's row and column, the expansion adds (n - q0) old rows' bits and a row of
+// n - q0 + 1 bits.  Called by thread 0 with the stream's final state.
+__device__ int next_edges(const State& st, int s) {
+  const uint64_t* adj = st.adj + (int64_t)s * st.N;
+  int n = st.n_kf[s];
+  int bits = 0;
+  for (int p = 0; p < n; ++p) bits += __popcll(adj[p]);
+  if (n == st.N) {
+    int col = 0;
+    for (int p = 1; p < n; ++p) col += (int)(adj[p] & 1ull);
+    bits -= __popcll(adj[0]) + col;
+    --n;
+  }
+  const int q0 = max(0, n - st.r);
+  bits += (n - q0) + (n - q0 + 1);
+  return bits * st.ppf;
+}
+
 // Solved depths into the state, flow magnitude, keyframe removal.
 __global__ void __launch_bounds__(WG) k_vo_keyframe(State st) {
-  __shared__ int lds[WG];
   __shared__ double fsum[WG];
   __shared__ int fcnt[WG];
   const int s = blockIdx.x, t = threadIdx.x;
@@ -360,7 +353,6 @@ __global__ void __launch_bounds__(WG) k_vo_keyframe(State st) {
         tot += fsum[i];
         c += fcnt[i];
       }
-      lds[0] = c;
       fsum[0] = c > 0 ? tot / c : INFINITY;
     }
     __syncthreads();
@@ -368,13 +360,15 @@ __global__ void __launch_bounds__(WG) k_vo_keyframe(State st) {
     __syncthreads();
     if (flow < st.thresh) {
       removed = st.kf_id[s * st.N + n - 5];
-      remove_slot(st, s, n - 5, n, lds);
+      remove_slot(st, s, n - 5, n);
       if (t == 0) st.n_kf[s] = n - 1;
     }
   }
+  __syncthreads();
   if (t == 0) {
     st.flow[s] = flow;
     st.removed[s] = removed;
+    st.e_next[s] = next_edges(st, s);
   }
 }
 
@@ -386,13 +380,15 @@ struct vo_handle {
   vo_config cfg;
   State st;
   ba_handle* ba = nullptr;
-  std::vector<int32_t> n_kf_host;
+  int64_t Ecap = 0;                 // edges of one window at most
+  std::vector<int32_t> n_kf_host, e_next_host;
   std::vector<int64_t> frame_off, patch_off, edge_off;
   std::vector<int32_t> n_fixed;
   std::vector<double> intr;
   int32_t* d_active = nullptr;
   int32_t* d_anchor = nullptr;     // [S][P] keyframe slot of every patch slot
   double* d_init_depth = nullptr;  // [S]
+  int64_t* d_e_off = nullptr;      // [S+1]
   int64_t* d_tab_off = nullptr;
   int32_t* d_tab_frames = nullptr;
   bool sensor = false;
@@ -415,23 +411,25 @@ int vo_create(const vo_config* cfg, vo_handle** out) {
   if (!out) return BA_E_INVAL;
   *out = nullptr;
   if (!cfg) return BA_E_INVAL;
-  const int maxw = cfg->precision == BA_PREC_FP64 ? 24 : 64;
+  const int maxw = cfg->precision == BA_PREC_FP64 ? 24 : MAXN;
   if (cfg->n_streams < 1 || cfg->window < 6 || cfg->window > maxw || cfg->patches_per_frame < 1 ||
       cfg->patches_per_frame > 256 || 3 * cfg->patches_per_frame > SORT_MAX || cfg->radius < 0 ||
-      cfg->radius > 15 || cfg->radius >= cfg->window || cfg->n_free < 1 || cfg->iterations < 1 || cfg->table_radius < cfg->radius ||
-      (cfg->precision != BA_PREC_FP32 && cfg->precision != BA_PREC_FP64) || !(cfg->lambda >= 0.0))
+      cfg->radius > 31 || cfg->radius >= cfg->window || cfg->n_free < 1 || cfg->iterations < 1 ||
+      cfg->table_radius < cfg->radius || (cfg->precision != BA_PREC_FP32 && cfg->precision != BA_PREC_FP64) ||
+      !(cfg->lambda >= 0.0))
     return BA_E_INVAL;
   vo_handle* h = new vo_handle();
   h->cfg = *cfg;
   const int S = cfg->n_streams, N = cfg->window, ppf = cfg->patches_per_frame;
   const int P = N * ppf;
-  const int Ecap = P * (2 * cfg->radius + 1);
+  // a patch has at most 2 r + 1 edges: r + 1 when its frame arrives, and one
+  // to each later frame added while its slot is within r of the newest
+  h->Ecap = (int64_t)P * (2 * cfg->radius + 1);
   State& st = h->st;
   st.S = S;
   st.N = N;
   st.ppf = ppf;
   st.P = P;
-  st.Ecap = Ecap;
   st.r = cfg->radius;
   st.n_free = cfg->n_free;
   st.R = cfg->table_radius;
@@ -442,26 +440,25 @@ int vo_create(const vo_config* cfg, vo_handle** out) {
   st.cx = cfg->intrinsics[2];
   st.cy = cfg->intrinsics[3];
   const size_t esz = cfg->precision == BA_PREC_FP32 ? 4 : 8;
+  const size_t E = (size_t)S * h->Ecap;
   int r = BA_OK;
   auto A = [&](void** p, size_t b) { if (r == BA_OK) r = dmalloc(h, p, b); };
   A((void**)&st.n_kf, 4 * S);
   A((void**)&st.kf_id, 4 * (size_t)S * N);
   A((void**)&st.poses, 8 * 7 * (size_t)S * N);
   A((void**)&st.patches, 8 * 3 * (size_t)S * P);
-  A((void**)&st.e_g, 4 * (size_t)S * Ecap);
-  A((void**)&st.e_f, 4 * (size_t)S * Ecap);
-  A((void**)&st.e_g2, 4 * (size_t)S * Ecap);
-  A((void**)&st.e_f2, 4 * (size_t)S * Ecap);
-  A((void**)&st.n_e, 4 * S);
-  A((void**)&st.kk, 4 * (size_t)S * Ecap);
-  A((void**)&st.jj, 4 * (size_t)S * Ecap);
-  A(&st.tgt, 2 * esz * (size_t)S * Ecap);
-  A(&st.wgt, 2 * esz * (size_t)S * Ecap);
+  A((void**)&st.adj, 8 * (size_t)S * N);
+  A((void**)&st.e_next, 4 * S);
+  A((void**)&st.kk, 4 * E);
+  A((void**)&st.jj, 4 * E);
+  A(&st.tgt, 2 * esz * E);
+  A(&st.wgt, 2 * esz * E);
   A((void**)&st.depth_out, 8 * (size_t)S * P);
   A((void**)&st.flow, 8 * S);
   A((void**)&st.removed, 4 * S);
   A((void**)&st.vstatus, 4 * S);
   A((void**)&h->d_active, 4 * S);
+  A((void**)&h->d_e_off, 8 * (S + 1));
   A((void**)&h->d_tab_off, 8 * S);
   A((void**)&h->d_tab_frames, 4 * S);
   A((void**)&h->d_anchor, 4 * (size_t)S * P);
@@ -471,20 +468,28 @@ int vo_create(const vo_config* cfg, vo_handle** out) {
     return r;
   }
   st.active = h->d_active;
+  st.e_off = h->d_e_off;
   st.tab_off = h->d_tab_off;
   st.tab_frames = h->d_tab_frames;
-  // empty windows: placeholder poses and patches, no edges
+  // empty windows: identity poses, unit inverse depths, no edges; the first
+  // expansion adds the self-edges of the first frame's patches
   std::vector<double> poses((size_t)S * N * 7, 0.0), patches((size_t)S * P * 3, 0.0);
   for (size_t i = 0; i < (size_t)S * N; ++i) poses[i * 7 + 6] = 1.0;
   for (size_t i = 0; i < (size_t)S * P; ++i) patches[i * 3 + 2] = 1.0;
-  std::vector<int32_t> ids((size_t)S * N, -1), zeros(S, 0), anchor((size_t)S * P);
+  std::vector<int32_t> ids((size_t)S * N, -1), zeros(S, 0), first(S, ppf), anchor((size_t)S * P);
+  std::vector<uint64_t> rows((size_t)S * N, 0);
   for (size_t i = 0; i < anchor.size(); ++i) anchor[i] = (int32_t)((i % P) / ppf);
   bool ok = hipMemcpy(h->d_anchor, anchor.data(), 4 * anchor.size(), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(st.poses, poses.data(), 8 * poses.size(), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(st.patches, patches.data(), 8 * patches.size(), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(st.kf_id, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(st.adj, rows.data(), 8 * rows.size(), hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(st.n_kf, zeros.data(), 4 * S, hipMemcpyHostToDevice) == hipSuccess &&
-            hipMemcpy(st.n_e, zeros.data(), 4 * S, hipMemcpyHostToDevice) == hipSuccess;
+            hipMemcpy(st.e_next, first.data(), 4 * S, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(st.removed, std::vector<int32_t>(S, -1).data(), 4 * S, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(st.vstatus, zeros.data(), 4 * S, hipMemcpyHostToDevice) == hipSuccess;
+  std::vector<double> nan(S, NAN);
+  ok = ok && hipMemcpy(st.flow, nan.data(), 8 * S, hipMemcpyHostToDevice) == hipSuccess;
   if (!ok) {
     vo_destroy(h);
     return BA_E_HIP;
@@ -501,20 +506,20 @@ int vo_create(const vo_config* cfg, vo_handle** out) {
   bc.chunk_frames = 0;
   bc.max_frames = (int64_t)S * N;
   bc.max_patches = (int64_t)S * P;
-  bc.max_edges = (int64_t)S * Ecap;
+  bc.max_edges = (int64_t)E;
   r = ba_create(&bc, &h->ba);
   if (r != BA_OK) {
     vo_destroy(h);
     return r;
   }
   h->n_kf_host.assign(S, 0);
+  h->e_next_host.assign(S, ppf);
   h->frame_off.resize(S + 1);
   h->patch_off.resize(S + 1);
-  h->edge_off.resize(S + 1);
+  h->edge_off.assign(S + 1, 0);
   for (int s = 0; s <= S; ++s) {
     h->frame_off[s] = (int64_t)s * N;
     h->patch_off[s] = (int64_t)s * P;
-    h->edge_off[s] = (int64_t)s * Ecap;
   }
   h->n_fixed.assign(S, 0);
   h->intr.resize(4 * S);
@@ -545,23 +550,29 @@ int vo_step(vo_handle* h, const int32_t* frame_id, const double* new_xy, const d
   const int S = h->cfg.n_streams, N = h->cfg.window;
   hipStream_t s = (hipStream_t)stream;
   State& st = h->st;
+  // keyframes and edges after the expansion, known on the host from the last
+  // step's read-back; idle streams enter the solve without edges, every pose
+  // fixed, and keep their state
+  for (int i = 0; i < S; ++i) {
+    const bool on = frame_id[i] >= 0;
+    const int n = on ? std::min(h->n_kf_host[i] + 1, N) : h->n_kf_host[i];
+    h->n_fixed[i] = on ? std::max(std::min(2, n), n - h->cfg.n_free) : N;
+    h->edge_off[i + 1] = h->edge_off[i] + (on ? h->e_next_host[i] : 0);
+    if (on && (h->e_next_host[i] < 0 || h->e_next_host[i] > h->Ecap)) return BA_E_STATE;
+  }
   // the host arrays are read before this call returns (it waits for the step)
   if (hipMemcpyAsync(h->d_active, frame_id, 4 * S, hipMemcpyHostToDevice, s) != hipSuccess) return BA_E_HIP;
   if (hipMemcpyAsync(h->d_init_depth, init_depth, 8 * S, hipMemcpyHostToDevice, s) != hipSuccess) return BA_E_HIP;
+  if (hipMemcpyAsync(h->d_e_off, h->edge_off.data(), 8 * (S + 1), hipMemcpyHostToDevice, s) != hipSuccess)
+    return BA_E_HIP;
   hipLaunchKernelGGL(k_vo_clear, dim3(1), dim3(256), 0, s, st.vstatus, S);
   hipLaunchKernelGGL(k_vo_expand, dim3(S), dim3(WG), 0, s, st, new_xy, init_poses, (const double*)h->d_init_depth);
-  const int chunks = std::max(1, std::min(64, (st.Ecap + 4095) / 4096));
+  const int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(64, (h->Ecap + 4095) / 4096));
   if (h->cfg.precision == BA_PREC_FP32)
     hipLaunchKernelGGL(k_vo_build<float>, dim3(S * chunks), dim3(256), 0, s, st, chunks);
   else
     hipLaunchKernelGGL(k_vo_build<double>, dim3(S * chunks), dim3(256), 0, s, st, chunks);
   if (hipGetLastError() != hipSuccess) return BA_E_HIP;
-  // keyframes after the expansion (known on the host: the window grows by
-  // one up to its capacity); idle streams keep every pose fixed
-  for (int i = 0; i < S; ++i) {
-    const int n = frame_id[i] >= 0 ? std::min(h->n_kf_host[i] + 1, N) : h->n_kf_host[i];
-    h->n_fixed[i] = frame_id[i] >= 0 ? std::max(std::min(2, n), n - h->cfg.n_free) : N;
-  }
   ba_problem p;
   memset(&p, 0, sizeof(p));
   p.n_windows = S;
@@ -584,6 +595,8 @@ int vo_step(vo_handle* h, const int32_t* frame_id, const double* new_xy, const d
   hipLaunchKernelGGL(k_vo_keyframe, dim3(S), dim3(WG), 0, s, st);
   if (hipGetLastError() != hipSuccess) return BA_E_HIP;
   if (hipMemcpyAsync(h->n_kf_host.data(), st.n_kf, 4 * S, hipMemcpyDeviceToHost, s) != hipSuccess) return BA_E_HIP;
+  if (hipMemcpyAsync(h->e_next_host.data(), st.e_next, 4 * S, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return BA_E_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return BA_E_HIP;
   return BA_OK;
 }
@@ -603,7 +616,7 @@ int vo_read_window(vo_handle* h, int32_t s, double* poses, double* depth, int32_
                    int64_t* n_edges) {
   if (!h || s < 0 || s >= h->cfg.n_streams) return BA_E_INVAL;
   State& st = h->st;
-  const int N = st.N, P = st.P;
+  const int N = st.N, P = st.P, ppf = st.ppf;
   if (poses && hipMemcpy(poses, st.poses + (int64_t)s * N * 7, 8 * 7 * N, hipMemcpyDeviceToHost) != hipSuccess)
     return BA_E_HIP;
   if (depth) {
@@ -612,13 +625,26 @@ int vo_read_window(vo_handle* h, int32_t s, double* poses, double* depth, int32_
       return BA_E_HIP;
     for (int i = 0; i < P; ++i) depth[i] = pt[3 * i + 2];
   }
-  int32_t ne = 0;
-  if (hipMemcpy(&ne, st.n_e + s, 4, hipMemcpyDeviceToHost) != hipSuccess) return BA_E_HIP;
+  int32_t n = 0;
+  std::vector<uint64_t> rows(N);
+  std::vector<int32_t> ids(N);
+  if (hipMemcpy(&n, st.n_kf + s, 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(rows.data(), st.adj + (int64_t)s * N, 8 * N, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(ids.data(), st.kf_id + (int64_t)s * N, 4 * N, hipMemcpyDeviceToHost) != hipSuccess)
+    return BA_E_HIP;
+  // (patch id, frame id) of every edge, in (slot, patch, target slot) order
+  int64_t ne = 0;
+  for (int p = 0; p < n; ++p) {
+    for (int i = 0; i < ppf; ++i) {
+      for (int q = 0; q < n; ++q) {
+        if (!((rows[p] >> q) & 1ull)) continue;
+        if (edge_patch) edge_patch[ne] = ids[p] * ppf + i;
+        if (edge_frame) edge_frame[ne] = ids[q];
+        ++ne;
+      }
+    }
+  }
   if (n_edges) *n_edges = ne;
-  if (edge_patch && hipMemcpy(edge_patch, st.e_g + (int64_t)s * st.Ecap, 4 * (size_t)ne, hipMemcpyDeviceToHost) != hipSuccess)
-    return BA_E_HIP;
-  if (edge_frame && hipMemcpy(edge_frame, st.e_f + (int64_t)s * st.Ecap, 4 * (size_t)ne, hipMemcpyDeviceToHost) != hipSuccess)
-    return BA_E_HIP;
   return BA_OK;
 }
 
