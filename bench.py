@@ -657,6 +657,51 @@ def run_aggregation(args, torch):
     return out
 
 
+def run_driver(args, torch):
+    """The sliding-window driver (Sec. 3.3) stepping `vo_streams` camera
+    streams together: 22-keyframe windows of 96 patches, radius 13, two
+    Gauss-Newton iterations per frame, flow-based keyframe removal.  Every
+    vo_step call waits for its step, so host wall clock per step is the
+    latency of one frame for every stream.  Parity: stream 0's final window
+    (FP64) against the driver oracle."""
+    from oracle import vo_oracle as V
+    from paper_2208_04726_amd import synth
+    from paper_2208_04726_amd.vo import Driver
+    S, warm, timed = args.vo_streams, 25, 30
+    T = warm + timed + 1
+    out = {"workload": f"{S} camera streams stepped together, 22-keyframe windows x 96 patches, radius 13, "
+                       f"2 GN iterations per frame; {T - 1} frames per stream, the first {warm} untimed "
+                       "(windows fill), 16 distinct synthetic streams replicated"}
+    for prec in ("fp32", "fp64"):
+        base = [synth.make_stream(T, 96, seed=[2208, 30, i], fp32=prec == "fp32") for i in range(16)]
+        drv = Driver([base[i % 16] for i in range(S)], precision=prec, track_trajectory=False)
+        ts = []
+        for t in range(warm + timed):
+            a = time.perf_counter()
+            drv.step(np.full(S, t, np.int32))
+            ts.append(time.perf_counter() - a)
+        ms = 1e3 * float(np.mean(ts[warm:]))
+        n, kf, flow, rem = drv.read()
+        rec = {"ms_per_step": round(ms, 4), "frames_per_s": round(S / (ms / 1e3), 1),
+               "mean_keyframes": round(float(n.mean()), 2), "status_nonzero": int((drv.status() != 0).sum())}
+        if prec == "fp64":
+            o = V.StreamOracle(base[0], window=22, radius=13)
+            for t in range(warm + timed):
+                r = o.step(t)
+            k = len(r["kf"])
+            poses, depth, eg, ef = drv.window(0)
+            dc, dr = synth.pose_errors(poses[:k], r["poses"])
+            rec["parity_stream0"] = {
+                "keyframes_match": kf[0, :k].tolist() == r["kf"] and int(n[0]) == k,
+                "edges_match": sorted(zip(eg.tolist(), ef.tolist())) == r["edges"],
+                "max_center_err_m": float(dc), "max_rot_err_deg": float(dr),
+                "max_depth_rel_err": float(np.max(np.abs(depth[:k * 96] - r["depth"]) / np.abs(r["depth"])))}
+        drv.close()
+        out[prec] = rec
+        del base
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -677,9 +722,11 @@ def main():
     ap.add_argument("--serve-fast-rate", type=float, default=20000.0)
     ap.add_argument("--serve-fast-requests", type=int, default=20000)
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the plain FP64, backward and correlation records")
+                    help="skip the plain FP64, backward, correlation, aggregation and driver records")
     ap.add_argument("--corr-only", action="store_true", help="run only the correlation record")
     ap.add_argument("--agg-only", action="store_true", help="run only the soft-aggregation record")
+    ap.add_argument("--vo-only", action="store_true", help="run only the sliding-window driver record")
+    ap.add_argument("--vo-streams", type=int, default=256)
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--large-only", action="store_true",
                     help="run only the 64x256 large-window batch (for its profile) and print its record")
@@ -720,6 +767,9 @@ def main():
         return
     if args.agg_only:
         print(json.dumps(run_aggregation(args, torch)), flush=True)
+        return
+    if args.vo_only:
+        print(json.dumps(run_driver(args, torch)), flush=True)
         return
     # the CPU baseline runs first, in processes started before the GPU is used
     cpu = None if args.no_cpu_baseline else cpu_oracle_baseline(args.cpu_budget)
@@ -848,6 +898,9 @@ def main():
         log(f"correlation: {out['correlation']}")
         out["aggregation"] = run_aggregation(args, torch)
         log(f"aggregation: {out['aggregation']}")
+        out["driver"] = run_driver(args, torch)
+        out["parity"]["driver"] = out["driver"]["fp64"]["parity_stream0"]
+        log(f"driver: {out['driver']}")
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

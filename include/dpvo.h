@@ -100,10 +100,20 @@ int vo_step(vo_handle* h, const int32_t* frame_id, const double* new_xy, const d
 
 /* Host copies of the state after the last step: n_kf (host [S], keyframes in
  * the window), kf_id (host [S, window], frame ids in window order, -1 beyond
- * n_kf), flow (host [S], the last flow magnitude, NaN when not computed) and
- * removed (host [S], the frame id removed by the last keyframe decision or
- * -1); any pointer may be NULL. */
+ * n_kf), flow (host [S], the step's flow magnitude, NaN when not computed or
+ * the stream was idle) and removed (host [S], the frame id removed by the
+ * step's keyframe decision or -1); any pointer may be NULL. */
 int vo_read(vo_handle* h, int32_t* n_kf, int32_t* kf_id, double* flow, int32_t* removed);
+
+/* What the last step took out of each window, for recovering the whole
+ * trajectory ("Keyframing", Sec. 3.3): retired (host [S]) the frame id that
+ * left the full window at the advance, or -1, with retired_pose (host [S, 7])
+ * its final pose; removed (host [S]) the keyframe removed by the flow test,
+ * or -1, with removed_prev (host [S]) the keyframe before it and removed_rel
+ * (host [S, 7]) its pose relative to that keyframe, T_removed T_prev^-1,
+ * taken after the step's optimisation.  Any pointer may be NULL. */
+int vo_read_events(vo_handle* h, int32_t* retired, double* retired_pose, int32_t* removed, int32_t* removed_prev,
+                   double* removed_rel);
 
 /* Host copies of stream s's window: poses (host [window, 7]), inverse depths
  * (host [window * patches_per_frame], by keyframe slot), its edges as (patch

@@ -58,7 +58,11 @@ struct State {
   const int64_t* e_off; // [S+1] this step's first edge of every stream
   double* depth_out;    // [S][P]
   double* flow;         // [S]
-  int32_t* removed;     // [S]
+  int32_t* removed;     // [S]     keyframe removed by this step's keyframing, or -1
+  int32_t* removed_prev;// [S]     its previous keyframe
+  double* removed_rel;  // [S][7]  its pose relative to that keyframe, T_q T_{q-1}^-1
+  int32_t* retired;     // [S]     keyframe that left the full window this step, or -1
+  double* retired_pose; // [S][7]  its pose when it left
   int32_t* vstatus;     // [S]
   int32_t* active;      // [S] this step's frame id (-1 idle)
   const double* tab_t;  // sensor
@@ -152,8 +156,15 @@ __device__ void remove_slot(const State& st, int s, int q, int n) {
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(256) k_vo_clear(int32_t* a, int n) {
-  for (int i = threadIdx.x; i < n; i += 256) a[i] = 0;
+// Per-step outputs of every stream reset before the step.
+__global__ void __launch_bounds__(256) k_vo_clear(State st) {
+  for (int s = blockIdx.x * 256 + threadIdx.x; s < st.S; s += gridDim.x * 256) {
+    st.vstatus[s] = 0;
+    st.removed[s] = -1;
+    st.removed_prev[s] = -1;
+    st.retired[s] = -1;
+    st.flow[s] = NAN;
+  }
 }
 
 // Window advance and expansion of every active stream.
@@ -165,6 +176,8 @@ __global__ void __launch_bounds__(WG) k_vo_expand(State st, const double* new_xy
   if (fid < 0) return;
   int n = st.n_kf[s];
   if (n == st.N) {
+    if (t < 7) st.retired_pose[s * 7 + t] = st.poses[(int64_t)s * st.N * 7 + t];
+    if (t == 0) st.retired[s] = st.kf_id[s * st.N];
     remove_slot(st, s, 0, n);
     --n;
   }
@@ -359,8 +372,15 @@ __global__ void __launch_bounds__(WG) k_vo_keyframe(State st) {
     flow = fsum[0];
     __syncthreads();
     if (flow < st.thresh) {
-      removed = st.kf_id[s * st.N + n - 5];
-      remove_slot(st, s, n - 5, n);
+      const int q = n - 5;
+      removed = st.kf_id[s * st.N + q];
+      if (t == 0) {
+        double inv[7];
+        inverse(ps + (q - 1) * 7, inv);
+        compose(ps + q * 7, inv, st.removed_rel + s * 7);
+        st.removed_prev[s] = st.kf_id[s * st.N + q - 1];
+      }
+      remove_slot(st, s, q, n);
       if (t == 0) st.n_kf[s] = n - 1;
     }
   }
@@ -456,6 +476,10 @@ int vo_create(const vo_config* cfg, vo_handle** out) {
   A((void**)&st.depth_out, 8 * (size_t)S * P);
   A((void**)&st.flow, 8 * S);
   A((void**)&st.removed, 4 * S);
+  A((void**)&st.removed_prev, 4 * S);
+  A((void**)&st.removed_rel, 8 * 7 * S);
+  A((void**)&st.retired, 4 * S);
+  A((void**)&st.retired_pose, 8 * 7 * S);
   A((void**)&st.vstatus, 4 * S);
   A((void**)&h->d_active, 4 * S);
   A((void**)&h->d_e_off, 8 * (S + 1));
@@ -487,6 +511,8 @@ int vo_create(const vo_config* cfg, vo_handle** out) {
             hipMemcpy(st.n_kf, zeros.data(), 4 * S, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(st.e_next, first.data(), 4 * S, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(st.removed, std::vector<int32_t>(S, -1).data(), 4 * S, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(st.removed_prev, std::vector<int32_t>(S, -1).data(), 4 * S, hipMemcpyHostToDevice) == hipSuccess &&
+            hipMemcpy(st.retired, std::vector<int32_t>(S, -1).data(), 4 * S, hipMemcpyHostToDevice) == hipSuccess &&
             hipMemcpy(st.vstatus, zeros.data(), 4 * S, hipMemcpyHostToDevice) == hipSuccess;
   std::vector<double> nan(S, NAN);
   ok = ok && hipMemcpy(st.flow, nan.data(), 8 * S, hipMemcpyHostToDevice) == hipSuccess;
@@ -565,7 +591,7 @@ int vo_step(vo_handle* h, const int32_t* frame_id, const double* new_xy, const d
   if (hipMemcpyAsync(h->d_init_depth, init_depth, 8 * S, hipMemcpyHostToDevice, s) != hipSuccess) return BA_E_HIP;
   if (hipMemcpyAsync(h->d_e_off, h->edge_off.data(), 8 * (S + 1), hipMemcpyHostToDevice, s) != hipSuccess)
     return BA_E_HIP;
-  hipLaunchKernelGGL(k_vo_clear, dim3(1), dim3(256), 0, s, st.vstatus, S);
+  hipLaunchKernelGGL(k_vo_clear, dim3((S + 255) / 256), dim3(256), 0, s, st);
   hipLaunchKernelGGL(k_vo_expand, dim3(S), dim3(WG), 0, s, st, new_xy, init_poses, (const double*)h->d_init_depth);
   const int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(64, (h->Ecap + 4095) / 4096));
   if (h->cfg.precision == BA_PREC_FP32)
@@ -609,6 +635,22 @@ int vo_read(vo_handle* h, int32_t* n_kf, int32_t* kf_id, double* flow, int32_t* 
   if (kf_id && hipMemcpy(kf_id, st.kf_id, 4 * (size_t)S * N, hipMemcpyDeviceToHost) != hipSuccess) return BA_E_HIP;
   if (flow && hipMemcpy(flow, st.flow, 8 * S, hipMemcpyDeviceToHost) != hipSuccess) return BA_E_HIP;
   if (removed && hipMemcpy(removed, st.removed, 4 * S, hipMemcpyDeviceToHost) != hipSuccess) return BA_E_HIP;
+  return BA_OK;
+}
+
+int vo_read_events(vo_handle* h, int32_t* retired, double* retired_pose, int32_t* removed, int32_t* removed_prev,
+                   double* removed_rel) {
+  if (!h) return BA_E_INVAL;
+  const int S = h->cfg.n_streams;
+  State& st = h->st;
+  if (retired && hipMemcpy(retired, st.retired, 4 * S, hipMemcpyDeviceToHost) != hipSuccess) return BA_E_HIP;
+  if (retired_pose && hipMemcpy(retired_pose, st.retired_pose, 8 * 7 * S, hipMemcpyDeviceToHost) != hipSuccess)
+    return BA_E_HIP;
+  if (removed && hipMemcpy(removed, st.removed, 4 * S, hipMemcpyDeviceToHost) != hipSuccess) return BA_E_HIP;
+  if (removed_prev && hipMemcpy(removed_prev, st.removed_prev, 4 * S, hipMemcpyDeviceToHost) != hipSuccess)
+    return BA_E_HIP;
+  if (removed_rel && hipMemcpy(removed_rel, st.removed_rel, 8 * 7 * S, hipMemcpyDeviceToHost) != hipSuccess)
+    return BA_E_HIP;
   return BA_OK;
 }
 

@@ -22,7 +22,7 @@ EXPORTED = ("ba_create", "ba_solve", "ba_backward", "ba_prepare", "ba_launch", "
             "ba_debug_reduced_system", "ba_debug_mfma", "ba_solve_noalloc",
             "dpc_correlation", "dpc_avg_pool", "dpc_debug_mfma_bf16",
             "dpa_softagg", "dpa_workspace_bytes",
-            "vo_create", "vo_set_sensor", "vo_step", "vo_read", "vo_read_window", "vo_status", "vo_destroy")
+            "vo_create", "vo_set_sensor", "vo_step", "vo_read", "vo_read_events", "vo_read_window", "vo_status", "vo_destroy")
 STAGES = ("prep", "assemble", "chol", "backsub", "finalize", "fused")
 
 
@@ -133,6 +133,8 @@ def lib() -> ctypes.CDLL:
         L.vo_step.restype = ctypes.c_int
         L.vo_read.argtypes = [vp, vp, vp, vp, vp]
         L.vo_read.restype = ctypes.c_int
+        L.vo_read_events.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.vo_read_events.restype = ctypes.c_int
         L.vo_read_window.argtypes = [vp, i32, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_int64)]
         L.vo_read_window.restype = ctypes.c_int
         L.vo_status.argtypes = [vp, vp]

@@ -15,6 +15,50 @@ from .native import BAError, VOConfig
 PRECISIONS = {"fp64": native.BA_PREC_FP64, "fp32": native.BA_PREC_FP32}
 
 
+def _quat_mul(a, b):
+    ax, ay, az, aw = a
+    bx, by, bz, bw = b
+    return np.array([aw * bx + bw * ax + ay * bz - az * by, aw * by + bw * ay + az * bx - ax * bz,
+                     aw * bz + bw * az + ax * by - ay * bx, aw * bw - ax * bx - ay * by - az * bz])
+
+
+def _rot(q):
+    x, y, z, w = q / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def compose(a, b):
+    """Pose 7-vector (t, q) of T_a T_b."""
+    q = _quat_mul(a[3:], b[3:])
+    return np.concatenate([_rot(a[3:]) @ b[:3] + a[:3], q / np.linalg.norm(q)])
+
+
+def assemble_trajectory(kf_ids, kf_poses, retired, removed):
+    """Whole trajectory of a stream ("Keyframing", Sec. 3.3): keyframes in the
+    window as they stand, keyframes that left full windows as they left
+    (retired: frame id -> pose), and removed keyframes (removed: frame id ->
+    (previous keyframe id, T_removed T_prev^-1)) as their relative pose
+    applied to the pose of the keyframe before them, itself resolved the same
+    way.  Returns frame id -> pose, in frame order."""
+    out = {int(f): np.asarray(p) for f, p in zip(kf_ids, kf_poses)}
+    out.update({int(f): np.asarray(p) for f, p in retired.items()})
+    todo = sorted(f for f in removed if f not in out)
+    while todo:
+        left = []
+        for f in todo:
+            prev, rel = removed[f]
+            if prev in out:
+                out[f] = compose(rel, out[prev])
+            else:
+                left.append(f)
+        if len(left) == len(todo):
+            raise ValueError(f"removed keyframes {left} refer to frames never seen")
+        todo = left
+    return dict(sorted(out.items()))
+
+
 def _host(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
@@ -26,7 +70,7 @@ class Driver:
 
     def __init__(self, streams: Sequence, precision: str = "fp64", window: int = 22, radius: int = 13,
                  n_free: int = 10, iterations: int = 2, flow_thresh: float = 64.0, lam: float = 1e-4,
-                 z_min: float = 0.1, device="cuda"):
+                 z_min: float = 0.1, device="cuda", track_trajectory: bool = True):
         self.lib = native.lib()
         self.streams = list(streams)
         s0 = self.streams[0]
@@ -54,6 +98,11 @@ class Driver:
         self.init_poses = torch.as_tensor(np.stack([s.init_poses for s in self.streams]), device=device).contiguous()
         self.init_depth = np.array([s.init_depth for s in self.streams], np.float64)
         self.device = device
+        # per stream: final poses of keyframes that left full windows, and the
+        # removed keyframes with their previous keyframe and relative pose
+        self.track = track_trajectory
+        self.retired = [dict() for _ in range(self.S)]
+        self.removed = [dict() for _ in range(self.S)]
 
     def _check(self, r):
         if r != native.BA_OK:
@@ -70,6 +119,30 @@ class Driver:
         st = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
         self._check(self.lib.vo_step(self.h, _host(fid), ctypes.c_void_p(self._xy.data_ptr()),
                                      ctypes.c_void_p(self.init_poses.data_ptr()), _host(self.init_depth), st))
+        if self.track:
+            ev = self.events()
+            for i in range(self.S):
+                if ev["retired"][i] >= 0:
+                    self.retired[i][int(ev["retired"][i])] = ev["retired_pose"][i].copy()
+                if ev["removed"][i] >= 0:
+                    self.removed[i][int(ev["removed"][i])] = (int(ev["removed_prev"][i]), ev["removed_rel"][i].copy())
+
+    def events(self):
+        """What the last step took out of each window (vo_read_events)."""
+        ev = dict(retired=np.zeros(self.S, np.int32), retired_pose=np.zeros((self.S, 7)),
+                  removed=np.zeros(self.S, np.int32), removed_prev=np.zeros(self.S, np.int32),
+                  removed_rel=np.zeros((self.S, 7)))
+        self._check(self.lib.vo_read_events(self.h, _host(ev["retired"]), _host(ev["retired_pose"]),
+                                            _host(ev["removed"]), _host(ev["removed_prev"]),
+                                            _host(ev["removed_rel"])))
+        return ev
+
+    def trajectory(self, s: int):
+        """Pose of every frame stream s has processed (assemble_trajectory)."""
+        n, kf, _, _ = self.read()
+        poses, _, _, _ = self.window(s)
+        k = int(n[s])
+        return assemble_trajectory(kf[s, :k].tolist(), poses[:k], self.retired[s], self.removed[s])
 
     def read(self):
         n = np.zeros(self.S, np.int32)

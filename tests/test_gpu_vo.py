@@ -20,6 +20,7 @@ import torch
 
 from oracle import vo_oracle as V
 from paper_2208_04726_amd import synth
+from paper_2208_04726_amd.vo import assemble_trajectory
 from tests.gpu_util import need_gpu
 
 pytestmark = pytest.mark.gpu
@@ -50,10 +51,12 @@ def _run(streams, steps, window, radius, precision="fp64", idle=None):
         print(f"step {t}: frames {ids.tolist()}", flush=True)
         drv.step(ids)
         n, kf, flow, rem = drv.read()
+        ev = drv.events()
         assert (drv.status() == 0).all(), drv.status()
         for s, o in enumerate(orc):
             if ids[s] < 0:
                 continue
+            before = set(o.final)
             rec = o.step(int(ids[s]))
             rec2 = shaken[s].step(int(ids[s]))
             if rec2["kf"] == rec["kf"]:
@@ -70,10 +73,35 @@ def _run(streams, steps, window, radius, precision="fp64", idle=None):
             else:
                 assert abs(flow[s] - rec["flow"]) <= 1e-6 * max(1.0, rec["flow"]), (t, s, flow[s], rec["flow"])
                 decisions["removed" if rec["removed"] is not None else "kept"] += 1
+            # what left the window: the retired keyframe and its pose, the
+            # removed keyframe's neighbour and relative pose
+            new = set(o.final) - before
+            if new:
+                fid, = new
+                assert ev["retired"][s] == fid, (t, s, ev["retired"][s], fid)
+                e1 = synth.pose_errors(ev["retired_pose"][s][None], o.final[fid][None])
+                worst[:2] = np.maximum(worst[:2], e1)
+            else:
+                assert ev["retired"][s] == -1
+            if rec["removed"] is not None:
+                f_, prev, rel = o.removed[-1]
+                assert ev["removed"][s] == f_ and ev["removed_prev"][s] == prev, (t, s)
+                e2 = synth.pose_errors(ev["removed_rel"][s][None], rel[None])
+                worst[:2] = np.maximum(worst[:2], e2)
+            else:
+                assert ev["removed"][s] == -1
             dc, drot = synth.pose_errors(poses[:k], rec["poses"])
             dd = float(np.max(np.abs(depth[:k * o.ppf] - rec["depth"]) / np.abs(rec["depth"])))
             worst = np.maximum(worst, (dc, drot, dd))
         frame += (ids >= 0)
+    # the whole trajectory: every processed frame, against the same assembly
+    # of the oracle's pieces
+    for s_, o in enumerate(orc):
+        got = drv.trajectory(s_)
+        want = assemble_trajectory(o.kf, o.poses, o.final, {f: (p, r) for f, p, r in o.removed})
+        assert sorted(got) == sorted(want) == list(range(int(frame[s_])))
+        e3 = synth.pose_errors(np.stack([got[f] for f in want]), np.stack(list(want.values())))
+        worst[:2] = np.maximum(worst[:2], e3)
     drv.close()
     print(f"worst over the run: {worst[0]:.2e} m {worst[1]:.2e} deg depth {worst[2]:.2e}; "
           f"oracle spread {spread[0]:.2e} m {spread[1]:.2e} deg depth {spread[2]:.2e}; decisions {decisions}")
