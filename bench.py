@@ -702,6 +702,45 @@ def run_driver(args, torch):
     return out
 
 
+def run_stream_serving(args, torch):
+    """Stateful serving of camera streams (serve.StreamServer): frames arrive
+    open-loop at a fixed rate per stream with random phases, every step takes
+    the oldest waiting frame of each stream; windows stay on the device.
+    Latency = arrival to the end of the step that took the frame, over frames
+    25 and later (full windows).  Baseline at 16 streams: one driver per
+    stream, one frame per step (serve.PlainStreamServer)."""
+    from paper_2208_04726_amd import synth
+    from paper_2208_04726_amd.serve import (PlainStreamServer, StreamServer, frame_latency_summary,
+                                             frame_trace)
+    from paper_2208_04726_amd.vo import Driver
+    F = 80
+    base = [synth.make_stream(F + 2, 96, seed=[2208, 30, i], fp32=True) for i in range(16)]
+    out = {"workload": f"camera streams of 22-keyframe windows x 96 patches, radius 13, FP32 assembly; {F} frames "
+                       "per stream at a fixed rate with random phases and 10% jitter; latency over frames 25+"}
+    for S, fps in ((256, 60.0), (256, 120.0), (16, 60.0)):
+        drv = Driver([base[i % 16] for i in range(S)], precision="fp32", track_trajectory=False)
+        reqs = frame_trace(S, F, fps, seed=S)
+        t = time.perf_counter()
+        res = StreamServer(drv).run(reqs)
+        wall = time.perf_counter() - t
+        rec = frame_latency_summary(res, min_frame=25)
+        rec.update(offered_frames_per_s=S * fps, served_frames_per_s=round(len(reqs) / wall, 1))
+        out[f"batched_{S}x{int(fps)}fps"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rec.items()}
+        drv.close()
+        if S == 16:
+            drivers = [Driver([base[i]], precision="fp32", track_trajectory=False) for i in range(S)]
+            t = time.perf_counter()
+            res = PlainStreamServer(drivers).run(reqs)
+            wall = time.perf_counter() - t
+            rec = frame_latency_summary(res, min_frame=25)
+            rec.update(offered_frames_per_s=S * fps, served_frames_per_s=round(len(reqs) / wall, 1))
+            out[f"plain_{S}x{int(fps)}fps"] = {k: (round(v, 4) if isinstance(v, float) else v)
+                                               for k, v in rec.items()}
+            for d in drivers:
+                d.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -770,6 +809,7 @@ def main():
         return
     if args.vo_only:
         print(json.dumps(run_driver(args, torch)), flush=True)
+        print(json.dumps(run_stream_serving(args, torch)), flush=True)
         return
     # the CPU baseline runs first, in processes started before the GPU is used
     cpu = None if args.no_cpu_baseline else cpu_oracle_baseline(args.cpu_budget)
@@ -901,6 +941,8 @@ def main():
         out["driver"] = run_driver(args, torch)
         out["parity"]["driver"] = out["driver"]["fp64"]["parity_stream0"]
         log(f"driver: {out['driver']}")
+        out["stream_serving"] = run_stream_serving(args, torch)
+        log(f"stream serving: {out['stream_serving']}")
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)

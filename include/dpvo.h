@@ -39,8 +39,9 @@
  * window together and share one set of target frames, so the patch graph is
  * one 64-bit row of target slots per keyframe slot.  Every step generates the
  * edge list from these rows, packed across the streams in (patch, target
- * frame) order, and solves all streams' windows in one bundle adjustment on
- * the state buffers themselves.
+ * frame) order, packs the windows of the streams with a new frame into
+ * staging buffers and solves them in one bundle adjustment; idle streams
+ * cost nothing in the solve.
  *
  * Errors: BA_OK (0) or BA_E_INVAL (-1) / BA_E_CAPACITY (-2) / BA_E_HIP (-3)
  * / BA_E_STATE (-4) of dpba.h.
@@ -123,7 +124,7 @@ int vo_read_window(vo_handle* h, int32_t s, double* poses, double* depth, int32_
                    int32_t* edge_frame, int64_t* n_edges);
 
 /* BA status bits (dpba.h BA_W_*) of each stream's window in the last step
- * (host [S]); bit 16 marks an edge outside the stream's sensor table (its
+ * (host [S]; 0 for a stream that was idle); bit 16 marks an edge outside the stream's sensor table (its
  * weight is 0), bit 17 an edge count that disagrees with the graph (an
  * internal error: the step used the smaller count). */
 int vo_status(vo_handle* h, int32_t* flags);

@@ -56,7 +56,10 @@ struct State {
   void* tgt;            // [E][2] f32 or f64
   void* wgt;
   const int64_t* e_off; // [S+1] this step's first edge of every stream
-  double* depth_out;    // [S][P]
+  const int32_t* cslot; // [S]    this step's position of the stream among the active ones, or -1
+  double* c_poses;      // [S][N][7] the active windows, packed in cslot order, for the solve
+  double* c_patches;    // [S][P][3]
+  double* depth_out;    // [S][P]    solved inverse depths, packed like c_patches
   double* flow;         // [S]
   int32_t* removed;     // [S]     keyframe removed by this step's keyframing, or -1
   int32_t* removed_prev;// [S]     its previous keyframe
@@ -271,6 +274,15 @@ __global__ void __launch_bounds__(256) k_vo_build(State st, int chunks) {
     rowoff[n] = o;
   }
   __syncthreads();
+  // the window's poses and patches into the packed staging of the solve
+  {
+    const int a = st.cslot[s];
+    const double* src = st.patches + (int64_t)s * st.P * 3;
+    double* dst = st.c_patches + (int64_t)a * st.P * 3;
+    for (int i = c * 256 + t; i < st.P * 3; i += chunks * 256) dst[i] = src[i];
+    if (c == 0)
+      for (int i = t; i < st.N * 7; i += 256) st.c_poses[(int64_t)a * st.N * 7 + i] = st.poses[(int64_t)s * st.N * 7 + i];
+  }
   const int64_t e0 = st.e_off[s];
   const int ne = (int)(st.e_off[s + 1] - e0);
   if (ne != rowoff[n]) {   // the host's edge count disagrees with the graph
@@ -332,8 +344,10 @@ __global__ void __launch_bounds__(WG) k_vo_keyframe(State st) {
   const int s = blockIdx.x, t = threadIdx.x;
   if (st.active[s] < 0) return;
   const int n = st.n_kf[s];
+  const int cs = st.cslot[s];
   double* pt = st.patches + (int64_t)s * st.P * 3;
-  for (int i = t; i < n * st.ppf; i += WG) pt[i * 3 + 2] = st.depth_out[(int64_t)s * st.P + i];
+  for (int i = t; i < n * st.ppf; i += WG) pt[i * 3 + 2] = st.depth_out[(int64_t)cs * st.P + i];
+  for (int i = t; i < st.N * 7; i += WG) st.poses[(int64_t)s * st.N * 7 + i] = st.c_poses[(int64_t)cs * st.N * 7 + i];
   __syncthreads();
   double flow = NAN;
   int removed = -1;
@@ -403,9 +417,11 @@ struct vo_handle {
   int64_t Ecap = 0;                 // edges of one window at most
   std::vector<int32_t> n_kf_host, e_next_host;
   std::vector<int64_t> frame_off, patch_off, edge_off;
-  std::vector<int32_t> n_fixed;
+  std::vector<int32_t> n_fixed, cslot;
+  std::vector<int64_t> c_frame_off, c_patch_off, c_edge_off;
   std::vector<double> intr;
   int32_t* d_active = nullptr;
+  int32_t* d_cslot = nullptr;
   int32_t* d_anchor = nullptr;     // [S][P] keyframe slot of every patch slot
   double* d_init_depth = nullptr;  // [S]
   int64_t* d_e_off = nullptr;      // [S+1]
@@ -474,6 +490,9 @@ int vo_create(const vo_config* cfg, vo_handle** out) {
   A(&st.tgt, 2 * esz * E);
   A(&st.wgt, 2 * esz * E);
   A((void**)&st.depth_out, 8 * (size_t)S * P);
+  A((void**)&st.c_poses, 8 * 7 * (size_t)S * N);
+  A((void**)&st.c_patches, 8 * 3 * (size_t)S * P);
+  A((void**)&h->d_cslot, 4 * S);
   A((void**)&st.flow, 8 * S);
   A((void**)&st.removed, 4 * S);
   A((void**)&st.removed_prev, 4 * S);
@@ -493,6 +512,7 @@ int vo_create(const vo_config* cfg, vo_handle** out) {
   }
   st.active = h->d_active;
   st.e_off = h->d_e_off;
+  st.cslot = h->d_cslot;
   st.tab_off = h->d_tab_off;
   st.tab_frames = h->d_tab_frames;
   // empty windows: identity poses, unit inverse depths, no edges; the first
@@ -548,6 +568,10 @@ int vo_create(const vo_config* cfg, vo_handle** out) {
     h->patch_off[s] = (int64_t)s * P;
   }
   h->n_fixed.assign(S, 0);
+  h->cslot.assign(S, -1);
+  h->c_frame_off.assign(S + 1, 0);
+  h->c_patch_off.assign(S + 1, 0);
+  h->c_edge_off.assign(S + 1, 0);
   h->intr.resize(4 * S);
   for (int s = 0; s < S; ++s)
     for (int i = 0; i < 4; ++i) h->intr[4 * s + i] = cfg->intrinsics[i];
@@ -577,21 +601,34 @@ int vo_step(vo_handle* h, const int32_t* frame_id, const double* new_xy, const d
   hipStream_t s = (hipStream_t)stream;
   State& st = h->st;
   // keyframes and edges after the expansion, known on the host from the last
-  // step's read-back; idle streams enter the solve without edges, every pose
-  // fixed, and keep their state
+  // step's read-back.  Only the streams with a new frame enter the solve,
+  // their windows packed in stream order; idle streams keep their state.
+  int na = 0;
   for (int i = 0; i < S; ++i) {
     const bool on = frame_id[i] >= 0;
-    const int n = on ? std::min(h->n_kf_host[i] + 1, N) : h->n_kf_host[i];
-    h->n_fixed[i] = on ? std::max(std::min(2, n), n - h->cfg.n_free) : N;
-    h->edge_off[i + 1] = h->edge_off[i] + (on ? h->e_next_host[i] : 0);
     if (on && (h->e_next_host[i] < 0 || h->e_next_host[i] > h->Ecap)) return BA_E_STATE;
+    h->edge_off[i + 1] = h->edge_off[i] + (on ? h->e_next_host[i] : 0);
+    h->cslot[i] = on ? na : -1;
+    if (on) {
+      const int n = std::min(h->n_kf_host[i] + 1, N);
+      h->n_fixed[na] = std::max(std::min(2, n), n - h->cfg.n_free);
+      h->c_frame_off[na + 1] = (int64_t)(na + 1) * N;
+      h->c_patch_off[na + 1] = (int64_t)(na + 1) * st.P;
+      h->c_edge_off[na + 1] = h->edge_off[i + 1];
+      ++na;
+    }
   }
   // the host arrays are read before this call returns (it waits for the step)
   if (hipMemcpyAsync(h->d_active, frame_id, 4 * S, hipMemcpyHostToDevice, s) != hipSuccess) return BA_E_HIP;
   if (hipMemcpyAsync(h->d_init_depth, init_depth, 8 * S, hipMemcpyHostToDevice, s) != hipSuccess) return BA_E_HIP;
   if (hipMemcpyAsync(h->d_e_off, h->edge_off.data(), 8 * (S + 1), hipMemcpyHostToDevice, s) != hipSuccess)
     return BA_E_HIP;
+  if (hipMemcpyAsync(h->d_cslot, h->cslot.data(), 4 * S, hipMemcpyHostToDevice, s) != hipSuccess) return BA_E_HIP;
   hipLaunchKernelGGL(k_vo_clear, dim3((S + 255) / 256), dim3(256), 0, s, st);
+  if (na == 0) {
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return BA_E_HIP;
+    return BA_OK;
+  }
   hipLaunchKernelGGL(k_vo_expand, dim3(S), dim3(WG), 0, s, st, new_xy, init_poses, (const double*)h->d_init_depth);
   const int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(64, (h->Ecap + 4095) / 4096));
   if (h->cfg.precision == BA_PREC_FP32)
@@ -601,20 +638,20 @@ int vo_step(vo_handle* h, const int32_t* frame_id, const double* new_xy, const d
   if (hipGetLastError() != hipSuccess) return BA_E_HIP;
   ba_problem p;
   memset(&p, 0, sizeof(p));
-  p.n_windows = S;
-  p.frame_off = h->frame_off.data();
-  p.patch_off = h->patch_off.data();
-  p.edge_off = h->edge_off.data();
+  p.n_windows = na;
+  p.frame_off = h->c_frame_off.data();
+  p.patch_off = h->c_patch_off.data();
+  p.edge_off = h->c_edge_off.data();
   p.n_fixed = h->n_fixed.data();
   p.intrinsics = h->intr.data();
-  p.poses_in = st.poses;
-  p.patches_in = st.patches;
+  p.poses_in = st.c_poses;
+  p.patches_in = st.c_patches;
   p.anchor = h->d_anchor;
   p.kk = st.kk;
   p.jj = st.jj;
   p.targets = st.tgt;
   p.weights = st.wgt;
-  p.poses_out = st.poses;        // in place: the window's poses are the state
+  p.poses_out = st.c_poses;      // in place in the staging, copied back by k_vo_keyframe
   p.depth_out = st.depth_out;
   int rc = ba_solve(h->ba, &p, stream);
   if (rc != BA_OK) return rc;
@@ -693,10 +730,13 @@ int vo_read_window(vo_handle* h, int32_t s, double* poses, double* depth, int32_
 int vo_status(vo_handle* h, int32_t* flags) {
   if (!h || !flags) return BA_E_INVAL;
   const int S = h->cfg.n_streams;
-  std::vector<int32_t> ba(S), vs(S);
-  if (ba_status(h->ba, ba.data()) != BA_OK) return BA_E_HIP;
+  // the last solve's windows are the streams that had a new frame, packed
+  std::vector<int32_t> ba(S, 0), vs(S);
+  if (std::any_of(h->cslot.begin(), h->cslot.end(), [](int32_t c) { return c >= 0; }) &&
+      ba_status(h->ba, ba.data()) != BA_OK)
+    return BA_E_HIP;
   if (hipMemcpy(vs.data(), h->st.vstatus, 4 * S, hipMemcpyDeviceToHost) != hipSuccess) return BA_E_HIP;
-  for (int s = 0; s < S; ++s) flags[s] = ba[s] | vs[s];
+  for (int s = 0; s < S; ++s) flags[s] = (h->cslot[s] >= 0 ? ba[h->cslot[s]] : 0) | vs[s];
   return BA_OK;
 }
 

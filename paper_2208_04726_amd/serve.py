@@ -407,3 +407,124 @@ def latency_summary(results: Dict[int, Result], skip: int = 0) -> Dict[str, floa
     return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "p999_ms": float(np.percentile(lat, 99.9)), "mean_ms": float(lat.mean()),
             "n": int(lat.size)}
+
+
+# ---------------------------------------------------------------------------
+# Stateful serving of camera streams on the sliding-window driver
+
+@dataclasses.dataclass
+class FrameRequest:
+    rid: int
+    stream: int
+    frame: int
+    arrival: float          # seconds after the start of the run
+
+
+@dataclasses.dataclass
+class FrameResult:
+    rid: int
+    stream: int
+    frame: int
+    latency: float          # seconds, arrival to the end of the step that took the frame
+    batch: int              # frames stepped together with this one (itself included)
+
+
+def frame_trace(n_streams: int, n_frames: int, fps: float, seed: int = 0,
+                jitter: float = 0.1) -> List[FrameRequest]:
+    """Every stream sends frames 0 .. n_frames-1 at `fps`, from a random phase
+    in [0, 1/fps), each arrival jittered by up to `jitter` of a frame period;
+    requests in arrival order (rid = position)."""
+    rng = np.random.default_rng(seed)
+    period = 1.0 / fps
+    phase = rng.uniform(0, period, n_streams)
+    reqs = []
+    for s in range(n_streams):
+        t = phase[s] + period * (np.arange(n_frames) + jitter * rng.uniform(0, 1, n_frames))
+        reqs += [(float(t[f]), s, f) for f in range(n_frames)]
+    reqs.sort()
+    return [FrameRequest(i, s, f, t) for i, (t, s, f) in enumerate(reqs)]
+
+
+def _wait_until(clock, t0, t):
+    while clock() - t0 < t:
+        dt = t - (clock() - t0)
+        if dt > 2e-4:
+            time.sleep(dt - 1e-4)
+
+
+class StreamServer:
+    """Continuous batching of camera streams whose windows live on the device
+    (include/dpvo.h): every step takes the oldest waiting frame of every
+    stream that has one and steps them together in one vo_step; a frame that
+    arrives during a step joins the next one.  A stream's frames are stepped
+    in order, one per step; nothing of a window is uploaded or read back."""
+
+    def __init__(self, driver):
+        self.driver = driver
+
+    def run(self, requests: Sequence[FrameRequest], clock=time.perf_counter) -> Dict[int, FrameResult]:
+        with _no_gc():
+            return self._run(requests, clock)
+
+    def _run(self, requests, clock):
+        S = self.driver.S
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        pending = [collections.deque() for _ in range(S)]
+        results: Dict[int, FrameResult] = {}
+        fid = np.full(S, -1, np.int32)
+        i, n = 0, len(reqs)
+        t0 = clock()
+        while len(results) < n:
+            now = clock() - t0
+            while i < n and reqs[i].arrival <= now:
+                pending[reqs[i].stream].append(reqs[i])
+                i += 1
+            ready = [s for s in range(S) if pending[s]]
+            if not ready:
+                _wait_until(clock, t0, reqs[i].arrival)
+                continue
+            fid[:] = -1
+            for s in ready:
+                fid[s] = pending[s][0].frame
+            self.driver.step(fid)
+            t = clock() - t0
+            for s in ready:
+                r = pending[s].popleft()
+                results[r.rid] = FrameResult(r.rid, r.stream, r.frame, t - r.arrival, len(ready))
+        return results
+
+
+class PlainStreamServer:
+    """The baseline: one driver per stream and one frame per step, in arrival
+    order."""
+
+    def __init__(self, drivers):
+        self.drivers = drivers
+
+    def run(self, requests: Sequence[FrameRequest], clock=time.perf_counter) -> Dict[int, FrameResult]:
+        with _no_gc():
+            return self._run(requests, clock)
+
+    def _run(self, requests, clock):
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        one = np.zeros(1, np.int32)
+        results: Dict[int, FrameResult] = {}
+        t0 = clock()
+        for r in reqs:
+            _wait_until(clock, t0, r.arrival)
+            one[0] = r.frame
+            self.drivers[r.stream].step(one)
+            results[r.rid] = FrameResult(r.rid, r.stream, r.frame, clock() - t0 - r.arrival, 1)
+        return results
+
+
+def frame_latency_summary(results: Dict[int, FrameResult], min_frame: int = 0) -> Dict[str, float]:
+    """Latency percentiles (ms) over frames >= min_frame, the mean batch, and
+    the frames per second the run sustained."""
+    sel = [r for r in results.values() if r.frame >= min_frame]
+    if not sel:
+        return {}
+    lat = np.array([r.latency for r in sel]) * 1e3
+    return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+            "mean_batch": float(np.mean([r.batch for r in sel])), "n": len(sel)}

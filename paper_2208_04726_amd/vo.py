@@ -86,11 +86,18 @@ class Driver:
         if r != native.BA_OK:
             raise BAError(r, "vo_create failed")
         self.h = h
-        # sensor tables of all streams, concatenated on the device
-        self.tab_t = torch.as_tensor(np.concatenate([s.table_t for s in self.streams]), device=device).contiguous()
-        self.tab_w = torch.as_tensor(np.concatenate([s.table_w for s in self.streams]), device=device).contiguous()
-        rows = np.array([s.table_t.shape[0] for s in self.streams], np.int64)
-        self.tab_off = np.concatenate([[0], np.cumsum(rows)[:-1]]).astype(np.int64)
+        # sensor tables on the device, one copy per distinct stream object
+        # (streams given more than once share their rows)
+        uniq, where = [], {}
+        for st_ in self.streams:
+            if id(st_) not in where:
+                where[id(st_)] = len(uniq)
+                uniq.append(st_)
+        rows = np.array([u.table_t.shape[0] for u in uniq], np.int64)
+        first = np.concatenate([[0], np.cumsum(rows)[:-1]]).astype(np.int64)
+        self.tab_t = torch.as_tensor(np.concatenate([u.table_t for u in uniq]), device=device).contiguous()
+        self.tab_w = torch.as_tensor(np.concatenate([u.table_w for u in uniq]), device=device).contiguous()
+        self.tab_off = np.array([first[where[id(st_)]] for st_ in self.streams], np.int64)
         self.tab_frames = np.array([s.poses_gt.shape[0] for s in self.streams], np.int32)
         self._check(self.lib.vo_set_sensor(self.h, ctypes.c_void_p(self.tab_t.data_ptr()),
                                            ctypes.c_void_p(self.tab_w.data_ptr()), _host(self.tab_off),
@@ -98,6 +105,15 @@ class Driver:
         self.init_poses = torch.as_tensor(np.stack([s.init_poses for s in self.streams]), device=device).contiguous()
         self.init_depth = np.array([s.init_depth for s in self.streams], np.float64)
         self.device = device
+        # the new frames' patch centres: gathered on the host into pinned
+        # memory, one asynchronous copy per step (vo_step waits for the step,
+        # so the buffers are free again when it returns)
+        self._uniq_xy = [u.xy for u in uniq]
+        same = len({u.xy.shape for u in uniq}) == 1
+        self._xy_all = np.stack(self._uniq_xy) if same else None
+        self._which = np.array([where[id(st_)] for st_ in self.streams])
+        self._xy_host = torch.zeros((self.S, self.ppf, 2), dtype=torch.float64, pin_memory=True)
+        self._xy_dev = torch.zeros((self.S, self.ppf, 2), dtype=torch.float64, device=device)
         # per stream: final poses of keyframes that left full windows, and the
         # removed keyframes with their previous keyframe and relative pose
         self.track = track_trajectory
@@ -111,13 +127,20 @@ class Driver:
     def step(self, frame_ids, stream=None):
         """One new frame per stream (frame_ids[s] < 0: stream idle)."""
         fid = np.ascontiguousarray(frame_ids, np.int32)
-        xy = np.zeros((self.S, self.ppf, 2))
-        for i, s in enumerate(self.streams):
-            if fid[i] >= 0:
-                xy[i] = s.xy[fid[i]]
-        self._xy = torch.as_tensor(xy, device=self.device).contiguous()
-        st = ctypes.c_void_p((stream or torch.cuda.current_stream()).cuda_stream)
-        self._check(self.lib.vo_step(self.h, _host(fid), ctypes.c_void_p(self._xy.data_ptr()),
+        if fid.shape != (self.S,):
+            raise ValueError(f"frame_ids must have shape ({self.S},)")
+        xy = self._xy_host.numpy()
+        act = np.nonzero(fid >= 0)[0]
+        if self._xy_all is not None:
+            xy[act] = self._xy_all[self._which[act], fid[act]]
+        else:
+            for i in act:
+                xy[i] = self._uniq_xy[self._which[i]][fid[i]]
+        torch_stream = stream or torch.cuda.current_stream()
+        with torch.cuda.stream(torch_stream):
+            self._xy_dev.copy_(self._xy_host, non_blocking=True)
+        st = ctypes.c_void_p(torch_stream.cuda_stream)
+        self._check(self.lib.vo_step(self.h, _host(fid), ctypes.c_void_p(self._xy_dev.data_ptr()),
                                      ctypes.c_void_p(self.init_poses.data_ptr()), _host(self.init_depth), st))
         if self.track:
             ev = self.events()

@@ -1,5 +1,6 @@
 """Host-side logic of the serving engine (admission, traces, summaries); no GPU."""
 import collections
+import time
 
 import numpy as np
 import pytest
@@ -98,3 +99,47 @@ def test_oversize_request_is_rejected_alone():
     for r in res.values():
         assert r.status == native.BA_E_CAPACITY
     assert res[7].poses.shape == (23, 7) and res[8].depth.shape == (500,)
+
+
+class _FakeDriver:
+    """Records the frame ids of every step (no GPU)."""
+
+    def __init__(self, S, step_time=0.0):
+        self.S, self.calls, self.step_time = S, [], step_time
+
+    def step(self, fid):
+        self.calls.append(np.array(fid).copy())
+        if self.step_time:
+            time.sleep(self.step_time)
+
+
+def test_stream_server_steps_each_stream_in_order_and_batches():
+    from paper_2208_04726_amd.serve import StreamServer, frame_trace
+    reqs = frame_trace(5, 7, fps=4000.0, seed=1)
+    drv = _FakeDriver(5, step_time=1e-3)
+    res = StreamServer(drv).run(reqs)
+    assert sorted(res) == list(range(len(reqs)))
+    per = {s: [] for s in range(5)}
+    step_of = {}
+    for k, fid in enumerate(drv.calls):
+        for s in range(5):
+            if fid[s] >= 0:
+                per[s].append(int(fid[s]))
+                step_of[(s, int(fid[s]))] = k
+    assert all(per[s] == list(range(7)) for s in range(5))           # in order, once each
+    assert max(r.batch for r in res.values()) > 1                     # frames were stepped together
+    assert len(drv.calls) < len(reqs)
+    for r in res.values():
+        assert r.latency >= 0
+        assert r.batch == int((drv.calls[step_of[(r.stream, r.frame)]] >= 0).sum())
+
+
+def test_plain_stream_server_is_one_frame_per_step_in_arrival_order():
+    from paper_2208_04726_amd.serve import PlainStreamServer, frame_trace
+    reqs = frame_trace(3, 4, fps=5000.0, seed=2)
+    drivers = [_FakeDriver(1) for _ in range(3)]
+    res = PlainStreamServer(drivers).run(reqs)
+    assert sorted(res) == list(range(len(reqs)))
+    for s in range(3):
+        assert [int(c[0]) for c in drivers[s].calls] == list(range(4))
+    assert all(r.batch == 1 for r in res.values())
