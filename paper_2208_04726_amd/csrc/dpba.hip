@@ -21,11 +21,18 @@ using namespace dpba;
 
 // ---------------------------------------------------------------------------
 // kernels
+// The edge pass of the preparation, EPB edges per workgroup.
+__global__ void __launch_bounds__(WG) k_prep_edges(Params P) {
+  __shared__ int lds[1];
+  if ((int)blockIdx.x >= P.counts[2]) return;
+  wg_prep_edges(P, blockIdx.x, lds);
+}
+
 template <typename T>
-__global__ void __launch_bounds__(WG) k_prep(Params P) {
+__global__ void __launch_bounds__(WG) k_prep(Params P, int edges_done) {
   __shared__ int lds[PREP_LDS_INTS];
   if ((int)blockIdx.x >= P.counts[0]) return;
-  wg_prep<T>(P, blockIdx.x, lds);
+  wg_prep<T>(P, blockIdx.x, lds, edges_done != 0);
 }
 
 template <typename T, int MAXT>
@@ -204,6 +211,7 @@ struct ba_handle {
   int n_cu = 256;
   int64_t cap_chunks = 0;
   int64_t cap_partial = 0;   // elements
+  int64_t cap_eblocks = 0;   // edge blocks of the split preparation
   WinDesc* d_win = nullptr;
   ChunkDesc* d_chunk = nullptr;
   WinDesc* h_win = nullptr;
@@ -212,6 +220,7 @@ struct ba_handle {
   bool staging_pending = false;
   hipStream_t last_stream = nullptr;
   int last_W = 0;
+  int32_t* eflags = nullptr;
   int32_t *status = nullptr, *wmeta = nullptr, *cnt = nullptr, *ptr = nullptr, *fill = nullptr;
   int32_t *acnt = nullptr, *afill = nullptr, *plist = nullptr, *csr = nullptr, *arange = nullptr,
           *cstate = nullptr, *estart = nullptr, *sbstart = nullptr, *gj = nullptr;
@@ -337,6 +346,9 @@ void set_capacities(ba_handle* h) {
     blocks = std::max(blocks, std::min<int64_t>(F, W * ((cfg->max_frames_per_window + cfg->chunk_frames - 1) /
                                                           cfg->chunk_frames)));
   h->cap_partial = blocks * (Dmax * Dmax + 2 * Dmax);
+  // edge blocks: every window's edges in blocks of EPB, so at most one partial
+  // block per window beyond the total
+  h->cap_eblocks = (std::max<int64_t>(cfg->max_edges, 0) + EPB - 1) / EPB + W;
 }
 
 // Every device buffer of a handle's workspace except the chunk partials,
@@ -351,6 +363,7 @@ void carve_workspace(ba_handle* h, Take take) {
   take((void**)&h->d_chunk, sizeof(ChunkDesc) * h->cap_chunks);
   take((void**)&h->d_counts, 16);
   take((void**)&h->status, 4 * W);
+  take((void**)&h->eflags, 4 * std::max<int64_t>(h->cap_eblocks, 1));
   take((void**)&h->wmeta, 16 * W);
   take((void**)&h->cnt, 4 * Pn);
   take((void**)&h->ptr, 4 * Pn);
@@ -408,7 +421,8 @@ int maxt_for(int tiles) {
 }
 
 struct Plan {
-  int W = 0, C = 0, Rcap = 1, nmax = 0, maxt = 4;
+  int W = 0, C = 0, Rcap = 1, nmax = 0, maxt = 4, EB = 0;
+  int64_t Emax = 0;        // edges of the largest window
   bool fused = false;
   bool capacity = false;   // grids sized for the handle's capacities (ba_launch)
   bool big = false;        // some window has more than 21 free frames
@@ -435,6 +449,7 @@ int validate_and_plan(ba_handle* h, const ba_problem* p, Plan& pl) {
     if (N > cfg.max_frames_per_window)
       return fail(h, BA_E_CAPACITY, "window %d has more frames than max_frames_per_window", w);
     if (M > INT32_MAX / 2 || E > INT32_MAX / 2) return fail(h, BA_E_CAPACITY, "window too large");
+    pl.Emax = std::max(pl.Emax, E);
     const int nf = p->n_fixed[w];
     if (nf < 0 || nf > N) return fail(h, BA_E_INVAL, "n_fixed outside [0, frames] in window %d", w);
     const int n = 6 * (int)(N - nf);
@@ -511,7 +526,7 @@ int build_descriptors(ba_handle* h, const ba_problem* p, Plan& pl, int sched) {
     h->staging_pending = false;
   }
   int64_t part_off = 0, sb_off = 0;
-  int ci = 0;
+  int ci = 0, eb = 0;
   for (int w = 0; w < W; ++w) {
     WinDesc& d = h->h_win[w];
     const int N = (int)(p->frame_off[w + 1] - p->frame_off[w]);
@@ -535,6 +550,9 @@ int build_descriptors(ba_handle* h, const ba_problem* p, Plan& pl, int sched) {
     d.part_stride = D * D + 2 * D;
     d.sb_off = sb_off;
     sb_off += (d.n_patches + 15) / 16 + N + 1;
+    d.eb_off = eb;
+    d.eb_n = (d.n_edges + EPB - 1) / EPB;
+    eb += d.eb_n;
     for (int q = 0; q < nc; ++q) {
       ChunkDesc& cd = h->h_chunk[ci++];
       cd.window = w;
@@ -545,6 +563,7 @@ int build_descriptors(ba_handle* h, const ba_problem* p, Plan& pl, int sched) {
     part_off += nc * d.part_stride;
   }
   pl.C = ci;
+  pl.EB = eb;
   if (sb_off > h->cap_sb) return fail(h, BA_E_CAPACITY, "sub-batch table too small");
   return BA_OK;
 }
@@ -567,6 +586,7 @@ void fill_params(ba_handle* h, const ba_problem* p, const Plan& pl, Params& P) {
   P.poses_out = p->poses_out;
   P.depth_out = p->depth_out;
   P.status = h->status;
+  P.eflags = h->eflags;
   P.wmeta = h->wmeta;
   P.cnt = h->cnt;
   P.ptr = h->ptr;
@@ -605,7 +625,8 @@ void fill_params(ba_handle* h, const ba_problem* p, const Plan& pl, Params& P) {
 int upload_descriptors(ba_handle* h, const Plan& pl, hipStream_t s) {
   h->h_counts[0] = pl.W;
   h->h_counts[1] = pl.C;
-  HIPCHK(h, hipMemcpyAsync(h->d_counts, h->h_counts, 8, hipMemcpyHostToDevice, s));
+  h->h_counts[2] = pl.EB;
+  HIPCHK(h, hipMemcpyAsync(h->d_counts, h->h_counts, 12, hipMemcpyHostToDevice, s));
   if (pl.W > 0)
     HIPCHK(h, hipMemcpyAsync(h->d_win, h->h_win, sizeof(WinDesc) * pl.W, hipMemcpyHostToDevice, s));
   if (pl.C > 0)
@@ -645,8 +666,15 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
     HIPCHK(h, hipGetLastError());
   } else {
     {
+      // the edge pass over many workgroups, then the rest per window.  The
+      // split pays when the batch leaves most CUs idle or a window is large;
+      // with many windows of moderate size the extra launch costs more than
+      // it saves.  Captured launches always split (any batch may follow).
+      const bool split = pl.capacity || 4LL * pl.W <= h->n_cu || pl.Emax >= 16LL * EPB;
+      const int64_t gEB = !split ? 0 : pl.capacity ? h->cap_eblocks : pl.EB;
       KernelTimer kt(h, s, BA_STAGE_PREP);
-      hipLaunchKernelGGL(k_prep<T>, dim3(gW), dim3(WG), 0, s, P);
+      if (gEB > 0) hipLaunchKernelGGL(k_prep_edges, dim3((unsigned)gEB), dim3(WG), 0, s, P);
+      hipLaunchKernelGGL(k_prep<T>, dim3(gW), dim3(WG), 0, s, P, gEB > 0 ? 1 : 0);
     }
     HIPCHK(h, hipGetLastError());
     for (int it = 0; it < P.iterations; ++it) {
@@ -706,7 +734,7 @@ int launch_backward(ba_handle* h, const ba_problem* p, const Plan& pl, const dou
   const int chol_adj_lds = chol_lds + 2 * 8 * pl.nmax + 64;
   const int adj_lds = edge_adj_lds_bytes(Rcap, esz);
   const int K = P.iterations;
-  hipLaunchKernelGGL(k_prep<T>, dim3(pl.W), dim3(WG), 0, s, P);
+  hipLaunchKernelGGL(k_prep<T>, dim3(pl.W), dim3(WG), 0, s, P, 0);
   HIPCHK(h, hipGetLastError());
   // recompute the iterates x_1 .. x_{K-1}
   for (int it = 0; it + 1 < K; ++it) {
@@ -930,7 +958,8 @@ int ba_solve_noalloc(const ba_config* cfg, const ba_problem* p, int32_t* status_
   if (r != BA_OK) return r;
   h->h_counts[0] = pl.W;
   h->h_counts[1] = pl.C;
-  h->h_counts[2] = h->h_counts[3] = 0;
+  h->h_counts[2] = pl.EB;
+  h->h_counts[3] = 0;
   r = noalloc_upload(h, D.base, h->d_counts, h->h_counts, 16, s);
   if (r == BA_OK) r = noalloc_upload(h, D.base, h->d_win, h->h_win, sizeof(WinDesc) * pl.W, s);
   if (r == BA_OK && pl.C > 0) r = noalloc_upload(h, D.base, h->d_chunk, h->h_chunk, sizeof(ChunkDesc) * pl.C, s);
@@ -1125,8 +1154,8 @@ int ba_debug_reduced_system(ba_handle* h, const ba_problem* p, int32_t window, d
   if (r != BA_OK) return r;
   const bool f32 = h->cfg.precision == BA_PREC_FP32;
   const int esz = f32 ? 4 : 8;
-  if (f32) hipLaunchKernelGGL(k_prep<float>, dim3(pl.W), dim3(WG), 0, s, P);
-  else hipLaunchKernelGGL(k_prep<double>, dim3(pl.W), dim3(WG), 0, s, P);
+  if (f32) hipLaunchKernelGGL(k_prep<float>, dim3(pl.W), dim3(WG), 0, s, P, 0);
+  else hipLaunchKernelGGL(k_prep<double>, dim3(pl.W), dim3(WG), 0, s, P, 0);
   HIPCHK(h, hipGetLastError());
   if (pl.C > 0) {
     // the accumulator-tile variant ba_solve selects for this batch

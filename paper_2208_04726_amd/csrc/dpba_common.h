@@ -29,6 +29,7 @@ struct WinDesc {
   int64_t part_off;               // first element of this window's partials
   int64_t part_stride;            // elements per chunk partial (D*D + D, D = 6*(N-nfix))
   int64_t sb_off;                 // first sub-batch descriptor of this window
+  int32_t eb_off, eb_n;           // edge blocks of the split preparation (EPB edges each)
 };
 
 struct ChunkDesc {
@@ -38,7 +39,7 @@ struct ChunkDesc {
 struct Params {
   const WinDesc* win;
   const ChunkDesc* chunk;
-  const int32_t* counts;  // device [2]: windows, chunks of this call (grids may be larger)
+  const int32_t* counts;  // device [3]: windows, chunks, edge blocks of this call (grids may be larger)
   int32_t iterations;
   double lambda, z_min;
   // problem (caller buffers)
@@ -53,6 +54,7 @@ struct Params {
   double* depth_out;
   // workspace
   int32_t* status;      // [W]
+  int32_t* eflags;      // [edge blocks] flags of each block of the edge pass (bad index, unsorted, duplicate)
   int32_t* wmeta;       // [W*4]: max degree, edges-sorted flag, anchors-sorted flag
   int32_t* cnt;         // [P] edges per patch
   int32_t* ptr;         // [P] first CSR slot of each patch (window-local)

@@ -31,7 +31,14 @@ constexpr int PU = 8;   // edges per thread in flight in the preparation loops
 // LDS of the preparation pass (ints): scan scratch, flags, per-frame ranges,
 // and per frame a regularity flag and the extremes of its patches' first and
 // last target frames
-constexpr int PREP_LDS_INTS = WG + 16 + 7 * RMAX;
+// Scan tiles: SCAN_PER consecutive entries per thread, staged through LDS
+// with one pad word per 32 (the per-thread runs then fall in distinct banks).
+constexpr int SCAN_PER = 8;
+constexpr int SCAN_TILE = SCAN_PER * WG;
+constexpr int SCAN_TILE_PAD = SCAN_TILE + SCAN_TILE / 32;
+// Stable ordering of unsorted patches: per wave and frame the counts of a
+// tile, and per frame the patches placed so far.
+constexpr int PREP_LDS_INTS = WG + 16 + 7 * RMAX + SCAN_TILE_PAD + NWAVES * RMAX + RMAX;
 // bit of a sub-batch descriptor's .y: every patch of the source frame has the
 // same strictly increasing sequence of target frames
 constexpr int SB_REGULAR = 1 << 16;
@@ -39,17 +46,128 @@ constexpr int SB_REGULAR = 1 << 16;
 __host__ __device__ inline int seg_width(int maxdeg) { return maxdeg <= 16 ? 16 : (maxdeg <= 32 ? 32 : 64); }
 __host__ __device__ inline int sb_width(int seg) { return seg == 64 ? 16 : 32; }
 
-__device__ __forceinline__ int lower_bound_i32(const int32_t* a, int n, int v) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (a[mid] < v) lo = mid + 1; else hi = mid;
+__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }
+
+// Exclusive prefix sum of data[0, n) in place, by tiles of SCAN_TILE entries:
+// coalesced loads into LDS, each thread sums its SCAN_PER consecutive
+// entries, a wave scan of the thread sums and one of the wave totals, then
+// coalesced stores.  `part` holds NWAVES ints, `tile` SCAN_TILE_PAD.
+// Returns the total.  All threads call.
+__device__ int wg_scan_tiled(int32_t* data, int n, int* part, int* tile) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int carry = 0;
+  for (int base = 0; base < n; base += SCAN_TILE) {
+    const int m = min(SCAN_TILE, n - base);
+#pragma unroll
+    for (int u = 0; u < SCAN_PER; ++u) {
+      const int i = u * WG + tid;
+      tile[scan_pad(i)] = i < m ? data[base + i] : 0;
+    }
+    __syncthreads();
+    int v[SCAN_PER], sum = 0;
+#pragma unroll
+    for (int u = 0; u < SCAN_PER; ++u) {
+      v[u] = tile[scan_pad(tid * SCAN_PER + u)];
+      sum += v[u];
+    }
+    int incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int x = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += x;
+    }
+    if (lane == 63) part[wv] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int q = 0; q < NWAVES; ++q) {
+      before += q < wv ? part[q] : 0;
+      total += part[q];
+    }
+    int run = carry + before + incl - sum;
+#pragma unroll
+    for (int u = 0; u < SCAN_PER; ++u) {
+      tile[scan_pad(tid * SCAN_PER + u)] = run;
+      run += v[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < SCAN_PER; ++u) {
+      const int i = u * WG + tid;
+      if (i < m) data[base + i] = tile[scan_pad(i)];
+    }
+    carry += total;
+    __syncthreads();
   }
-  return lo;
+  return carry;
+}
+
+// Edges per block of the split edge pass.
+constexpr int EPB = PU * WG;
+
+// The edge pass over edges [lo, hi) of window W (window-local indices, in
+// batches of PU per thread from lo + tid): index checks, order checks, and
+// where each patch's run of edges starts (fill) and ends (cnt), which gives
+// the counts when the edges turn out to be sorted.
+__device__ __forceinline__ void prep_edge_range(const Params& P, const WinDesc& W, int lo, int hi, bool& bad,
+                                                bool& uns_e, bool& dup_e) {
+  const int M = W.n_patches, N = W.n_frames, E = W.n_edges;
+  const int32_t* kk = P.kk + W.edge_off;
+  const int32_t* jj = P.jj + W.edge_off;
+  int32_t* cnt = P.cnt + W.patch_off;
+  int32_t* fill = P.fill + W.patch_off;
+  for (int e0 = lo + (int)threadIdx.x; e0 < hi; e0 += PU * WG) {
+    int k[PU], j[PU], kp[PU], jp[PU], kn[PU];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int e = e0 + u * WG;
+      const bool in = e < hi;
+      k[u] = in ? kk[e] : 0;
+      j[u] = in ? jj[e] : 0;
+      kp[u] = (in && e > 0) ? kk[e - 1] : -1;
+      jp[u] = (in && e > 0) ? jj[e - 1] : -1;
+      kn[u] = (in && e + 1 < E) ? kk[e + 1] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int e = e0 + u * WG;
+      if (e < hi) {
+        const bool kbad = k[u] < 0 || k[u] >= M;
+        bad |= (kbad || j[u] < 0 || j[u] >= N);
+        uns_e |= (kp[u] > k[u] || (kp[u] == k[u] && jp[u] > j[u]));
+        dup_e |= kp[u] == k[u] && jp[u] == j[u];
+        if (!kbad) {
+          if (kp[u] != k[u]) fill[k[u]] = e;
+          if (kn[u] != k[u]) cnt[k[u]] = e + 1;
+        }
+      }
+    }
+  }
+}
+
+// Split edge pass: block b takes edges [EPB * (b - eb_off), ...) of the window
+// whose blocks contain b, and writes its flags to eflags[b] (bit 0 bad index,
+// bit 1 unsorted, bit 2 duplicate).  Blocks never span windows, so no flag
+// word is shared and none needs clearing.
+__device__ __forceinline__ void wg_prep_edges(const Params& P, int b, int* lds) {
+  int lo = 0, hi = P.counts[0] - 1;   // last window with eb_off <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (P.win[mid].eb_off <= b) lo = mid; else hi = mid - 1;
+  }
+  const WinDesc W = P.win[lo];
+  const int e_lo = EPB * (b - W.eb_off), e_hi = min(W.n_edges, e_lo + EPB);
+  if (threadIdx.x == 0) lds[0] = 0;
+  __syncthreads();
+  bool bad = false, uns_e = false, dup_e = false;
+  prep_edge_range(P, W, e_lo, e_hi, bad, uns_e, dup_e);
+  const int f = (__any(bad) ? 1 : 0) | (__any(uns_e) ? 2 : 0) | (__any(dup_e) ? 4 : 0);
+  if (f && lane_id() == 0) atomicOr(&lds[0], f);
+  __syncthreads();
+  if (threadIdx.x == 0) P.eflags[b] = lds[0];
 }
 
 template <typename T>
-__device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
+__device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds, bool edges_done = false) {
   const WinDesc W = P.win[w];
   const int N = W.n_frames, M = W.n_patches, E = W.n_edges;
   const int tid = threadIdx.x;
@@ -74,6 +192,9 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
   int* flags = lds + WG;
   int* lr = lds + WG + 16;   // [2 * RMAX]
   int* rg = lr + 2 * RMAX;   // [5 * RMAX]
+  int* tile = rg + 5 * RMAX;           // [SCAN_TILE_PAD] scan staging
+  int* wcnt = tile + SCAN_TILE_PAD;    // [NWAVES * RMAX] stable patch ordering
+  int* frun = wcnt + NWAVES * RMAX;    // [RMAX]
 
   if (tid < 16) flags[tid] = 0;
   for (int a = tid; a < N; a += WG) {
@@ -85,10 +206,14 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
     rg[a + 3 * RMAX] = 1 << 30;
     rg[a + 4 * RMAX] = -1;
   }
-  // run ends / run starts of the edges per patch (read when the edges are sorted)
-  for (int k = tid; k < M; k += WG) {
-    cnt[k] = 0;
-    fill[k] = 0;
+  // run ends / run starts of the edges per patch (read when the edges are
+  // sorted); after the split edge pass they hold this call's runs, and stale
+  // values for patches without edges, which the count below recognises
+  if (!edges_done) {
+    for (int k = tid; k < M; k += WG) {
+      cnt[k] = 0;
+      fill[k] = 0;
+    }
   }
   __syncthreads();
 
@@ -114,43 +239,30 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
     }
 #pragma unroll
     for (int u = 0; u < PU; ++u) {
-      if (k0 + u * WG < M) {
+      const int k = k0 + u * WG;
+      if (k < M) {
         bad |= (a[u] < 0 || a[u] >= N);
         uns_p |= ap[u] > a[u];
         nonfin |= !(isfinite_d(x[u]) && isfinite_d(y[u]) && isfinite_d(d[u]));
+        // first position of each source frame, for anchors in frame order
+        // (frames without patches start where the next frame does); the
+        // unsorted path below recomputes them
+        for (int f = max(ap[u] + 1, 0); f <= min(a[u], N); ++f) acnt[f] = k;
+        if (k == M - 1)
+          for (int f = max(a[u] + 1, 0); f <= N; ++f) acnt[f] = M;
       }
     }
   }
   // edges in batches of PU per thread, so that the loads of a batch are in
-  // flight together.  The same pass records where each patch's run of edges
-  // starts (fill) and ends (cnt), which gives the counts when the edges turn
-  // out to be sorted.
-  for (int e0 = tid; e0 < E; e0 += PU * WG) {
-    int k[PU], j[PU], kp[PU], jp[PU], kn[PU];
-#pragma unroll
-    for (int u = 0; u < PU; ++u) {
-      const int e = e0 + u * WG;
-      const bool in = e < E;
-      k[u] = in ? kk[e] : 0;
-      j[u] = in ? jj[e] : 0;
-      kp[u] = (in && e > 0) ? kk[e - 1] : -1;
-      jp[u] = (in && e > 0) ? jj[e - 1] : -1;
-      kn[u] = (in && e + 1 < E) ? kk[e + 1] : -1;
-    }
-#pragma unroll
-    for (int u = 0; u < PU; ++u) {
-      const int e = e0 + u * WG;
-      if (e < E) {
-        const bool kbad = k[u] < 0 || k[u] >= M;
-        bad |= (kbad || j[u] < 0 || j[u] >= N);
-        uns_e |= (kp[u] > k[u] || (kp[u] == k[u] && jp[u] > j[u]));
-        dup_e |= kp[u] == k[u] && jp[u] == j[u];
-        if (!kbad) {
-          if (kp[u] != k[u]) fill[k[u]] = e;
-          if (kn[u] != k[u]) cnt[k[u]] = e + 1;
-        }
-      }
-    }
+  // flight together (or the flags of the split edge pass)
+  if (!edges_done) {
+    prep_edge_range(P, W, 0, E, bad, uns_e, dup_e);
+  } else {
+    int f = 0;
+    for (int b = tid; b < W.eb_n; b += WG) f |= P.eflags[W.eb_off + b];
+    bad |= (f & 1) != 0;
+    uns_e |= (f & 2) != 0;
+    dup_e |= (f & 4) != 0;
   }
   if (__any(bad) && lane_id() == 0) atomicOr(&flags[0], 1);
   if (__any(uns_e) && lane_id() == 0) atomicOr(&flags[1], 1);
@@ -178,16 +290,52 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
     __syncthreads();
   }
   int mx = 0;
-  for (int k = tid; k < M; k += WG) {
-    // sorted edges: the run end minus the run start (0 for a patch without edges)
-    const int c = unsorted_e ? cnt[k] : cnt[k] - fill[k];
-    cnt[k] = c;
-    ptr[k] = c;
-    mx = max(mx, c);
+  for (int k0 = tid; k0 < M; k0 += PU * WG) {
+    int f0[PU], ce[PU], c[PU];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int k = k0 + u * WG;
+      const bool in = k < M;
+      f0[u] = (in && !unsorted_e) ? fill[k] : 0;
+      ce[u] = in ? cnt[k] : 0;
+    }
+    if (unsorted_e) {
+#pragma unroll
+      for (int u = 0; u < PU; ++u) c[u] = ce[u];
+    } else if (edges_done) {
+      // after the split pass a patch has a run of this call exactly when its
+      // recorded start is an edge of the patch with no edge of the patch
+      // before it (no edge names a patch without edges)
+      int ka[PU], kb[PU];
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        const bool ok = k0 + u * WG < M && f0[u] >= 0 && f0[u] < E;
+        ka[u] = ok ? kk[f0[u]] : -1;
+        kb[u] = (ok && f0[u] > 0) ? kk[f0[u] - 1] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < PU; ++u) {
+        const int k = k0 + u * WG;
+        c[u] = (ka[u] == k && kb[u] != k) ? ce[u] - f0[u] : 0;
+      }
+    } else {
+      // sorted edges: the run end minus the run start (0 for a patch without edges)
+#pragma unroll
+      for (int u = 0; u < PU; ++u) c[u] = ce[u] - f0[u];
+    }
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int k = k0 + u * WG;
+      if (k < M) {
+        cnt[k] = c[u];
+        ptr[k] = c[u];
+        mx = max(mx, c[u]);
+      }
+    }
   }
   atomicMax(&flags[3], mx);
   __syncthreads();
-  wg_exclusive_scan(ptr, M, lds);
+  wg_scan_tiled(ptr, M, lds, tile);
   if (unsorted_e) {
     for (int e = tid; e < E; e += WG) {
       const int k = kk[e];
@@ -217,36 +365,70 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
 
   // ---- positions: patches by (source frame, index)
   if (!unsorted_p) {
-    for (int a = tid; a <= N; a += WG) acnt[a] = a == N ? M : lower_bound_i32(anc, M, a);
+    if (M == 0)
+      for (int a = tid; a <= N; a += WG) acnt[a] = 0;
     for (int k = tid; k < M; k += WG) pk[k] = k;
   } else {
+    // stable counting sort by source frame: frame sizes, their prefix sum,
+    // then tiles of WG patches in index order; inside a tile a patch's rank
+    // among the earlier patches of its frame comes from the ballots of its
+    // wave and the per-frame counts of the earlier waves
     for (int a = tid; a <= N; a += WG) acnt[a] = 0;
-    for (int a = tid; a < N; a += WG) afill[a] = 0;
+    for (int a = tid; a < RMAX; a += WG) frun[a] = 0;
     __syncthreads();
     for (int k = tid; k < M; k += WG) atomicAdd(&acnt[anc[k]], 1);
     __syncthreads();
-    wg_exclusive_scan(acnt, N + 1, lds);
-    for (int k = tid; k < M; k += WG) {
-      const int a = anc[k];
-      pk[acnt[a] + atomicAdd(&afill[a], 1)] = k;
-    }
-    __syncthreads();
-    for (int a = tid; a < N; a += WG) {
-      const int b = acnt[a], n = acnt[a + 1] - b;
-      for (int x = 1; x < n; ++x) {
-        const int v = pk[b + x];
-        int y = x - 1;
-        while (y >= 0 && pk[b + y] > v) { pk[b + y + 1] = pk[b + y]; --y; }
-        pk[b + y + 1] = v;
+    wg_scan_tiled(acnt, N + 1, lds, tile);
+    const int lane = tid & 63, wv = tid >> 6;
+    const uint64_t lt = (1ull << lane) - 1;
+    for (int base = 0; base < M; base += WG) {
+      const int k = base + tid;
+      const int a = k < M ? anc[k] : -1;
+      for (int q = tid; q < NWAVES * RMAX; q += WG) wcnt[q] = 0;
+      __syncthreads();
+      uint64_t left = __ballot(k < M);
+      int rank = 0;
+      while (left) {
+        const int lead = __ffsll((long long)left) - 1;
+        const int a0 = __shfl(a, lead, 64);
+        const uint64_t same = __ballot(a == a0) & left;
+        if (a == a0) rank = __popcll(same & lt);
+        if (lane == lead) wcnt[wv * RMAX + a0] = __popcll(same);
+        left &= ~same;
       }
+      __syncthreads();
+      if (k < M) {
+        int before = frun[a];
+        for (int q = 0; q < wv; ++q) before += wcnt[q * RMAX + a];
+        pk[acnt[a] + before + rank] = k;
+      }
+      __syncthreads();
+      for (int a2 = tid; a2 < N; a2 += WG) {
+        int t = 0;
+        for (int q = 0; q < NWAVES; ++q) t += wcnt[q * RMAX + a2];
+        frun[a2] += t;
+      }
+      __syncthreads();
     }
   }
   __syncthreads();
 
   // ---- edge order offsets per position
-  for (int q = tid; q < M; q += WG) est[q] = cnt[pk[q]];
+  for (int q0 = tid; q0 < M; q0 += PU * WG) {
+    int k[PU], c[PU];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int q = q0 + u * WG;
+      k[u] = q < M ? (unsorted_p ? pk[q] : q) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < PU; ++u) c[u] = q0 + u * WG < M ? cnt[k[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < PU; ++u)
+      if (q0 + u * WG < M) est[q0 + u * WG] = c[u];
+  }
   __syncthreads();
-  wg_exclusive_scan(est, M, lds);
+  wg_scan_tiled(est, M, lds, tile);
   if (tid == 0) est[M] = E;
   // per-position pixel rays, initial depths, frame ranges
   T* pxy = (T*)P.pxy + 2 * W.patch_off;
@@ -343,9 +525,11 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
   // sub-batches per source frame
   const int maxdeg = flags[3];
   const int SBw = sb_width(seg_width(maxdeg));
+  // wave 0, one frame per lane (at most 64): sub-batch counts and their
+  // prefix sum (also kept in LDS: the scan scratch, free again here); then
+  // one thread per sub-batch writes its descriptor
+  int* sbl = lds;   // [RMAX + 1] first sub-batch of each frame
   if (tid < 64) {
-    // wave 0, one frame per lane (at most 64): sub-batch counts, their prefix
-    // sum, and the frame's descriptors
     const int a = tid;
     const int p0 = a < N ? acnt[a] : 0, p1 = a < N ? acnt[a + 1] : 0;
     const int c = (p1 - p0 + SBw - 1) / SBw;
@@ -356,18 +540,31 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds) {
       if (tid >= off) incl += v;
     }
     if (a < N) {
-      int s = incl - c;
-      sbs[a] = s;
-      if (a == N - 1) sbs[N] = incl;
+      sbs[a] = incl - c;
+      sbl[a] = incl - c;
+      if (a == N - 1) {
+        sbs[N] = incl;
+        sbl[N] = incl;
+      }
       ar[2 * a] = lr[2 * a];
       ar[2 * a + 1] = lr[2 * a + 1];
-      const int flag = (lr[2 * RMAX + a] ? SB_REGULAR : 0) | (a << 8);
-      for (int q = p0; q < p1; q += SBw, ++s) {
-        const int n = min(SBw, p1 - q);
-        sbd[s] = make_int4(q, flag | n, est[q], est[q + n]);
-      }
     }
-    if (N == 0 && a == 0) sbs[0] = 0;
+    if (N == 0 && a == 0) {
+      sbs[0] = 0;
+      sbl[0] = 0;
+    }
+  }
+  __syncthreads();
+  const int nsb = sbl[N];
+  for (int s = tid; s < nsb; s += WG) {
+    int a = 0;   // frame of sub-batch s: the last frame whose first sub-batch is <= s
+    for (int step = 32; step > 0; step >>= 1)
+      if (a + step < N && sbl[a + step] <= s) a += step;
+    const int p1 = acnt[a + 1];
+    const int q = acnt[a] + (s - sbl[a]) * SBw;
+    const int n = min(SBw, p1 - q);
+    const int flag = (lr[2 * RMAX + a] ? SB_REGULAR : 0) | (a << 8);
+    sbd[s] = make_int4(q, flag | n, est[q], est[q + n]);
   }
   __syncthreads();
   if (tid == 0) {

@@ -154,3 +154,38 @@ def test_irregular_graph_method_scale(precision):
     print(precision, "irregular 22x96:", f"{dc:.2e} m {drot:.2e} deg depth {dd:.2e}")
     tol = FP64_TOL if precision == "fp64" else (1e-4, 1e-2, 1e-3)
     assert dc < tol[0] and drot < tol[1] and dd < tol[2], (dc, drot, dd)
+
+
+@pytest.mark.parametrize("shape,precision", [((22, 96, 13), "fp64"), ((22, 96, 13), "fp32"),
+                                             ((64, 256, 16), "fp32")])
+def test_interleaved_patches_equal_frame_ordered_input(shape, precision):
+    """Patches of different source frames interleaved at random, each frame's
+    patches keeping their relative order, edges left in their input order
+    (so neither patches nor edges are grouped any more).  The preparation
+    orders positions by (source frame, patch index) and each patch's edges by
+    (target frame, input index), which is the order of the frame-ordered
+    input: the solve must be bitwise the same.  Exercises the stable ordering
+    of unsorted patches at up to 256 patches per frame and the gathered edge
+    layout."""
+    need_gpu()
+    F, ppf, r = shape
+    w = synth.make_window(F, ppf, r, seed=[41, F], outlier_frac=0.1, fp32=True)
+    rng = np.random.default_rng(5)
+    labels = rng.permutation(np.asarray(w.anchor))
+    by_frame = [list(np.nonzero(np.asarray(w.anchor) == a)[0]) for a in range(F)]
+    nxt = np.zeros(F, np.int64)
+    order = np.empty(w.n_patches, np.int64)          # new patch i = old patch order[i]
+    for i, a in enumerate(labels):
+        order[i] = by_frame[a][nxt[a]]
+        nxt[a] += 1
+    inv = np.argsort(order)
+    u = w.copy()
+    u.patches, u.anchor = w.patches[order].copy(), w.anchor[order].copy()
+    u.depth_gt = w.depth_gt[order].copy()
+    u.kk = inv[w.kk].astype(np.int32)
+    assert np.any(np.diff(u.anchor) < 0) and np.any(np.diff(u.kk) < 0)
+    (a_,), sa = solve_gpu([w], precision, "split")
+    (b_,), sb = solve_gpu([u], precision, "split")
+    assert sa[0] == 0 and sb[0] == 0
+    assert np.array_equal(a_[0], b_[0])
+    assert np.array_equal(a_[1][order], b_[1])
