@@ -74,9 +74,8 @@ __host__ __device__ inline int upd_groups(int n, int j) { return (upd_tiles(n, j
 __host__ __device__ constexpr int chol_panel_lds_bytes(int n) {
   return 64 + CB * PLD * 8 + 64 * 4 + ((n + 1 + 15) / 16) * 16 * CLD * 8;
 }
-// LDS of the back substitution: flags, the solution, the running right-hand
-// side, the reciprocal diagonal, two staged 16-row blocks of L.
-__host__ __device__ constexpr int chol_big_lds_bytes(int n) { return 64 + 3 * (n + 8) * 8 + 2 * CB * (n + 1) * 8; }
+// LDS of the back substitution: flags, the solution, two blocks of it.
+__host__ __device__ constexpr int chol_big_lds_bytes(int n) { return 64 + (n + 8) * 8 + 2 * CB * 8; }
 static_assert((NBIG_MAX + 1 + 15) / 16 <= 32, "row-block flags of a sub-block hold 32 entries");
 static_assert(chol_panel_lds_bytes(NBIG_MAX) <= 160 * 1024 && chol_big_lds_bytes(NBIG_MAX) <= 160 * 1024,
               "the largest reduced system fits the LDS of a workgroup");
@@ -375,67 +374,72 @@ __device__ __forceinline__ void wg_chol_panel(const Params& P, int w, int j, int
   if (wv == 0 && lane == 0) *ax.bad = (j == 0 ? 0 : *ax.bad) | bad;
 }
 
-// L^T x = y, L in A (lower, ld), y = row n of A; x into LDS `x` (n entries).
-// By 16-row blocks from the bottom: the rows of block b (columns up to its
-// diagonal) are staged in LDS while block b+1 is solved, so each step waits
-// on LDS only.  buf: 2 x 16 rows of n + 1 doubles; dv: n doubles.
+// One 16-row block b of the back substitution L^T x = y (rows b0 .. b0+bs-1).
+// Thread t < n holds entry t of the running right-hand side in `z` and, in
+// `cur`, its column of the block's rows: cur[s] = L[b0 + s][t] for t <= b0 + s.
+// The wave holding entries b0 .. b0+15 (one wave: b0 is a multiple of 16)
+// solves the block's triangle from its registers, lane b0 + r taking x_r;
+// then every thread above the block subtracts the block's products.  `nxt`
+// receives the rows of block b - 2 (loads in flight across the step).
+__device__ __forceinline__ void backsolve_block(const double* A, int ld, int n, int b, double& z, double dv,
+                                                double (&cur)[CB], double (&nxt)[CB], double* x, double* xl) {
+  const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  {
+    const int bp = b - 2, p0 = bp * CB, ps = min(CB, n - p0);
+#pragma unroll
+    for (int s = 0; s < CB; ++s)
+      nxt[s] = (bp >= 0 && s < ps && tid <= p0 + s && tid < n) ? A[(int64_t)(p0 + s) * ld + tid] : 0.0;
+  }
+  const int b0 = b * CB, bs = min(CB, n - b0);
+  double* xb = xl + (b & 1) * CB;
+  if (wv == b0 / 64) {
+    const int lb = b0 & 63;
+#pragma unroll
+    for (int s = CB - 1; s >= 0; --s) {
+      if (s < bs) {
+        const double xs = readlane_f64(z, lb + s) * readlane_f64(dv, lb + s);
+        if (lane == lb + s) z = xs;
+        else if (lane >= lb && lane < lb + s) z -= cur[s] * xs;
+      }
+    }
+    if (lane >= lb && lane < lb + bs) {
+      xb[lane - lb] = z;
+      x[b0 + lane - lb] = z;
+    }
+  }
+  __syncthreads();
+  if (tid < b0) {
+#pragma unroll
+    for (int s = 0; s < CB; ++s)
+      if (s < bs) z -= cur[s] * xb[s];
+  }
+}
+
+// L^T x = y, L in A (lower, ld), y = row n of A, 1/L_ii in dinv; x into LDS
+// `x` (n entries); xl: 2 x 16 doubles of LDS.  By 16-row blocks from the
+// bottom (backsolve_block), the rows of each block fetched two blocks ahead;
+// the block's values are double-buffered in xl, so each block needs one
+// barrier.
 static_assert(NBIG_MAX < WG, "a row of the reduced system is staged one entry per thread");
 __device__ __forceinline__ void wg_backsolve_big(const double* A, int ld, int n, const double* dinv, double* x,
-                                        double* z, double* dv, double* buf) {
-  const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
-  const int ldb = n + 1;
-  double pf[CB];
-  // block b's rows b0 .. b0+bs-1, columns 0 .. b0+bs-1 (thread = column),
-  // into registers
-  auto fetch = [&](int b) {
-    const int b0 = b * CB, bs = min(CB, n - b0), cols = b0 + bs;
-#pragma unroll
-    for (int r = 0; r < CB; ++r) pf[r] = (r < bs && tid < cols) ? A[(int64_t)(b0 + r) * ld + tid] : 0.0;
-  };
-  auto stash = [&](int b) {
-    const int b0 = b * CB, bs = min(CB, n - b0), cols = b0 + bs;
-    double* dst = buf + (b & 1) * CB * ldb;
-#pragma unroll
-    for (int r = 0; r < CB; ++r)
-      if (r < bs && tid < cols) dst[r * ldb + tid] = pf[r];
-  };
+                                        double* xl) {
+  const int tid = threadIdx.x;
+  double z = tid < n ? A[(int64_t)n * ld + tid] : 0.0;
+  const double dv = tid < n ? dinv[tid] : 0.0;
+  double c0[CB], c1[CB], c2[CB];
   const int nb = (n + CB - 1) / CB;
-  fetch(nb - 1);
-  for (int j = tid; j < n; j += WG) {
-    z[j] = A[(int64_t)n * ld + j];
-    dv[j] = dinv[j];
+#pragma unroll
+  for (int s = 0; s < CB; ++s) {
+    const int b0 = (nb - 1) * CB, q0 = (nb - 2) * CB;
+    c0[s] = (s < n - b0 && tid <= b0 + s && tid < n) ? A[(int64_t)(b0 + s) * ld + tid] : 0.0;
+    c1[s] = (nb >= 2 && tid <= q0 + s) ? A[(int64_t)(q0 + s) * ld + tid] : 0.0;
   }
-  stash(nb - 1);
+  for (int b = nb - 1; b >= 0; b -= 3) {
+    backsolve_block(A, ld, n, b, z, dv, c0, c2, x, xl);
+    if (b - 1 >= 0) backsolve_block(A, ld, n, b - 1, z, dv, c1, c0, x, xl);
+    if (b - 2 >= 0) backsolve_block(A, ld, n, b - 2, z, dv, c2, c1, x, xl);
+  }
   __syncthreads();
-  for (int b = nb - 1; b >= 0; --b) {
-    const int b0 = b * CB, bs = min(CB, n - b0);
-    const double* L = buf + (b & 1) * CB * ldb;
-    if (b > 0) fetch(b - 1);
-    if (wv == 0) {
-      // lane t holds column t of the diagonal block and z_t
-      double Lc[CB];
-#pragma unroll
-      for (int s = 0; s < CB; ++s) Lc[s] = (lane < bs && s < bs && s >= lane) ? L[s * ldb + b0 + lane] : 0.0;
-      double zz = lane < bs ? z[b0 + lane] : 0.0;
-#pragma unroll
-      for (int s = CB - 1; s >= 0; --s) {
-        if (s < bs) {
-          const double xs = readlane_f64(zz, s) * dv[b0 + s];
-          if (lane == s) zz = xs;
-          else if (lane < s) zz -= Lc[s] * xs;
-        }
-      }
-      if (lane < bs) x[b0 + lane] = zz;
-    }
-    __syncthreads();
-    for (int j = tid; j < b0; j += WG) {
-      double v = z[j];
-      for (int s = 0; s < bs; ++s) v -= L[s * ldb + j] * x[b0 + s];
-      z[j] = v;
-    }
-    if (b > 0) stash(b - 1);
-    __syncthreads();
-  }
 }
 
 // Back substitution and retraction of a window with n > 126 (the system was
@@ -458,18 +462,13 @@ __device__ __forceinline__ void wg_chol_big(const Params& P, int w, int iter, ch
   const int ld = P.ld_big;
   double* A = P.s_big + (int64_t)w * ld * ld;
   double* x = (double*)(smem + 64);
-  double* z = x + n + 8;
-  double* dv = z + n + 8;
+  double* xl = x + n + 8;
   const BigAux ax = big_aux(P, w);
-  wg_backsolve_big(A, ld, n, ax.dinv, x, z, dv, dv + n + 8);
-  if (tid == 0) {
-    int bad = *ax.bad;
-    for (int i = 0; i < n; ++i)
-      if (!isfinite_d(x[i])) bad |= W_NONFINITE;
-    misc[2] = bad;
-    if (bad) atomicOr(&P.status[w], bad);
-  }
+  if (tid == 0) misc[2] = *ax.bad;
+  wg_backsolve_big(A, ld, n, ax.dinv, x, xl);
+  if (tid < n && !isfinite_d(x[tid])) atomicOr(&misc[2], W_NONFINITE);
   __syncthreads();
+  if (tid == 0 && misc[2]) atomicOr(&P.status[w], misc[2]);
   const int bad = misc[2];
   for (int i = tid; i < 6 * N; i += WG) {
     const int a = i / 6;
