@@ -101,8 +101,17 @@ __global__ void __launch_bounds__(WG) k_adj_init(Params P) {
 template <typename T>
 __global__ void __launch_bounds__(WG) k_chol_adj(Params P, int iter) {
   extern __shared__ __align__(16) char smem[];
+  const int w = blockIdx.x;
+  if (w >= P.counts[0]) return;
+  if (6 * (P.win[w].n_frames - P.win[w].n_fixed) > NCHOL_MAX) return;   // k_chol_adj_big
+  wg_chol_adj<T>(P, w, iter, smem);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_chol_adj_big(Params P, int iter) {
+  extern __shared__ __align__(16) char smem[];
   if ((int)blockIdx.x >= P.counts[0]) return;
-  wg_chol_adj<T>(P, blockIdx.x, iter, smem);
+  wg_chol_adj_big<T>(P, blockIdx.x, iter, smem);
 }
 
 template <typename T>
@@ -283,6 +292,7 @@ int set_kernel_attrs() {
   if (hipFuncSetAttribute((const void*)k_backsub<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_debug_gather<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_chol_adj<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
+  if (hipFuncSetAttribute((const void*)k_chol_adj_big<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_edge_adj<T>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   return 0;
 }
@@ -730,18 +740,34 @@ int launch_backward(ba_handle* h, const ba_problem* p, const Plan& pl, const dou
   const int Rcap = pl.Rcap, esz = (int)sizeof(T);
   const int asm_lds = asm_layout(Rcap, esz, pl.maxt).total;
   const int bs_lds = backsub_lds_bytes(Rcap, esz);
-  const int chol_lds = chol_lds_bytes(pl.nmax);
-  const int chol_adj_lds = chol_lds + 2 * 8 * pl.nmax + 64;
+  const int nsmall = std::min(pl.nmax, NCHOL_MAX);   // windows above take the panel path
+  const int chol_lds = chol_lds_bytes(nsmall);
+  const int chol_adj_lds = chol_lds + 2 * 8 * nsmall + 64;
   const int adj_lds = edge_adj_lds_bytes(Rcap, esz);
   const int K = P.iterations;
   hipLaunchKernelGGL(k_prep<T>, dim3(pl.W), dim3(WG), 0, s, P, 0);
   HIPCHK(h, hipGetLastError());
+  // windows with n > 126: the system gathered into device memory and
+  // factorised by panels (the forward path's kernels)
+  auto big_factor = [&](const Params& Q) {
+    const int tiles = gather_tiles(pl.nmax);
+    hipLaunchKernelGGL(k_gather_big, dim3(pl.W * tiles), dim3(WG), 0, s, Q, tiles);
+    for (int j = 0; PW * j < pl.nmax; ++j) {
+      const int groups = upd_groups(pl.nmax, j);
+      hipLaunchKernelGGL(k_chol_panel, dim3(pl.W * (1 + groups)), dim3(WG), chol_panel_lds_bytes(pl.nmax), s, Q, j,
+                         groups);
+    }
+  };
   // recompute the iterates x_1 .. x_{K-1}
   for (int it = 0; it + 1 < K; ++it) {
     if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<T, 4>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
     else if (pl.maxt == 5) hipLaunchKernelGGL((k_assemble<T, 5>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
     else hipLaunchKernelGGL((k_assemble<T, 8>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
     hipLaunchKernelGGL(k_chol<T>, dim3(pl.W), dim3(WG), chol_lds, s, P, it);
+    if (pl.big) {
+      big_factor(P);
+      hipLaunchKernelGGL(k_chol_big<T>, dim3(pl.W), dim3(WG), chol_big_lds_bytes(pl.nmax), s, P, it);
+    }
     hipLaunchKernelGGL(k_backsub<T>, dim3(pl.C), dim3(WG), bs_lds, s, P, it, Rcap, 1);
     HIPCHK(h, hipGetLastError());
   }
@@ -754,6 +780,10 @@ int launch_backward(ba_handle* h, const ba_problem* p, const Plan& pl, const dou
     else if (pl.maxt == 5) hipLaunchKernelGGL((k_assemble<T, 5>), dim3(pl.C), dim3(WG), asm_lds, s, PA, it, Rcap);
     else hipLaunchKernelGGL((k_assemble<T, 8>), dim3(pl.C), dim3(WG), asm_lds, s, PA, it, Rcap);
     hipLaunchKernelGGL(k_chol_adj<T>, dim3(pl.W), dim3(WG), chol_adj_lds, s, PA, it);
+    if (pl.big) {
+      big_factor(PA);
+      hipLaunchKernelGGL(k_chol_adj_big<T>, dim3(pl.W), dim3(WG), chol_adj_big_lds_bytes(pl.nmax), s, PA, it);
+    }
     hipLaunchKernelGGL(k_edge_adj<T>, dim3(pl.C), dim3(WG), adj_lds, s, PA, it, Rcap);
     hipLaunchKernelGGL(k_frame_adj, dim3(pl.W), dim3(WG), 0, s, PA);
     HIPCHK(h, hipGetLastError());
@@ -985,7 +1015,6 @@ int ba_backward(ba_handle* h, const ba_problem* p, const double* grad_poses,
   h->last_W = pl.W;
   if (pl.W == 0) return BA_OK;
   if (h->cfg.iterations < 1) return fail(h, BA_E_STATE, "ba_backward needs at least one iteration");
-  if (pl.big) return fail(h, BA_E_CAPACITY, "ba_backward holds at most 21 free frames per window");
   if ((pl.F > 0 && !grad_poses) || (pl.Pn > 0 && !grad_depth) ||
       (pl.E > 0 && (!grad_targets || !grad_weights)))
     return fail(h, BA_E_INVAL, "gradient pointer is NULL");

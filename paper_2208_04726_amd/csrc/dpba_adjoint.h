@@ -21,6 +21,7 @@
 // call; nothing is kept from the forward call.
 #pragma once
 #include "dpba_solve.h"
+#include "dpba_chol_big.h"
 
 namespace dpba {
 
@@ -196,6 +197,73 @@ __device__ __forceinline__ void wg_chol_adj(const Params& P, int w, int it, char
     if (a < nfix) xid[i] = 0.0;
   }
 }
+
+// The reduced solves of wg_chol_adj for a window with n > 126: the system and
+// both right-hand sides were gathered by wg_gather_big (adjoint mode) and
+// factorised by the panel launches, which also carried out L y = -s.  Here:
+// dxi from L^T dxi = y; the second right-hand side completed with
+// J_l(dxi)^T xi_bar per free frame; q_xi from L z = rhs, L^T q_xi = z.
+template <typename T>
+__device__ __forceinline__ void wg_chol_adj_big(const Params& P, int w, int it, char* smem) {
+  const WinDesc W = P.win[w];
+  const int tid = threadIdx.x;
+  int* misc = (int*)smem;
+  const int N = W.n_frames, nfix = W.n_fixed;
+  const int n = 6 * (N - nfix);
+  if (n <= NCHOL_MAX) return;   // wg_chol_adj
+  const int st = wg_bcast_status(P.status, w, misc);
+  double* dxi = P.dxi + 6 * W.frame_off;
+  double* qxi = P.qxi + 6 * W.frame_off;
+  double* xid = P.xid + 6 * W.frame_off;
+  double* xib = P.xib + 6 * W.frame_off;
+  if (st != 0) {
+    for (int i = tid; i < 6 * N; i += WG) { dxi[i] = 0.0; qxi[i] = 0.0; xid[i] = 0.0; }
+    return;
+  }
+  const double* poses = state_poses<T>(P, W, it);
+  const int ld = P.ld_big;
+  const double* A = P.s_big + (int64_t)w * ld * ld;
+  const BigAux ax = big_aux(P, w);
+  double* x = (double*)(smem + 64);
+  double* xl = x + n + 8;
+  double* b2 = xl + 2 * CB;
+  double* x2 = b2 + n + 8;
+  if (tid == 0) misc[2] = *ax.bad;
+  wg_backsolve_big(A, ld, n, ax.dinv, x, xl);
+  for (int i = tid; i < n; i += WG) b2[i] = ax.b2[i];
+  __syncthreads();
+  for (int a = nfix + tid; a < N; a += WG) {
+    const double* dx = x + 6 * (a - nfix);
+    double xin[6];
+    if (it == P.iterations - 1) {
+      double pn[7];
+      retract_left(dx, poses + 7 * a, pn);
+      pose7_cotangent(pn, P.grad_poses + 7 * (W.frame_off + a), xin);
+    } else {
+      for (int m = 0; m < 6; ++m) xin[m] = xib[6 * a + m];
+    }
+    double dbarx[6], dir[6];
+    left_jacobian_T(dx, xin, dbarx);
+    adjoint_exp_T(dx, xin, dir);
+    for (int m = 0; m < 6; ++m) {
+      b2[6 * (a - nfix) + m] += dbarx[m];
+      xid[6 * a + m] = dir[m];
+    }
+  }
+  __syncthreads();
+  wg_forwardsolve_big(A, ld, n, ax.dinv, b2, b2, xl);
+  wg_backsolve_big(A, ld, n, ax.dinv, x2, xl, b2);
+  if (tid < n && !(isfinite_d(x[tid]) && isfinite_d(x2[tid]))) atomicOr(&misc[2], W_NONFINITE);
+  __syncthreads();
+  if (tid == 0 && misc[2]) atomicOr(&P.status[w], misc[2]);
+  for (int i = tid; i < 6 * N; i += WG) {
+    const int a = i / 6;
+    dxi[i] = a >= nfix ? x[6 * (a - nfix) + i % 6] : 0.0;
+    qxi[i] = a >= nfix ? x2[6 * (a - nfix) + i % 6] : 0.0;
+    if (a < nfix) xid[i] = 0.0;
+  }
+}
+__host__ __device__ constexpr int chol_adj_big_lds_bytes(int n) { return 64 + 3 * (n + 8) * 8 + 2 * CB * 8; }
 
 // Second-order term of one (u, v) pair: gradient of u^T J(x) v with respect
 // to the edge's left perturbation eps = eps_j - Ad(T_ji) eps_i (g[0..5]) and

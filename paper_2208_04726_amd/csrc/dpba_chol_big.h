@@ -39,19 +39,21 @@ constexpr int PW = 2 * CB;     // panel width
 constexpr int CLD = PW + 1;    // LDS row stride of a panel's column block
 
 // Per-window side data of the factorisation (FP64 words, after the window's
-// slot): the reciprocal diagonal of L (ld words), then as ints, for the last
-// two panels (panel & 1), the nonzero flags of the 16-row blocks below each
+// slot): the reciprocal diagonal of L (ld words), the adjoint's second
+// right-hand side as gathered (ld words), then as ints, for the last two
+// panels (panel & 1), the nonzero flags of the 16-row blocks below each
 // sub-block (32 + 32), and the pivot flags of the factorisation (one int).
-__host__ __device__ inline int big_aux_stride(int ld) { return ld + 72; }
+__host__ __device__ inline int big_aux_stride(int ld) { return 2 * ld + 72; }
 struct BigAux {
   double* dinv;
+  double* b2;
   int* nzb;    // panel p: nzb + 64 * (p & 1), first sub-block, then + 32 the second
   int* bad;
 };
 __device__ __forceinline__ BigAux big_aux(const Params& P, int w) {
   double* base = P.big_aux + (int64_t)w * big_aux_stride(P.ld_big);
-  int* ints = (int*)(base + P.ld_big);
-  return {base, ints, ints + 128};
+  int* ints = (int*)(base + 2 * P.ld_big);
+  return {base, base + P.ld_big, ints, ints + 128};
 }
 
 constexpr int TU_PANEL = 4;   // row tiles per wave in flight, panel workgroup
@@ -82,7 +84,9 @@ static_assert(chol_panel_lds_bytes(NBIG_MAX) <= 160 * 1024 && chol_big_lds_bytes
 
 // One 64 x 64 tile of the augmented system of window w, summed from the chunk
 // partials in chunk order (the order of the small-window gather):
-// rows < n hold S + lambda I (lower triangle), row n holds -s.
+// rows < n hold S + lambda I (lower triangle), row n holds -s.  In the
+// adjoint (P.adjoint) the tiles of row n also sum the partials' second
+// right-hand side (the depth-cotangent column) into the side data.
 __device__ __forceinline__ void wg_gather_big(const Params& P, int w, int tile) {
   const WinDesc W = P.win[w];
   const int nfix = W.n_fixed;
@@ -95,7 +99,7 @@ __device__ __forceinline__ void wg_gather_big(const Params& P, int w, int tile) 
   const int ld = P.ld_big;
   double* A = P.s_big + (int64_t)w * ld * ld;
   constexpr int EPT = GT * GT / WG;   // elements per thread
-  double v[EPT];
+  double v[EPT], v2[EPT];
   int rr[EPT], cc_[EPT];
 #pragma unroll
   for (int u = 0; u < EPT; ++u) {
@@ -103,7 +107,9 @@ __device__ __forceinline__ void wg_gather_big(const Params& P, int w, int tile) 
     rr[u] = GT * bi + e / GT;
     cc_[u] = GT * bj + e % GT;
     v[u] = 0.0;
+    v2[u] = 0.0;
   }
+  const bool adj = P.adjoint != 0;
   const int r_lo = GT * bi, r_hi = min(GT * bi + GT - 1, n);
   const int c_lo = GT * bj, c_hi = min(GT * bj + GT - 1, n - 1);
   // chunks in order; a chunk whose columns miss the tile, or whose rows miss
@@ -116,24 +122,34 @@ __device__ __forceinline__ void wg_gather_big(const Params& P, int w, int tile) 
     if (c_hi < off || c_lo >= off + Dc) continue;
     if (!(r_hi >= off && r_lo < off + Dc) && !(r_lo <= n && n <= r_hi)) continue;
     const double* part = P.partial + W.part_off + (int64_t)cc * W.part_stride;
-    double a[EPT];
+    double a[EPT], a2[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
       const int r = rr[u], c = cc_[u];
       a[u] = 0.0;
+      a2[u] = 0.0;
       if (r <= n && c <= r && c < n && c >= off && c < off + Dc) {
-        if (r == n) a[u] = part[Dc * Dc + (c - off)];
-        else if (r < off + Dc) a[u] = part[(r - off) * Dc + (c - off)];
+        if (r == n) {
+          a[u] = part[Dc * Dc + (c - off)];
+          if (adj) a2[u] = part[Dc * Dc + Dc + (c - off)];
+        } else if (r < off + Dc) {
+          a[u] = part[(r - off) * Dc + (c - off)];
+        }
       }
     }
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) v[u] += a[u];
+    for (int u = 0; u < EPT; ++u) {
+      v[u] += a[u];
+      v2[u] += a2[u];
+    }
   }
+  double* b2 = big_aux(P, w).b2;
 #pragma unroll
   for (int u = 0; u < EPT; ++u) {
     const int r = rr[u], c = cc_[u];
     if (r > n || c > r || c >= n) continue;
     A[(int64_t)r * ld + c] = (r == n) ? -v[u] : (r == c ? v[u] + P.lambda : v[u]);
+    if (adj && r == n) b2[c] = v2[u];
   }
 }
 
@@ -415,16 +431,16 @@ __device__ __forceinline__ void backsolve_block(const double* A, int ld, int n, 
   }
 }
 
-// L^T x = y, L in A (lower, ld), y = row n of A, 1/L_ii in dinv; x into LDS
-// `x` (n entries); xl: 2 x 16 doubles of LDS.  By 16-row blocks from the
+// L^T x = y, L in A (lower, ld), y = row n of A (or y0 in LDS), 1/L_ii in
+// dinv; x into LDS `x` (n entries); xl: 2 x 16 doubles of LDS.  By 16-row blocks from the
 // bottom (backsolve_block), the rows of each block fetched two blocks ahead;
 // the block's values are double-buffered in xl, so each block needs one
 // barrier.
 static_assert(NBIG_MAX < WG, "a row of the reduced system is staged one entry per thread");
 __device__ __forceinline__ void wg_backsolve_big(const double* A, int ld, int n, const double* dinv, double* x,
-                                        double* xl) {
+                                        double* xl, const double* y0 = nullptr) {
   const int tid = threadIdx.x;
-  double z = tid < n ? A[(int64_t)n * ld + tid] : 0.0;
+  double z = tid < n ? (y0 ? y0[tid] : A[(int64_t)n * ld + tid]) : 0.0;
   const double dv = tid < n ? dinv[tid] : 0.0;
   double c0[CB], c1[CB], c2[CB];
   const int nb = (n + CB - 1) / CB;
@@ -438,6 +454,70 @@ __device__ __forceinline__ void wg_backsolve_big(const double* A, int ld, int n,
     backsolve_block(A, ld, n, b, z, dv, c0, c2, x, xl);
     if (b - 1 >= 0) backsolve_block(A, ld, n, b - 1, z, dv, c1, c0, x, xl);
     if (b - 2 >= 0) backsolve_block(A, ld, n, b - 2, z, dv, c2, c1, x, xl);
+  }
+  __syncthreads();
+}
+
+// One 16-row block b of the forward substitution L y = r: thread t < n
+// holds entry t of the running right-hand side in `z` and, in `cur`, its
+// row's entries in the block's columns: cur[s] = L[t][b0 + s] for
+// b0 + s <= t.  The wave holding entries b0 .. b0+15 solves the block's
+// triangle from its registers; then every thread below the block subtracts
+// the block's products.  `nxt` receives the columns of block b + 2.
+__device__ __forceinline__ void forwardsolve_block(const double* A, int ld, int n, int b, double& z, double dv,
+                                                   double (&cur)[CB], double (&nxt)[CB], double* y, double* yl) {
+  const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
+  {
+    const int p0 = (b + 2) * CB;
+#pragma unroll
+    for (int s = 0; s < CB; ++s)
+      nxt[s] = (p0 + s < n && p0 + s <= tid && tid < n) ? A[(int64_t)tid * ld + p0 + s] : 0.0;
+  }
+  const int b0 = b * CB, bs = min(CB, n - b0);
+  double* yb = yl + (b & 1) * CB;
+  if (wv == b0 / 64) {
+    const int lb = b0 & 63;
+#pragma unroll
+    for (int s = 0; s < CB; ++s) {
+      if (s < bs) {
+        const double ys = readlane_f64(z, lb + s) * readlane_f64(dv, lb + s);
+        if (lane == lb + s) z = ys;
+        else if (lane > lb + s && lane < lb + bs) z -= cur[s] * ys;
+      }
+    }
+    if (lane >= lb && lane < lb + bs) {
+      yb[lane - lb] = z;
+      y[b0 + lane - lb] = z;
+    }
+  }
+  __syncthreads();
+  if (tid >= b0 + bs && tid < n) {
+#pragma unroll
+    for (int s = 0; s < CB; ++s)
+      if (s < bs) z -= cur[s] * yb[s];
+  }
+}
+
+// L y = r, L in A (lower, ld), r in LDS (n entries), 1/L_ii in dinv; y into
+// LDS `y` (may be r); yl: 2 x 16 doubles of LDS.  By 16-row blocks from the
+// top (forwardsolve_block), columns fetched two blocks ahead.
+__device__ __forceinline__ void wg_forwardsolve_big(const double* A, int ld, int n, const double* dinv,
+                                                    const double* r, double* y, double* yl) {
+  const int tid = threadIdx.x;
+  double z = tid < n ? r[tid] : 0.0;
+  const double dv = tid < n ? dinv[tid] : 0.0;
+  __syncthreads();   // r read before y (possibly the same array) is written
+  double c0[CB], c1[CB], c2[CB];
+#pragma unroll
+  for (int s = 0; s < CB; ++s) {
+    c0[s] = (s < n && s <= tid && tid < n) ? A[(int64_t)tid * ld + s] : 0.0;
+    c1[s] = (CB + s < n && CB + s <= tid && tid < n) ? A[(int64_t)tid * ld + CB + s] : 0.0;
+  }
+  const int nb = (n + CB - 1) / CB;
+  for (int b = 0; b < nb; b += 3) {
+    forwardsolve_block(A, ld, n, b, z, dv, c0, c2, y, yl);
+    if (b + 1 < nb) forwardsolve_block(A, ld, n, b + 1, z, dv, c1, c0, y, yl);
+    if (b + 2 < nb) forwardsolve_block(A, ld, n, b + 2, z, dv, c2, c1, y, yl);
   }
   __syncthreads();
 }

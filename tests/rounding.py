@@ -58,6 +58,33 @@ def translation_loss_grad_rounded(w, iterations=2, dtype=torch.float32, lam=1e-4
     return float(L.detach()), gy.numpy(), gw.numpy()
 
 
+def cotangent_grad_rounded(w, grad_poses, grad_depth, iterations=2, dtype=torch.float32, lam=1e-4, z_min=0.1):
+    """The oracle's vector-Jacobian product (cotangents of the output pose
+    7-vectors and inverse depths) through `iterations` steps of the
+    block-eliminated solve with (S, s) rounded to `dtype` as in
+    `solve_schur_rounded` (the rounding passes the gradient through
+    unchanged): how far it lies from the exact product measures how strongly
+    the map amplifies assembly rounding."""
+    P = O.to_problem(w)
+    P["targets"].requires_grad_(True)
+    P["weights"].requires_grad_(True)
+    poses, depth = P["poses"], P["depth"]
+    nf, N = P["n_fixed"], poses.shape[0]
+    for _ in range(iterations):
+        Hpp, Hpd, hdd, gp, gd, _ = O.normal_blocks(poses, depth, P, lam, z_min)
+        S = Hpp - (Hpd / hdd) @ Hpd.T
+        s = gp - Hpd @ (gd / hdd)
+        S = S + (S.detach().to(dtype).to(O.DT) - S.detach())
+        s = s + (s.detach().to(dtype).to(O.DT) - s.detach())
+        dxi = -torch.cholesky_solve(s[:, None], torch.linalg.cholesky(S))[:, 0]
+        depth = depth - (gd + Hpd.T @ dxi) / hdd
+        poses = torch.cat([poses[:nf], O.retract(poses[nf:], dxi.reshape(N - nf, 6))], 0)
+    L = (poses * torch.as_tensor(grad_poses, dtype=O.DT)).sum() + \
+        (depth * torch.as_tensor(grad_depth, dtype=O.DT)).sum()
+    gy, gw = torch.autograd.grad(L, (P["targets"], P["weights"]))
+    return gy.numpy(), gw.numpy()
+
+
 # Probabilistic rounding-error model (Higham and Mary, "A new approach to
 # probabilistic rounding error analysis", SIAM J. Sci. Comput. 2019): a sum of
 # m terms formed in a precision with unit roundoff u is, with high

@@ -166,3 +166,43 @@ def test_vjp_subwindow_vs_central_differences(precision):
           f"norm rel err targets {norm_err['targets']:.2e} weights {norm_err['weights']:.2e}")
     assert not bad, bad[:5]
     assert max(norm_err.values()) < (1e-4 if precision == "fp64" else 1e-3)
+
+
+@pytest.mark.parametrize("shape,precision", [((24, 12, 8), "fp64"), ((40, 16, 16), "fp32"), ((64, 16, 16), "fp32")])
+def test_vjp_wide_windows_match_oracle(shape, precision):
+    """Windows with more than 21 free frames (n = 132, 228, 372): the reduced
+    system gathered into device memory and factorised by panels in both the
+    recomputed forward steps and the adjoint steps, the second right-hand side
+    solved on the same factor.  Against the oracle's autograd with fixed
+    random cotangents: FP64 within 1e-8; FP32 assembly within the change the
+    oracle's own product shows when its reduced system is rounded once to
+    FP32, times the summation factor sqrt(patches per source frame), and at
+    least 1e-4 (as for the loss gradient at 22 x 96)."""
+    need_gpu()
+    F, ppf, r = shape
+    w = synth.make_window(F, ppf, r, seed=[2208, 11, F], outlier_frac=0.1, fp32=True)
+    assert 6 * (F - 2) > 126
+    rng = np.random.default_rng(F)
+    gp = rng.normal(size=(w.n_frames, 7))
+    gd = rng.normal(size=w.n_patches)
+    gy_ref, gw_ref = O.cotangent_grad(w, gp, gd)
+    from paper_2208_04726_amd.solver import Solver, make_batch, capacities_for
+    s = Solver(precision=precision, **capacities_for([w]))
+    b = make_batch([w], precision)
+    gt, gw = s.backward(b, torch.as_tensor(gp), torch.as_tensor(gd))
+    torch.cuda.synchronize()
+    st = s.status()
+    s.close()
+    gy, gwt = gt.double().cpu().numpy(), gw.double().cpu().numpy()
+    assert st[0] == 0
+    if precision == "fp64":
+        tol_y = tol_w = 1e-8
+    else:
+        from tests.rounding import cotangent_grad_rounded, fp32_assembly_factor
+        gy32, gw32 = cotangent_grad_rounded(w, gp, gd)
+        f = fp32_assembly_factor(w)
+        tol_y = max(1e-4, f * rel_err(gy32, gy_ref))
+        tol_w = max(1e-4, f * rel_err(gw32, gw_ref))
+    eg, ew = rel_err(gy, gy_ref), rel_err(gwt, gw_ref)
+    print(f"{F} frames {precision}: vjp rel err targets {eg:.2e} (bound {tol_y:.1e}) weights {ew:.2e} (bound {tol_w:.1e})")
+    assert eg < tol_y and ew < tol_w

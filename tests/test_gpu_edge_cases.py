@@ -189,3 +189,22 @@ def test_interleaved_patches_equal_frame_ordered_input(shape, precision):
     assert sa[0] == 0 and sb[0] == 0
     assert np.array_equal(a_[0], b_[0])
     assert np.array_equal(a_[1][order], b_[1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_depth_only_method_scale(precision):
+    """Structure-only BA at method scale: 22 x 96, r = 13, every pose fixed
+    (the depth-only training stage, Sec. 3.2).  Poses come back bitwise
+    unchanged; inverse depths match the oracle, FP64 within 1e-6 relative,
+    FP32 by the FP32 depth criterion (tests/rounding.py)."""
+    need_gpu()
+    from tests.rounding import check_depths, depth_sensitivity
+    w = synth.make_window(22, 96, 13, seed=[42], outlier_frac=0.1, fp32=True, n_fixed=22)
+    (r,), st = solve_gpu([w], precision, "split")
+    assert st[0] == 0
+    assert np.array_equal(r[0], w.poses)
+    pr, dr = O.solve(w)
+    if precision == "fp64":
+        _check_fp64(w, r)
+    else:
+        check_depths(r[1], dr, depth_sensitivity(w), label="depth-only 22x96")
