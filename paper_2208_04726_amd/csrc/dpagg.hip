@@ -4,16 +4,17 @@
 // 1. The neighbourhoods as a CSR: a key per edge (its patch, or its source
 //    and target frame), a counting sort, and each segment put in edge order
 //    by a rank sort (so that every sum below runs in a fixed order).
-// 2. k_agg_gate: the hidden states of 64 consecutive CSR rows are staged in
-//    LDS; the 8 waves multiply them by the gate and value layers on the
-//    16x16x32 bfloat16 matrix cores (FP32 accumulation), each wave a band of
-//    output channels of both layers; the epilogue forms sigma and
-//    sigma * phi and sums them down the rows of each neighbourhood piece of
-//    the chunk, writing one partial per (chunk, neighbourhood).
+// 2. k_agg_gate: a workgroup takes a 128-channel slice of the gate and value
+//    layers, each wave the weights of 16 channels for every K step in
+//    registers, and runs through a group of 64-row CSR chunks: the chunk's
+//    hidden states staged in LDS (the next chunk's loaded meanwhile), the
+//    products on the 16x16x32 bfloat16 matrix cores (FP32 accumulation); the
+//    epilogue forms sigma and sigma * phi and sums them down the rows of each
+//    neighbourhood piece of the chunk, writing one partial per (chunk,
+//    neighbourhood) for the slice's channels.
 // 3. k_agg_mean sums each neighbourhood's partials in chunk order and
-//    divides; k_agg_psi passes 16 neighbourhoods at a time through psi (FP32
-//    on the vector ALU: every thread one output channel of a 128-channel
-//    slice, its weight row read once for all 16);
+//    divides; k_agg_psi passes 16 neighbourhoods x 64 channels at a time
+//    through psi on the FP32 matrix cores (bfloat16 weights widened exactly);
 //    k_agg_bcast writes each neighbourhood's row to its edges, a 64-row chunk
 //    of the CSR per workgroup.
 // The CSR depends only on the graph: with graph_ready set, a call reuses the
@@ -31,7 +32,6 @@ namespace dpagg {
 
 constexpr int CH = 64;          // CSR rows per chunk
 constexpr int NW = 8;           // waves of the gate kernel
-constexpr int GB = 16;          // neighbourhoods per output workgroup
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -203,106 +203,147 @@ __global__ void __launch_bounds__(1024) k_agg_plan(Params P, int64_t NC) {
 
 __device__ __forceinline__ bf16x8 load8(const uint16_t* p) { return __builtin_bit_cast(bf16x8, *(const uint4*)p); }
 
-// Gate and value layers of 64 CSR rows, sigma and sigma * phi, summed down
-// each neighbourhood piece.  CT = 16-channel column tiles per wave.
+// Gate and value layers of `cpw` consecutive 64-row chunks of the CSR for one
+// 128-channel slice of both layers (blockIdx.x = chunk group * NS + slice):
+// every wave keeps the weights of its 16 channels for all K steps in
+// registers (read once per workgroup), the chunk's rows are staged in LDS
+// while the next chunk's rows are loaded into registers; sigma and
+// sigma * phi are summed down each neighbourhood piece of the chunk.
 template <int D>
-__global__ void __launch_bounds__(64 * NW) k_agg_gate(Params P) {
+__global__ void __launch_bounds__(64 * NW) k_agg_gate(Params P, int64_t NC, int cpw) {
   constexpr int KB = D / 32;
-  constexpr int CT = D / (16 * NW);
+  constexpr int XS = D + 8;                   // LDS row stride (bf16): rows 16 bytes apart in the banks
+  constexpr int NS = D / (16 * NW);           // channel slices
+  constexpr int XQ = CH * (D / 8) / (64 * NW);  // 16-byte row pieces per thread
+  static_assert(CH * (D / 8) % (64 * NW) == 0, "rows stage evenly");
   extern __shared__ __align__(16) char smem[];
-  uint16_t* xs = (uint16_t*)smem;                                      // [CH][D]
-  int32_t* rgrp = (int32_t*)(smem + CH * D * 2);                       // [CH]
-  float* scratch = (float*)(smem + CH * D * 2 + CH * 4);              // [NW][2][CH][16]
-  const int c = blockIdx.x;
+  uint16_t* xs = (uint16_t*)smem;                                      // [CH][XS]
+  int32_t* rgrp = (int32_t*)(smem + CH * XS * 2);                      // [CH]
+  float* scratch = (float*)(smem + CH * XS * 2 + CH * 4);             // [NW][2][16][CH]
+  const int slice = blockIdx.x % NS;
+  const int64_t c_begin = (int64_t)(blockIdx.x / NS) * cpw;
+  const int64_t c_end = std::min<int64_t>(NC, c_begin + cpw);
   const int64_t Ev = P.off[P.G];
-  const int64_t r0 = (int64_t)c * CH;
-  const int nrows = (int)std::min<int64_t>(CH, Ev - r0);
-  if (nrows <= 0) return;   // whole workgroup: chunks past the valid edges
   const int t = threadIdx.x, wave = t >> 6, l = t & 63;
-  // stage the chunk's rows (zeros past the last row)
-  for (int i = t; i < CH * (D / 8); i += 64 * NW) {
-    const int r = i / (D / 8), q = i - r * (D / 8);
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (r < nrows) v = *(const uint4*)(P.x + (int64_t)P.segs[r0 + r] * D + q * 8);
-    *(uint4*)(xs + r * D + q * 8) = v;
-  }
-  for (int r = t; r < CH; r += 64 * NW) rgrp[r] = r < nrows ? P.key[P.segs[r0 + r]] : -1;
-  __syncthreads();
-  const int ch0 = wave * CT * 16;
   const int col = l & 15, kq = l >> 4;
-  f32x4 acc[2][4][CT];
+  const int chan = slice * 16 * NW + wave * 16 + col;
+  bf16x8 wgk[KB], wvk[KB];
 #pragma unroll
-  for (int L = 0; L < 2; ++L)
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) acc[L][rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // weight operands of the next K step are loaded while this one's
-  // products run
-  bf16x8 bg[CT], bv[CT];
-#pragma unroll
-  for (int ct = 0; ct < CT; ++ct) {
-    const int64_t w = (int64_t)(ch0 + ct * 16 + col) * D + kq * 8;
-    bg[ct] = load8(P.wg + w);
-    bv[ct] = load8(P.wv + w);
-  }
   for (int kb = 0; kb < KB; ++kb) {
-    bf16x8 a[4], ng[CT], nv[CT];
-    const int kn = kb + 1 < KB ? kb + 1 : kb;
+    const int64_t w = (int64_t)chan * D + kb * 32 + kq * 8;
+    wgk[kb] = load8(P.wg + w);
+    wvk[kb] = load8(P.wv + w);
+  }
+  const float bgc = P.bg[chan], bvc = P.bv[chan];
+  // rows of chunk c into registers (zeros past the valid rows), and the key
+  // of row t for t < CH.  The CSR entries of a chunk are loaded one chunk
+  // ahead of its rows (si, st), so a chunk's rows need one round trip.
+  uint4 xr[XQ];
+  int si[XQ];
+  int st = -1, rk = -1;
+  auto fetch_segs = [&](int64_t c) {
+    const int64_t r0 = c * CH;
+    const int nr = c < c_end ? (int)std::min<int64_t>(CH, Ev - r0) : 0;
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      const int64_t w = (int64_t)(ch0 + ct * 16 + col) * D + kn * 32 + kq * 8;
-      ng[ct] = load8(P.wg + w);
-      nv[ct] = load8(P.wv + w);
+    for (int u = 0; u < XQ; ++u) {
+      const int r = (t + u * 64 * NW) / (D / 8);
+      si[u] = r < nr ? P.segs[r0 + r] : -1;
     }
+    st = t < CH && t < nr ? P.segs[r0 + t] : -1;
+  };
+  auto fetch_rows = [&]() {
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) a[rt] = load8(xs + (rt * 16 + col) * D + kb * 32 + kq * 8);
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-      for (int ct = 0; ct < CT; ++ct) {
-        acc[0][rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], bg[ct], acc[0][rt][ct], 0, 0, 0);
-        acc[1][rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], bv[ct], acc[1][rt][ct], 0, 0, 0);
-      }
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      bg[ct] = ng[ct];
-      bv[ct] = nv[ct];
+    for (int u = 0; u < XQ; ++u) {
+      const int i = t + u * 64 * NW;
+      const int q = i % (D / 8);
+      xr[u] = si[u] >= 0 ? *(const uint4*)(P.x + (int64_t)si[u] * D + q * 8) : make_uint4(0, 0, 0, 0);
     }
+    rk = st >= 0 ? P.key[st] : -1;
+  };
+  if (c_begin < c_end) {
+    fetch_segs(c_begin);
+    fetch_rows();
+    fetch_segs(c_begin + 1);
   }
   float* sc = scratch + wave * (2 * CH * 16);
-  const int gf = P.gfirst[c];
-  const int pb = P.pbase[c];
+  for (int64_t c = c_begin; c < c_end; ++c) {
+    const int64_t r0 = c * CH;
+    const int nrows = (int)std::min<int64_t>(CH, Ev - r0);
+    if (nrows <= 0) break;   // whole workgroup: chunks past the valid edges
+    __syncthreads();         // the previous chunk's rows and keys are no longer read
 #pragma unroll
-  for (int ct = 0; ct < CT; ++ct) {
-    const int chan = ch0 + ct * 16 + col;
-    const float bgc = P.bg[chan], bvc = P.bv[chan];
+    for (int u = 0; u < XQ; ++u) {
+      const int i = t + u * 64 * NW;
+      const int r = i / (D / 8), q = i - r * (D / 8);
+      *(uint4*)(xs + r * XS + q * 8) = xr[u];
+    }
+    if (t < CH) rgrp[t] = rk;
+    __syncthreads();
+    if (c + 1 < c_end) {
+      fetch_rows();          // chunk c + 1, from the CSR entries loaded last time
+      fetch_segs(c + 2);
+    }
+    f32x4 acc[2][4];
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt)
+    for (int L = 0; L < 2; ++L)
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) acc[L][rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      bf16x8 a[4];
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) a[rt] = load8(xs + (rt * 16 + col) * XS + kb * 32 + kq * 8);
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) {
+        acc[0][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], wgk[kb], acc[0][rt], 0, 0, 0);
+        acc[1][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], wvk[kb], acc[1][rt], 0, 0, 0);
+      }
+    }
+    const int gf = P.gfirst[c];
+    const int pb = P.pbase[c];
+    // sigma * phi and sigma, column-major per wave ([which][col][row]) so that
+    // each summing lane reads its column's rows with 16-byte loads
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      float4 sp, sg4;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = rt * 16 + 4 * kq + r;
-        const float s = 1.0f / (1.0f + expf(-(acc[0][rt][ct][r] + bgc)));
-        sc[row * 16 + col] = s * (acc[1][rt][ct][r] + bvc);
-        sc[CH * 16 + row * 16 + col] = s;
+        const float sg = 1.0f / (1.0f + expf(-(acc[0][rt][r] + bgc)));
+        (&sp.x)[r] = sg * (acc[1][rt][r] + bvc);
+        (&sg4.x)[r] = sg;
       }
+      *(float4*)(sc + col * CH + rt * 16 + 4 * kq) = sp;
+      *(float4*)(sc + (16 + col) * CH + rt * 16 + 4 * kq) = sg4;
+    }
     wave_lds_sync();
-    // lanes 0-15: sigma * phi of channel col; lanes 16-31: sigma
+    // lanes 0-15: sigma * phi of channel col; lanes 16-31: sigma; the rows
+    // summed in order, in registers, 16 at a time
     if (l < 32) {
       const int which = l >> 4;
-      const float* src = sc + which * CH * 16;
+      const float* src = sc + (which * 16 + col) * CH;
       float sum = 0.f;
-      int cur = nrows > 0 ? rgrp[0] : -1;
-      for (int row = 0; row < nrows; ++row) {
-        const int g = rgrp[row];
-        if (g != cur) {
-          P.part[((int64_t)(pb + cur - gf) * 2 + which) * D + chan] = sum;
-          sum = 0.f;
-          cur = g;
+      int cur = rgrp[0];
+      for (int r0b = 0; r0b < nrows; r0b += 16) {
+        float v[16];
+        int g[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          *(float4*)(v + 4 * q) = *(const float4*)(src + r0b + 4 * q);
+          *(int4*)(g + 4 * q) = *(const int4*)(rgrp + r0b + 4 * q);
         }
-        sum += src[row * 16 + col];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          if (r0b + q < nrows) {
+            if (g[q] != cur) {
+              P.part[((int64_t)(pb + cur - gf) * 2 + which) * D + chan] = sum;
+              sum = 0.f;
+              cur = g[q];
+            }
+            sum += v[q];
+          }
+        }
       }
-      if (nrows > 0) P.part[((int64_t)(pb + cur - gf) * 2 + which) * D + chan] = sum;
+      P.part[((int64_t)(pb + cur - gf) * 2 + which) * D + chan] = sum;
     }
     wave_lds_sync();
   }
@@ -330,38 +371,39 @@ __global__ void __launch_bounds__(256) k_agg_mean(Params P) {
   }
 }
 
-// psi of GB neighbourhoods for a 128-channel slice of the outputs (blockIdx.y),
-// one thread per output channel, its weight row read once for all GB.
+// psi of 16 neighbourhoods x 64 output channels per workgroup (blockIdx.x,
+// blockIdx.y) on the FP32 matrix cores, a 16-channel tile per wave: lane
+// (i, q) = (lane % 16, lane / 16) supplies row i of the means and column i of
+// the (bfloat16, widened exactly) weights for input channels k = q * D/4 + s
+// at step s, so each lane reads contiguous runs of both.
 template <int D>
-__global__ void __launch_bounds__(128) k_agg_psi(Params P) {
-  __shared__ float y[GB][D];
-  const int t = threadIdx.x;
-  const int64_t g0 = (int64_t)blockIdx.x * GB;
-  for (int i = t; i < GB * D; i += 128) {
-    const int q = i / D, c = i - q * D;
-    y[q][c] = g0 + q < P.G ? P.ymean[(g0 + q) * D + c] : 0.f;
-  }
-  __syncthreads();
-  const int ch = blockIdx.y * 128 + t;
-  float o[GB];
+__global__ void __launch_bounds__(256) k_agg_psi(Params P) {
+  constexpr int KQ = D / 4;
+  const int l = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = l & 15, q = l >> 4;
+  const int64_t g0 = (int64_t)blockIdx.x * 16;
+  const int c0 = blockIdx.y * 64 + wave * 16;
+  const int64_t g = g0 + i < P.G ? g0 + i : 0;   // rows past the last neighbourhood: any row, not stored
+  const float* yrow = P.ymean + g * D + q * KQ;
+  const uint16_t* wrow = P.wo + (int64_t)(c0 + i) * D + q * KQ;
+  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int q = 0; q < GB; ++q) o[q] = 0.f;
-  const uint16_t* w = P.wo + (int64_t)ch * D;
-  for (int k = 0; k < D; k += 8) {
-    const uint4 v = *(const uint4*)(w + k);
-    const uint32_t h[4] = {v.x, v.y, v.z, v.w};
+  for (int s0 = 0; s0 < KQ; s0 += 8) {
+    const float4 a0 = *(const float4*)(yrow + s0), a1 = *(const float4*)(yrow + s0 + 4);
+    const uint4 wv = *(const uint4*)(wrow + s0);
+    const float av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+    const uint32_t h[4] = {wv.x, wv.y, wv.z, wv.w};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float w0 = __uint_as_float(h[i] << 16), w1 = __uint_as_float(h[i] & 0xffff0000u);
-#pragma unroll
-      for (int q = 0; q < GB; ++q) o[q] += w0 * y[q][k + 2 * i] + w1 * y[q][k + 2 * i + 1];
+    for (int u = 0; u < 4; ++u) {
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2 * u], __uint_as_float(h[u] << 16), acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2 * u + 1], __uint_as_float(h[u] & 0xffff0000u), acc, 0, 0, 0);
     }
   }
-  const float bo = P.bo[ch];
-  for (int q = 0; q < GB; ++q) {
-    const int64_t g = g0 + q;
-    if (g >= P.G) break;
-    P.psi[g * D + ch] = o[q] + bo;
+  const float bo = P.bo[c0 + i];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t gg = g0 + 4 * q + r;
+    if (gg < P.G) P.psi[gg * D + c0 + i] = acc[r] + bo;
   }
 }
 
@@ -381,13 +423,22 @@ __global__ void __launch_bounds__(256) k_agg_bcast(Params P) {
 
 template <int D>
 int launch(const Params& P, int64_t NC, hipStream_t s) {
-  const int lds = CH * D * 2 + CH * 4 + NW * 2 * CH * 16 * 4;
+  const int lds = CH * (D + 8) * 2 + CH * 4 + NW * 2 * CH * 16 * 4;
   if (hipFuncSetAttribute((const void*)k_agg_gate<D>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
     return BA_E_HIP;
-  hipLaunchKernelGGL(k_agg_gate<D>, dim3((unsigned)NC), dim3(64 * NW), lds, s, P);
+  // chunks per workgroup: about one workgroup per CU over all slices, so
+  // each slice's weights are read once per CU
+  constexpr int NS = D / (16 * NW);
+  int dev = 0, n_cu = 256;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu <= 0)
+    n_cu = 256;
+  const int cpw = (int)std::max<int64_t>(1, (NC * NS + n_cu - 1) / n_cu);
+  const int64_t groups = (NC + cpw - 1) / cpw;
+  if (groups > 0) hipLaunchKernelGGL(k_agg_gate<D>, dim3((unsigned)(groups * NS)), dim3(64 * NW), lds, s, P, NC, cpw);
   hipLaunchKernelGGL(k_agg_mean, dim3((unsigned)std::min<int64_t>((P.G * D + 255) / 256, 16384)), dim3(256), 0, s,
                      P);
-  hipLaunchKernelGGL(k_agg_psi<D>, dim3((unsigned)((P.G + GB - 1) / GB), D / 128), dim3(128), 0, s, P);
+  hipLaunchKernelGGL(k_agg_psi<D>, dim3((unsigned)((P.G + 15) / 16), D / 64), dim3(256), 0, s, P);
   hipLaunchKernelGGL(k_agg_bcast<D>, dim3((unsigned)NC), dim3(256), 0, s, P);
   return BA_OK;
 }
