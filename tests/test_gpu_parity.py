@@ -57,12 +57,12 @@ def test_reduced_system_matches_oracle(precision, win):
     s.close()
 
 
-N_PARITY = 32   # seeded windows per configuration, solved as one batch
+N_PARITY = 100  # seeded windows per configuration, solved as one batch
 
 
 @pytest.mark.parametrize("schedule", ["split", "fused"])
 def test_fp64_small_window_matches_oracle(schedule):
-    """8 frames x 16 patches, FP64: 32 seeded windows in one call, each against
+    """8 frames x 16 patches, FP64: 100 seeded windows in one call, each against
     the dense FP64 oracle at 1e-6 m / 1e-4 deg / 1e-6 relative depth."""
     need_gpu()
     wins = [synth.plain_fp64_window(i) for i in range(N_PARITY)]
