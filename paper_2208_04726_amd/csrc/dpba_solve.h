@@ -155,6 +155,36 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Lane j of each row of 16 lanes, broadcast to the whole row (DPP
+// row_newbcast): a vector-register move, no round trip through scalar
+// registers.  j must fold to a constant (the callers' loops are unrolled).
+__device__ __forceinline__ int row_bcast_i32(int v, int j) {
+  switch (j) {
+    case 0: return __builtin_amdgcn_mov_dpp(v, 0x150, 0xf, 0xf, false);
+    case 1: return __builtin_amdgcn_mov_dpp(v, 0x151, 0xf, 0xf, false);
+    case 2: return __builtin_amdgcn_mov_dpp(v, 0x152, 0xf, 0xf, false);
+    case 3: return __builtin_amdgcn_mov_dpp(v, 0x153, 0xf, 0xf, false);
+    case 4: return __builtin_amdgcn_mov_dpp(v, 0x154, 0xf, 0xf, false);
+    case 5: return __builtin_amdgcn_mov_dpp(v, 0x155, 0xf, 0xf, false);
+    case 6: return __builtin_amdgcn_mov_dpp(v, 0x156, 0xf, 0xf, false);
+    case 7: return __builtin_amdgcn_mov_dpp(v, 0x157, 0xf, 0xf, false);
+    case 8: return __builtin_amdgcn_mov_dpp(v, 0x158, 0xf, 0xf, false);
+    case 9: return __builtin_amdgcn_mov_dpp(v, 0x159, 0xf, 0xf, false);
+    case 10: return __builtin_amdgcn_mov_dpp(v, 0x15a, 0xf, 0xf, false);
+    case 11: return __builtin_amdgcn_mov_dpp(v, 0x15b, 0xf, 0xf, false);
+    case 12: return __builtin_amdgcn_mov_dpp(v, 0x15c, 0xf, 0xf, false);
+    case 13: return __builtin_amdgcn_mov_dpp(v, 0x15d, 0xf, 0xf, false);
+    case 14: return __builtin_amdgcn_mov_dpp(v, 0x15e, 0xf, 0xf, false);
+    default: return __builtin_amdgcn_mov_dpp(v, 0x15f, 0xf, 0xf, false);
+  }
+}
+__device__ __forceinline__ double row_bcast_f64(double v, int j) {
+  const long long b = __double_as_longlong(v);
+  const int lo = row_bcast_i32((int)(b & 0xffffffffLL), j);
+  const int hi = row_bcast_i32((int)(b >> 32), j);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // 1/sqrt(x) for x > 0 in FP64: the hardware estimate refined by two Newton
 // steps (within a few ulps).
 __device__ __forceinline__ double rsqrt_f64(double x) {
@@ -169,16 +199,24 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
 // the inverse of the factor.  The factor's rows are written to Ld (row stride
 // ldd), the reciprocals of its diagonal to dinv, and Linv (LDS, CBS x CBS,
 // row stride CBS + 1) receives L^{-1} (lower, zeros elsewhere).  Lane values
-// are exchanged with lane reads; the updates are branch-free (entries above
-// the diagonal hold garbage that is never read).  Pivot problems accumulate
-// BA_W_* bits into bad.
+// are exchanged by broadcasts within the first row of 16 lanes (the other
+// rows compute on their own lanes' values, which are never stored); the
+// updates are branch-free (entries above the diagonal hold garbage that is
+// never read).  Pivot problems accumulate BA_W_* bits into bad (meaningful in
+// lanes below 16).
 __device__ __forceinline__ void wave_factor_invert(double (&Lr)[CBS], int kb, double* Ld, int ldd,
                                           double* Linv, double* dinv, int& bad) {
   const int lane = lane_id();
-  double ilv[CBS];
+  // Column `lane` of L^{-1}, X[i][j] = (delta_ij - sum_{k<i} L[i][k] X[k][j]) / L[i][i],
+  // accumulated alongside the factorisation: column k of L, broadcast once at
+  // step k, updates both the trailing rows and the pending X[i] (i > k), in
+  // the same order (k ascending) as the row-by-row recurrence.
+  double ilv[CBS], Xc[CBS];
+#pragma unroll
+  for (int i = 0; i < CBS; ++i) Xc[i] = (lane == i) ? 1.0 : 0.0;
 #pragma unroll
   for (int kk = 0; kk < CBS; ++kk) {
-    double piv = readlane_f64(Lr[kk], kk);
+    double piv = row_bcast_f64(Lr[kk], kk);
     if (!(piv > 0.0) || !isfinite_d(piv)) {
       bad |= isfinite_d(piv) ? W_NOT_SPD : W_NONFINITE;
       piv = 1.0;
@@ -186,8 +224,21 @@ __device__ __forceinline__ void wave_factor_invert(double (&Lr)[CBS], int kb, do
     const double il = rsqrt_f64(piv);
     ilv[kk] = il;
     Lr[kk] = (lane == kk) ? piv * il : Lr[kk] * il;
+    Xc[kk] = (lane <= kk) ? Xc[kk] * il : 0.0;
 #pragma unroll
-    for (int jj = kk + 1; jj < CBS; ++jj) Lr[jj] -= Lr[kk] * readlane_f64(Lr[kk], jj);
+    for (int jj = kk + 1; jj < CBS; ++jj) {
+      const double c = row_bcast_f64(Lr[kk], jj);   // L[jj][kk]
+      Lr[jj] -= Lr[kk] * c;
+      Xc[jj] -= c * Xc[kk];
+    }
+    // finish each step before the next (empty statements that take the rows
+    // as operands): scheduled ahead along the pivot chain, the other
+    // updates' broadcasts would all wait in registers
+#pragma unroll
+    for (int q = 0; q < CBS; q += 4) {
+      asm volatile("" : "+v"(Lr[q]), "+v"(Lr[q + 1]), "+v"(Lr[q + 2]), "+v"(Lr[q + 3]));
+      asm volatile("" : "+v"(Xc[q]), "+v"(Xc[q + 1]), "+v"(Xc[q + 2]), "+v"(Xc[q + 3]));
+    }
   }
   if (lane < kb) {
 #pragma unroll
@@ -197,15 +248,6 @@ __device__ __forceinline__ void wave_factor_invert(double (&Lr)[CBS], int kb, do
 #pragma unroll
     for (int t = 0; t < CBS; ++t) d = (t == lane) ? ilv[t] : d;
     dinv[lane] = d;
-  }
-  // column `lane` of L^{-1}: X[i][j] = (delta_ij - sum_{k<i} L[i][k] X[k][j]) / L[i][i]
-  double Xc[CBS];
-#pragma unroll
-  for (int i = 0; i < CBS; ++i) {
-    double v = (lane == i) ? 1.0 : 0.0;
-#pragma unroll
-    for (int k = 0; k < i; ++k) v -= readlane_f64(Lr[k], i) * Xc[k];
-    Xc[i] = (lane <= i) ? v * ilv[i] : 0.0;
   }
   if (lane < CBS) {
 #pragma unroll
