@@ -184,12 +184,11 @@ __device__ __forceinline__ void wg_chol_adj(const Params& P, int w, int it, char
   __syncthreads();
   if (tid < 64) wave_cholesky_solve(A, lda, n, b2, x2);
   __syncthreads();
-  if (tid == 0) {
-    int bad = misc[1];
-    for (int i = 0; i < n; ++i)
-      if (!isfinite_d(x[i]) || !isfinite_d(x2[i])) bad |= W_NONFINITE;
-    if (bad) atomicOr(&P.status[w], bad);
-  }
+  if (tid == 0) misc[2] = misc[1];
+  __syncthreads();
+  if (tid < n && !(isfinite_d(x[tid]) && isfinite_d(x2[tid]))) atomicOr(&misc[2], W_NONFINITE);
+  __syncthreads();
+  if (tid == 0 && misc[2]) atomicOr(&P.status[w], misc[2]);
   for (int i = tid; i < 6 * N; i += WG) {
     const int a = i / 6;
     dxi[i] = a >= nfix ? x[6 * (a - nfix) + i % 6] : 0.0;

@@ -413,7 +413,7 @@ __device__ __forceinline__ void backsolve_block(const double* A, int ld, int n, 
 #pragma unroll
     for (int s = CB - 1; s >= 0; --s) {
       if (s < bs) {
-        const double xs = readlane_f64(z, lb + s) * readlane_f64(dv, lb + s);
+        const double xs = row_bcast_f64(z, s) * row_bcast_f64(dv, s);   // lanes lb .. lb+15 form one DPP row
         if (lane == lb + s) z = xs;
         else if (lane >= lb && lane < lb + s) z -= cur[s] * xs;
       }
@@ -480,7 +480,7 @@ __device__ __forceinline__ void forwardsolve_block(const double* A, int ld, int 
 #pragma unroll
     for (int s = 0; s < CB; ++s) {
       if (s < bs) {
-        const double ys = readlane_f64(z, lb + s) * readlane_f64(dv, lb + s);
+        const double ys = row_bcast_f64(z, s) * row_bcast_f64(dv, s);
         if (lane == lb + s) z = ys;
         else if (lane > lb + s && lane < lb + bs) z -= cur[s] * ys;
       }

@@ -406,7 +406,7 @@ __device__ __forceinline__ void wg_backsolve_lds(const double* A, int lda, int n
 #pragma unroll
       for (int s2 = CBS - 1; s2 >= 0; --s2) {
         if (s2 < bs) {
-          const double xs = readlane_f64(zz, s2) * dinv[b0 + s2];
+          const double xs = row_bcast_f64(zz, s2) * dinv[b0 + s2];
           if (lane == s2) zz = xs;
           else if (lane < s2) zz -= Lc[s2] * xs;
         }
@@ -455,13 +455,11 @@ __device__ __forceinline__ void wg_chol(const Params& P, int w, int iter, char* 
     wg_cholesky_lds(A, lda, n, colbuf, colbuf + CBS * (CBS + 1) + 16, misc + 1);
     wg_backsolve_lds(A, lda, n, colbuf + CBS * (CBS + 1) + 16, x, colbuf + CBS * (CBS + 1) + 16 + NCHOL_MAX);
     __syncthreads();
-    if (tid == 0) {
-      int bad = misc[1];
-      for (int i = 0; i < n; ++i)
-        if (!isfinite_d(x[i])) bad |= W_NONFINITE;
-      misc[2] = bad;
-      if (bad) atomicOr(&P.status[w], bad);
-    }
+    if (tid == 0) misc[2] = misc[1];
+    __syncthreads();
+    if (tid < n && !isfinite_d(x[tid])) atomicOr(&misc[2], W_NONFINITE);
+    __syncthreads();
+    if (tid == 0 && misc[2]) atomicOr(&P.status[w], misc[2]);
   } else if (tid == 0) {
     misc[2] = 0;
   }
