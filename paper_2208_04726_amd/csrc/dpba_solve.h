@@ -148,13 +148,6 @@ __device__ __forceinline__ void wave_cholesky_solve(const double* A, int lda, in
 
 constexpr int CBS = 16;   // panel width of the blocked factorisation
 
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
 // Lane j of each row of 16 lanes, broadcast to the whole row (DPP
 // row_newbcast): a vector-register move, no round trip through scalar
 // registers.  j must fold to a constant (the callers' loops are unrolled).
