@@ -98,7 +98,8 @@ typedef struct {
   int32_t max_frames_per_window;  /* 1..64 (1..24 for BA_PREC_FP64)               */
   int32_t chunk_frames;           /* split schedule: source frames per assembly
                                      workgroup.  0 = chosen per call from the
-                                     batch size (about two workgroups per CU);
+                                     batch size (about one workgroup per CU, at
+                                     least two source frames each);
                                      > 0 = fixed, so that each window's result
                                      is bitwise independent of the other windows
                                      of the batch (the fused schedule always is) */

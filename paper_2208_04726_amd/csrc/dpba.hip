@@ -505,14 +505,17 @@ int build_descriptors(ba_handle* h, const ba_problem* p, Plan& pl, int sched) {
   else if (sched == BA_SCHED_SPLIT) pl.fused = false;
   else pl.fused = false;   // AUTO: the split schedule, faster at every batch size measured
   // anchors per chunk for the split schedule: fixed, or aim for one assembly
-  // workgroup per CU
+  // workgroup per CU, with at least two source frames per chunk (a window cut
+  // into single frames leaves the solve ~4 us per chunk partial to gather,
+  // more than the assembly gains: measured faster for batches of 1-8 windows
+  // of 22 x 96, the same from 12 windows up, where this bound does not bite)
   int c = 1;
   if (!pl.fused) {
     if (cfg.chunk_frames > 0) {
       c = cfg.chunk_frames;
     } else {
       const int64_t target = h->n_cu;
-      c = (int)std::max<int64_t>(1, (total_anchor + target - 1) / target);
+      c = (int)std::max<int64_t>(2, (total_anchor + target - 1) / target);
     }
   }
   for (;;) {
