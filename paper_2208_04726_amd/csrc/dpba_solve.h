@@ -22,27 +22,75 @@ __host__ __device__ inline int chol_lds_bytes(int n) {
 
 // Sum the chunk partials of window w into A (n x lda, lower) and b (n).
 // With b2 (adjoint), also the depth-cotangent row: b2 = -sum_k E_k dbar_k / C_k.
+// Chunks are added in chunk order, one at a time (their blocks overlap); the
+// next chunk's entries are loaded into registers while the current one is
+// added, so each chunk does not wait for a memory round trip.  Thread tid
+// takes the entries e = tid + k WG of a chunk's lower triangle.
+constexpr int GATHER_K = ((NCHOL_MAX * (NCHOL_MAX + 1)) / 2 + WG - 1) / WG;
+__device__ __forceinline__ void tri_index(int e, int& r, int& c) {
+  r = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+  if (((r + 1) * (r + 2)) / 2 <= e) ++r;
+  if ((r * (r + 1)) / 2 > e) --r;
+  c = e - (r * (r + 1)) / 2;
+}
+struct GatherChunk {
+  int off, Dc;
+  double v[GATHER_K];
+  double vb, vb2;
+};
+__device__ __forceinline__ void gather_load(const Params& P, const WinDesc& W, int cc, bool adj, GatherChunk& g) {
+  const int tid = threadIdx.x;
+  const int c = W.chunk_off + cc;
+  const int lo_free = P.cstate[2 * c], Dc = P.cstate[2 * c + 1];
+  g.off = 6 * (lo_free - W.n_fixed);
+  g.Dc = Dc;
+  const double* part = P.partial + W.part_off + (int64_t)cc * W.part_stride;
+  const int ntri = (Dc * (Dc + 1)) / 2;
+#pragma unroll
+  for (int k = 0; k < GATHER_K; ++k) {
+    const int e = tid + k * WG;
+    int r, col;
+    tri_index(e, r, col);
+    g.v[k] = e < ntri ? part[r * Dc + col] : 0.0;
+  }
+  g.vb = tid < Dc ? part[Dc * Dc + tid] : 0.0;
+  g.vb2 = (adj && tid < Dc) ? part[Dc * Dc + Dc + tid] : 0.0;
+}
 __device__ __forceinline__ void gather_partials(const Params& P, int w, const WinDesc& W, double* A,
                                        int lda, double* b, int n, double* b2 = nullptr) {
   const int tid = threadIdx.x;
-  const int nfix = W.n_fixed;
   for (int i = tid; i < n * lda; i += WG) A[i] = 0.0;
   for (int i = tid; i < n; i += WG) b[i] = 0.0;
   if (b2)
     for (int i = tid; i < n; i += WG) b2[i] = 0.0;
   __syncthreads();
-  for (int cc = 0; cc < W.n_chunks; ++cc) {
-    const int c = W.chunk_off + cc;
-    const int lo_free = P.cstate[2 * c], Dc = P.cstate[2 * c + 1];
-    if (Dc == 0) continue;
-    const int off = 6 * (lo_free - nfix);
-    const double* part = P.partial + W.part_off + (int64_t)cc * W.part_stride;
-    for (int r = tid >> 4; r < Dc; r += WG >> 4)
-      for (int col = tid & 15; col <= r; col += 16) A[(off + r) * lda + off + col] += part[r * Dc + col];
-    for (int r = tid; r < Dc; r += WG) b[off + r] += part[Dc * Dc + r];
-    if (b2)
-      for (int r = tid; r < Dc; r += WG) b2[off + r] += part[Dc * Dc + Dc + r];
+  const int nc = W.n_chunks;
+  const bool adj = b2 != nullptr;
+  GatherChunk cur, nxt;
+  int cc = 0;
+  while (cc < nc && P.cstate[2 * (W.chunk_off + cc) + 1] == 0) ++cc;   // chunks without free frames
+  if (cc < nc) gather_load(P, W, cc, adj, nxt);
+  while (cc < nc) {
+    cur = nxt;
+    int cn = cc + 1;
+    while (cn < nc && P.cstate[2 * (W.chunk_off + cn) + 1] == 0) ++cn;
+    if (cn < nc) gather_load(P, W, cn, adj, nxt);
+    const int ntri = (cur.Dc * (cur.Dc + 1)) / 2;
+#pragma unroll
+    for (int k = 0; k < GATHER_K; ++k) {
+      const int e = tid + k * WG;
+      if (e < ntri) {
+        int r, col;
+        tri_index(e, r, col);
+        A[(cur.off + r) * lda + cur.off + col] += cur.v[k];
+      }
+    }
+    if (tid < cur.Dc) {
+      b[cur.off + tid] += cur.vb;
+      if (b2) b2[cur.off + tid] += cur.vb2;
+    }
     __syncthreads();
+    cc = cn;
   }
 }
 
