@@ -436,6 +436,7 @@ struct Plan {
   bool fused = false;
   bool capacity = false;   // grids sized for the handle's capacities (ba_launch)
   bool big = false;        // some window has more than 21 free frames
+  bool small = false;      // some window has at most 21 (the LDS Cholesky's windows)
   int64_t F = 0, Pn = 0, E = 0;
 };
 
@@ -463,6 +464,7 @@ int validate_and_plan(ba_handle* h, const ba_problem* p, Plan& pl) {
     const int nf = p->n_fixed[w];
     if (nf < 0 || nf > N) return fail(h, BA_E_INVAL, "n_fixed outside [0, frames] in window %d", w);
     const int n = 6 * (int)(N - nf);
+    if (n <= NCHOL_MAX) pl.small = true;
     if (n > NCHOL_MAX) {
       if (!h->s_big)
         return fail(h, BA_E_CAPACITY, "window %d: more than 21 free frames", w);
@@ -700,7 +702,7 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
       HIPCHK(h, hipGetLastError());
       {
         KernelTimer kt(h, s, BA_STAGE_CHOL);
-        hipLaunchKernelGGL(k_chol<T>, dim3(gW), dim3(WG), chol_lds, s, P, it);
+        if (pl.small) hipLaunchKernelGGL(k_chol<T>, dim3(gW), dim3(WG), chol_lds, s, P, it);
         if (pl.big) {
           const int tiles = gather_tiles(pl.nmax);
           hipLaunchKernelGGL(k_gather_big, dim3(gW * tiles), dim3(WG), 0, s, P, tiles);
@@ -766,7 +768,7 @@ int launch_backward(ba_handle* h, const ba_problem* p, const Plan& pl, const dou
     if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<T, 4>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
     else if (pl.maxt == 5) hipLaunchKernelGGL((k_assemble<T, 5>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
     else hipLaunchKernelGGL((k_assemble<T, 8>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
-    hipLaunchKernelGGL(k_chol<T>, dim3(pl.W), dim3(WG), chol_lds, s, P, it);
+    if (pl.small) hipLaunchKernelGGL(k_chol<T>, dim3(pl.W), dim3(WG), chol_lds, s, P, it);
     if (pl.big) {
       big_factor(P);
       hipLaunchKernelGGL(k_chol_big<T>, dim3(pl.W), dim3(WG), chol_big_lds_bytes(pl.nmax), s, P, it);
@@ -782,7 +784,7 @@ int launch_backward(ba_handle* h, const ba_problem* p, const Plan& pl, const dou
     if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<T, 4>), dim3(pl.C), dim3(WG), asm_lds, s, PA, it, Rcap);
     else if (pl.maxt == 5) hipLaunchKernelGGL((k_assemble<T, 5>), dim3(pl.C), dim3(WG), asm_lds, s, PA, it, Rcap);
     else hipLaunchKernelGGL((k_assemble<T, 8>), dim3(pl.C), dim3(WG), asm_lds, s, PA, it, Rcap);
-    hipLaunchKernelGGL(k_chol_adj<T>, dim3(pl.W), dim3(WG), chol_adj_lds, s, PA, it);
+    if (pl.small) hipLaunchKernelGGL(k_chol_adj<T>, dim3(pl.W), dim3(WG), chol_adj_lds, s, PA, it);
     if (pl.big) {
       big_factor(PA);
       hipLaunchKernelGGL(k_chol_adj_big<T>, dim3(pl.W), dim3(WG), chol_adj_big_lds_bytes(pl.nmax), s, PA, it);
@@ -1061,6 +1063,7 @@ int ba_launch(ba_handle* h, void* stream) {
   pl.Rcap = h->cfg.max_frames_per_window;
   pl.nmax = 6 * pl.Rcap;
   pl.big = !pl.fused && pl.nmax > NCHOL_MAX;
+  pl.small = true;
   if (pl.fused) pl.nmax = std::min(NCHOL_MAX, pl.nmax);
   {
     // tile passes sized for windows with at least two fixed poses (the gauge

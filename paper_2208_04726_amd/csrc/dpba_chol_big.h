@@ -87,6 +87,63 @@ static_assert(chol_panel_lds_bytes(NBIG_MAX) <= 160 * 1024 && chol_big_lds_bytes
 // rows < n hold S + lambda I (lower triangle), row n holds -s.  In the
 // adjoint (P.adjoint) the tiles of row n also sum the partials' second
 // right-hand side (the depth-cotangent column) into the side data.
+//
+// A chunk whose columns miss the tile, or whose rows miss it (the
+// right-hand-side row n belongs to every chunk), is skipped.  The chunks'
+// descriptors arrive with one vector load (a window has at most RMAX <= 64
+// chunks, one per lane), a ballot marks the chunks that reach the tile, and
+// their entries are loaded GB chunks at a time, so a pass waits on one
+// memory round trip for GB chunks; they are then added in chunk order.
+constexpr int GEPT = GT * GT / WG;   // tile elements per thread
+static_assert(RMAX <= 64, "the chunks of a window fit the lanes of a wave");
+
+template <bool ADJ>
+__device__ __forceinline__ void gather_big_passes(const Params& P, const WinDesc& W, int n, uint64_t mask, int lo_l,
+                                                  int dc_l, const int (&rr)[GEPT], const int (&cc_)[GEPT],
+                                                  double (&v)[GEPT], double (&v2)[GEPT]) {
+  constexpr int GB = ADJ ? 4 : 8;   // chunks per pass
+  while (mask) {
+    int ch[GB];
+#pragma unroll
+    for (int q = 0; q < GB; ++q) {
+      ch[q] = mask ? __ffsll((unsigned long long)mask) - 1 : -1;
+      mask &= mask - 1;
+    }
+    double a[GB][GEPT], a2[GB][GEPT];
+#pragma unroll
+    for (int q = 0; q < GB; ++q) {
+      const int cc = max(ch[q], 0);
+      const int off = 6 * (__builtin_amdgcn_readlane(lo_l, cc) - W.n_fixed);
+      const int Dc = __builtin_amdgcn_readlane(dc_l, cc);
+      const double* part = P.partial + W.part_off + (int64_t)cc * W.part_stride;
+#pragma unroll
+      for (int u = 0; u < GEPT; ++u) {
+        const int r = rr[u], c = cc_[u];
+        a[q][u] = 0.0;
+        a2[q][u] = 0.0;
+        if (ch[q] >= 0 && r <= n && c <= r && c < n && c >= off && c < off + Dc) {
+          if (r == n) {
+            a[q][u] = part[Dc * Dc + (c - off)];
+            if (ADJ) a2[q][u] = part[Dc * Dc + Dc + (c - off)];
+          } else if (r < off + Dc) {
+            a[q][u] = part[(r - off) * Dc + (c - off)];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < GB; ++q) {
+      if (ch[q] >= 0) {
+#pragma unroll
+        for (int u = 0; u < GEPT; ++u) {
+          v[u] += a[q][u];
+          if (ADJ) v2[u] += a2[q][u];
+        }
+      }
+    }
+  }
+}
+
 __device__ __forceinline__ void wg_gather_big(const Params& P, int w, int tile) {
   const WinDesc W = P.win[w];
   const int nfix = W.n_fixed;
@@ -98,11 +155,10 @@ __device__ __forceinline__ void wg_gather_big(const Params& P, int w, int tile) 
   const int bj = tile - (bi * (bi + 1)) / 2;
   const int ld = P.ld_big;
   double* A = P.s_big + (int64_t)w * ld * ld;
-  constexpr int EPT = GT * GT / WG;   // elements per thread
-  double v[EPT], v2[EPT];
-  int rr[EPT], cc_[EPT];
+  double v[GEPT], v2[GEPT];
+  int rr[GEPT], cc_[GEPT];
 #pragma unroll
-  for (int u = 0; u < EPT; ++u) {
+  for (int u = 0; u < GEPT; ++u) {
     const int e = threadIdx.x + u * WG;
     rr[u] = GT * bi + e / GT;
     cc_[u] = GT * bj + e % GT;
@@ -112,40 +168,19 @@ __device__ __forceinline__ void wg_gather_big(const Params& P, int w, int tile) 
   const bool adj = P.adjoint != 0;
   const int r_lo = GT * bi, r_hi = min(GT * bi + GT - 1, n);
   const int c_lo = GT * bj, c_hi = min(GT * bj + GT - 1, n - 1);
-  // chunks in order; a chunk whose columns miss the tile, or whose rows miss
-  // it (the right-hand-side row n belongs to every chunk), is skipped
-  for (int cc = 0; cc < W.n_chunks; ++cc) {
-    const int ci = W.chunk_off + cc;
-    const int lo_free = P.cstate[2 * ci], Dc = P.cstate[2 * ci + 1];
-    if (Dc == 0) continue;
-    const int off = 6 * (lo_free - nfix);
-    if (c_hi < off || c_lo >= off + Dc) continue;
-    if (!(r_hi >= off && r_lo < off + Dc) && !(r_lo <= n && n <= r_hi)) continue;
-    const double* part = P.partial + W.part_off + (int64_t)cc * W.part_stride;
-    double a[EPT], a2[EPT];
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      const int r = rr[u], c = cc_[u];
-      a[u] = 0.0;
-      a2[u] = 0.0;
-      if (r <= n && c <= r && c < n && c >= off && c < off + Dc) {
-        if (r == n) {
-          a[u] = part[Dc * Dc + (c - off)];
-          if (adj) a2[u] = part[Dc * Dc + Dc + (c - off)];
-        } else if (r < off + Dc) {
-          a[u] = part[(r - off) * Dc + (c - off)];
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      v[u] += a[u];
-      v2[u] += a2[u];
-    }
-  }
+  const int lane = lane_id();
+  const bool has = lane < W.n_chunks;
+  const int lo_l = has ? P.cstate[2 * (W.chunk_off + lane)] : 0;
+  const int dc_l = has ? P.cstate[2 * (W.chunk_off + lane) + 1] : 0;
+  const int off_l = 6 * (lo_l - nfix);
+  const bool hit = has && dc_l != 0 && !(c_hi < off_l || c_lo >= off_l + dc_l) &&
+                   ((r_hi >= off_l && r_lo < off_l + dc_l) || (r_lo <= n && n <= r_hi));
+  const uint64_t mask = __ballot(hit);
+  if (adj) gather_big_passes<true>(P, W, n, mask, lo_l, dc_l, rr, cc_, v, v2);
+  else gather_big_passes<false>(P, W, n, mask, lo_l, dc_l, rr, cc_, v, v2);
   double* b2 = big_aux(P, w).b2;
 #pragma unroll
-  for (int u = 0; u < EPT; ++u) {
+  for (int u = 0; u < GEPT; ++u) {
     const int r = rr[u], c = cc_[u];
     if (r > n || c > r || c >= n) continue;
     A[(int64_t)r * ld + c] = (r == n) ? -v[u] : (r == c ? v[u] + P.lambda : v[u]);
