@@ -219,11 +219,26 @@ __device__ __forceinline__ int row_bcast_i32(int v, int j) {
     default: return __builtin_amdgcn_mov_dpp(v, 0x15f, 0xf, 0xf, false);
   }
 }
+// FP64: one 64-bit DPP move (gfx950 moves 64-bit values with row_newbcast).
 __device__ __forceinline__ double row_bcast_f64(double v, int j) {
-  const long long b = __double_as_longlong(v);
-  const int lo = row_bcast_i32((int)(b & 0xffffffffLL), j);
-  const int hi = row_bcast_i32((int)(b >> 32), j);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  switch (j) {
+    case 0: return __builtin_amdgcn_mov_dpp(v, 0x150, 0xf, 0xf, false);
+    case 1: return __builtin_amdgcn_mov_dpp(v, 0x151, 0xf, 0xf, false);
+    case 2: return __builtin_amdgcn_mov_dpp(v, 0x152, 0xf, 0xf, false);
+    case 3: return __builtin_amdgcn_mov_dpp(v, 0x153, 0xf, 0xf, false);
+    case 4: return __builtin_amdgcn_mov_dpp(v, 0x154, 0xf, 0xf, false);
+    case 5: return __builtin_amdgcn_mov_dpp(v, 0x155, 0xf, 0xf, false);
+    case 6: return __builtin_amdgcn_mov_dpp(v, 0x156, 0xf, 0xf, false);
+    case 7: return __builtin_amdgcn_mov_dpp(v, 0x157, 0xf, 0xf, false);
+    case 8: return __builtin_amdgcn_mov_dpp(v, 0x158, 0xf, 0xf, false);
+    case 9: return __builtin_amdgcn_mov_dpp(v, 0x159, 0xf, 0xf, false);
+    case 10: return __builtin_amdgcn_mov_dpp(v, 0x15a, 0xf, 0xf, false);
+    case 11: return __builtin_amdgcn_mov_dpp(v, 0x15b, 0xf, 0xf, false);
+    case 12: return __builtin_amdgcn_mov_dpp(v, 0x15c, 0xf, 0xf, false);
+    case 13: return __builtin_amdgcn_mov_dpp(v, 0x15d, 0xf, 0xf, false);
+    case 14: return __builtin_amdgcn_mov_dpp(v, 0x15e, 0xf, 0xf, false);
+    default: return __builtin_amdgcn_mov_dpp(v, 0x15f, 0xf, 0xf, false);
+  }
 }
 
 // 1/sqrt(x) for x > 0 in FP64: the hardware estimate refined by two Newton
