@@ -35,25 +35,30 @@ __host__ __device__ inline int gather_tiles(int n) {
 __host__ __device__ inline int big_ld(int rcap) { return 6 * rcap + 1; }
 
 // The factorisation advances by panels of two 16-column sub-blocks.
-constexpr int PW = 2 * CB;     // panel width
+constexpr int PW = 2 * CB;     // panel width (the column-major panel copies assume 32)
+static_assert(PW == 32, "side data holds 32-column panel copies");
 constexpr int CLD = PW + 1;    // LDS row stride of a panel's column block
 
 // Per-window side data of the factorisation (FP64 words, after the window's
 // slot): the reciprocal diagonal of L (ld words), the adjoint's second
 // right-hand side as gathered (ld words), then as ints, for the last two
 // panels (panel & 1), the nonzero flags of the 16-row blocks below each
-// sub-block (32 + 32), and the pivot flags of the factorisation (one int).
-__host__ __device__ inline int big_aux_stride(int ld) { return 2 * ld + 72; }
+// sub-block (32 + 32), and the pivot flags of the factorisation (one int);
+// then, for the last two panels, a column-major copy of the panel's columns
+// of L (PW columns of ld words), which the next launch reads with coalesced
+// loads (16 consecutive rows of a column per lane group).
+__host__ __device__ inline int big_aux_stride(int ld) { return 2 * ld + 72 + 2 * 32 * ld; }
 struct BigAux {
   double* dinv;
   double* b2;
   int* nzb;    // panel p: nzb + 64 * (p & 1), first sub-block, then + 32 the second
   int* bad;
+  double* pt;  // panel p: pt + (p & 1) * PW * ld, entry L[r][32 p + c] at c * ld + r
 };
 __device__ __forceinline__ BigAux big_aux(const Params& P, int w) {
   double* base = P.big_aux + (int64_t)w * big_aux_stride(P.ld_big);
   int* ints = (int*)(base + 2 * P.ld_big);
-  return {base, base + P.ld_big, ints, ints + 128};
+  return {base, base + P.ld_big, ints, ints + 128, base + 2 * P.ld_big + 72};
 }
 
 constexpr int TU_PANEL = 4;   // row tiles per wave in flight, panel workgroup
@@ -74,7 +79,7 @@ __host__ __device__ inline int upd_groups(int n, int j) { return (upd_tiles(n, j
 // LDS of a panel launch: flags, the diagonal block's inverse, row-block
 // flags, the column block ((n+1) rows padded to 16, stride CLD).
 __host__ __device__ constexpr int chol_panel_lds_bytes(int n) {
-  return 64 + CB * PLD * 8 + 64 * 4 + ((n + 1 + 15) / 16) * 16 * CLD * 8;
+  return 64 + CB * PLD * 8 + 64 * 4 + ((n + 1 + 15) / 16) * 16 * CLD * 8 + CB * PLD * 8;
 }
 // LDS of the back substitution: flags, the solution, two blocks of it.
 __host__ __device__ constexpr int chol_big_lds_bytes(int n) { return 64 + (n + 8) * 8 + 2 * CB * 8; }
@@ -188,8 +193,9 @@ __device__ __forceinline__ void wg_gather_big(const Params& P, int w, int tile) 
   }
 }
 
-// Applies panel j-1 (columns kp = k0 - 32 .. k0 - 1 of L in A: two 16-column
-// sub-blocks) to lower 16x16 tiles of the trailing matrix at r0 = k0: tile
+// Applies panel j-1 (columns kp = k0 - 32 .. k0 - 1 of L, read from its
+// column-major copy Pt: two 16-column sub-blocks) to lower 16x16 tiles of
+// the trailing matrix at r0 = k0: tile
 // (ti, tj) covers rows r0 + 16 ti .. and columns r0 + 16 tj ..;
 // A[r][c] -= sum_t L[r][kp+t] L[c][kp+t] for c <= r, c < n, r <= n, as four
 // 16x16x4 FP64 matrix-core steps per sub-block, first sub-block first.  A
@@ -198,10 +204,10 @@ __device__ __forceinline__ void wg_gather_big(const Params& P, int w, int tile) 
 // second, from k0).  The wave takes tiles t_beg, t_beg + NWAVES, .. below
 // t_end, TU at a time; tile_of maps an index to (ti, tj).
 template <int TU, typename TileOf>
-__device__ __forceinline__ void apply_panel(double* A, int ld, int n, int k0, int t_beg, int t_end, TileOf tile_of,
-                                            const int* nzb_a, const int* nzb_b) {
+__device__ __forceinline__ void apply_panel(double* A, const double* Pt, int ld, int n, int k0, int t_beg, int t_end,
+                                            TileOf tile_of, const int* nzb_a, const int* nzb_b) {
   const int lane = lane_id(), l16 = lane & 15, g = lane >> 4;
-  const int kp = k0 - PW, m = n + 1 - k0;
+  const int m = n + 1 - k0;
   for (int t0 = t_beg; t0 < t_end; t0 += TU * NWAVES) {
     f64x4 acc[TU];
     double pa[TU][8], pb[TU][8];
@@ -218,10 +224,10 @@ __device__ __forceinline__ void apply_panel(double* A, int ld, int n, int k0, in
       const int ra = 16 * ti[u] + l16, ca = 16 * tj[u] + l16;
 #pragma unroll
       for (int kq = 0; kq < 4; ++kq) {
-        pa[u][kq] = (ha[u] && ra < m) ? A[(int64_t)(k0 + ra) * ld + kp + g + 4 * kq] : 0.0;
-        pb[u][kq] = (ha[u] && ca < m) ? A[(int64_t)(k0 + ca) * ld + kp + g + 4 * kq] : 0.0;
-        pa[u][4 + kq] = (hb[u] && ra < m) ? A[(int64_t)(k0 + ra) * ld + kp + CB + g + 4 * kq] : 0.0;
-        pb[u][4 + kq] = (hb[u] && ca < m) ? A[(int64_t)(k0 + ca) * ld + kp + CB + g + 4 * kq] : 0.0;
+        pa[u][kq] = (ha[u] && ra < m) ? Pt[(int64_t)(g + 4 * kq) * ld + k0 + ra] : 0.0;
+        pb[u][kq] = (ha[u] && ca < m) ? Pt[(int64_t)(g + 4 * kq) * ld + k0 + ca] : 0.0;
+        pa[u][4 + kq] = (hb[u] && ra < m) ? Pt[(int64_t)(CB + g + 4 * kq) * ld + k0 + ra] : 0.0;
+        pb[u][4 + kq] = (hb[u] && ca < m) ? Pt[(int64_t)(CB + g + 4 * kq) * ld + k0 + ca] : 0.0;
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -274,11 +280,13 @@ __device__ __forceinline__ void wg_chol_panel(const Params& P, int w, int j, int
   const BigAux ax = big_aux(P, w);
   const int* pa_prev = ax.nzb + 64 * ((j + 1) & 1);   // panel j-1, first sub-block
   const int* pb_prev = pa_prev + 32;                  // and second
+  const double* pt_prev = ax.pt + ((j + 1) & 1) * PW * ld;   // panel j-1, column-major
+  double* pt_cur = ax.pt + (j & 1) * PW * ld;
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   const int l16 = lane & 15, g = lane >> 4;
   if (b > 0) {
     const int t_end = min(b * UPD_TILES, upd_tiles(n, j));
-    apply_panel<TU_UPD>(A, ld, n, k0, (b - 1) * UPD_TILES + wv, t_end,
+    apply_panel<TU_UPD>(A, pt_prev, ld, n, k0, (b - 1) * UPD_TILES + wv, t_end,
                         [](int t, int& ti, int& tj) {
                           int a = 0;
                           while (((a + 1) * (a + 2)) / 2 <= t) ++a;
@@ -296,7 +304,7 @@ __device__ __forceinline__ void wg_chol_panel(const Params& P, int w, int j, int
   {
     // column block j with panel j-1 applied: row tiles ti, column tiles tc
     // = 0, 1 (the entries and order of apply_panel)
-    const int T = (mc + 15) / 16, kp = k0 - PW;
+    const int T = (mc + 15) / 16;
     double qa[2][4], qb[2][4];
     bool ca[2], cb[2];
 #pragma unroll
@@ -306,8 +314,8 @@ __device__ __forceinline__ void wg_chol_panel(const Params& P, int w, int j, int
       const int rr = 16 * tc + l16;
 #pragma unroll
       for (int kq = 0; kq < 4; ++kq) {
-        qa[tc][kq] = (ca[tc] && rr < mc) ? A[(int64_t)(k0 + rr) * ld + kp + g + 4 * kq] : 0.0;
-        qb[tc][kq] = (cb[tc] && rr < mc) ? A[(int64_t)(k0 + rr) * ld + kp + CB + g + 4 * kq] : 0.0;
+        qa[tc][kq] = (ca[tc] && rr < mc) ? pt_prev[(int64_t)(g + 4 * kq) * ld + k0 + rr] : 0.0;
+        qb[tc][kq] = (cb[tc] && rr < mc) ? pt_prev[(int64_t)(CB + g + 4 * kq) * ld + k0 + rr] : 0.0;
       }
     }
     for (int t0 = wv; t0 < T; t0 += TU_PANEL * NWAVES) {
@@ -322,8 +330,8 @@ __device__ __forceinline__ void wg_chol_panel(const Params& P, int w, int j, int
         const int ra = 16 * ti + l16;
 #pragma unroll
         for (int kq = 0; kq < 4; ++kq) {
-          pa[u][kq] = (ra_nz[u] && ra < mc) ? A[(int64_t)(k0 + ra) * ld + kp + g + 4 * kq] : 0.0;
-          pa[u][4 + kq] = (rb_nz[u] && ra < mc) ? A[(int64_t)(k0 + ra) * ld + kp + CB + g + 4 * kq] : 0.0;
+          pa[u][kq] = (ra_nz[u] && ra < mc) ? pt_prev[(int64_t)(g + 4 * kq) * ld + k0 + ra] : 0.0;
+          pa[u][4 + kq] = (rb_nz[u] && ra < mc) ? pt_prev[(int64_t)(CB + g + 4 * kq) * ld + k0 + ra] : 0.0;
         }
 #pragma unroll
         for (int tc = 0; tc < 2; ++tc) {
@@ -366,61 +374,100 @@ __device__ __forceinline__ void wg_chol_panel(const Params& P, int w, int j, int
       }
     }
   }
-  __syncthreads();
   int bad = 0;
-  const int nsub = (kw + CB - 1) / CB;
-  for (int sb = 0; sb < nsub; ++sb) {
-    const int c0 = CB * sb;              // sub-block's first column within the panel
-    const int kb = min(CB, kw - c0);
-    if (sb == 1) {
-      // second sub-block's columns (rows from 16) minus the first's products,
-      // tiles (ti, 0) at r0 = k0 + 16 as in a 16-column factorisation
-      const int m1 = mc - CB, T1 = (m1 + 15) / 16;
-      const int* nz1 = nzb;
-      double qb1[4];
+  double* Linv1 = Cb + ((n + 1 - k0 + 15) / 16) * 16 * CLD;   // the second sub-block's inverse
+  // wave 0: factor and invert the diagonal block of sub-block sb (columns
+  // 16 sb .. of the column block) into Li
+  auto factor = [&](int sb, double* Li) {
+    const int c0 = CB * sb, kb = min(CB, kw - c0);
+    double Lr[CB];
 #pragma unroll
-      for (int kq = 0; kq < 4; ++kq) qb1[kq] = (nz1[0] && l16 < m1) ? Cb[(CB + l16) * CLD + g + 4 * kq] : 0.0;
-      for (int ti = wv; ti < T1; ti += NWAVES) {
-        const bool has = nz1[ti] && nz1[0];
-        const int ra = 16 * ti + l16;
-        f64x4 acc;
+    for (int t = 0; t < CB; ++t)
+      Lr[t] = (lane < kb && t <= lane) ? Cb[(c0 + lane) * CLD + c0 + t] : (t == lane ? 1.0 : 0.0);
+    wave_factor_invert(Lr, kb, A + (int64_t)(k0 + c0) * ld + k0 + c0, ld, Li, ax.dinv + k0 + c0, bad);
+  };
+  // rows below sub-block sb: X = A L^{-T} in the column block (LDS), in A and
+  // in the column-major copy of the panel; row block rb by the calling wave
+  auto trsm = [&](int sb, const double* Li, int rb) {
+    const int c0 = CB * sb, kb = min(CB, kw - c0);
+    const int r0 = k0 + c0 + kb, m = n + 1 - r0;
+    auto rows = [&](int r) { return (const double*)(Cb + (c0 + kb + r) * CLD + c0); };
+    auto dst = [&](int r) { return Cb + (c0 + kb + r) * CLD + c0; };
+    auto dst2 = [&](int r, int c, double v) {
+      A[(int64_t)(r0 + r) * ld + k0 + c0 + c] = v;
+      pt_cur[(int64_t)(c0 + c) * ld + r0 + r] = v;
+    };
+    trsm_row_block(rb, m, kb, Li, rows, dst, dst2, nzb + 32 * sb);
+  };
+  const int m0 = n + 1 - (k0 + min(CB, kw)), nb0 = (m0 + 15) / 16;   // rows below sub-block 0
+  // Sub-block 0: wave 0 factors it and forms row block 0 below it (the
+  // second sub-block's diagonal rows), whose products every later tile of
+  // the second sub-block's update needs.
+  __syncthreads();
+  if (wv == 0) {
+    factor(0, Linv);
+    wave_sync();
+    if (nb0 > 0) trsm(0, Linv, 0);
+  }
+  __syncthreads();
+  if (kw <= CB) {
+    // one sub-block (the last panel of a window): its remaining rows
+    for (int rb = 1 + wv; rb < nb0; rb += NWAVES) trsm(0, Linv, rb);
+  } else {
+    // Look-ahead.  The second sub-block's columns (rows from 16) lose the
+    // first sub-block's products tile by tile, tiles (ti, 0) at r0 = k0 + 16
+    // as in a 16-column factorisation; tile ti needs row block ti of the
+    // first sub-block's rows and row block 0.  Wave 0 updates tile 0 (the
+    // second diagonal block) and factors it, while the other waves form the
+    // first sub-block's remaining row blocks and update their tiles.
+    const int m1 = m0, T1 = nb0;
+    const int* nz1 = nzb;
+    double qb1[4];
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq) qb1[kq] = (nz1[0] && l16 < m1) ? Cb[(CB + l16) * CLD + g + 4 * kq] : 0.0;
+    auto update1 = [&](int ti) {
+      const bool has = nz1[ti] && nz1[0];
+      const int ra = 16 * ti + l16;
+      f64x4 acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * ti + acc_row(0.0, g, r);
+        acc[r] = (row < m1 && l16 <= row) ? Cb[(CB + row) * CLD + CB + l16] : 0.0;
+      }
+      if (has) {
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) {
+          const double av = ra < m1 ? Cb[(CB + ra) * CLD + g + 4 * kq] : 0.0;
+          acc = mfma16(-av, qb1[kq], acc);
+        }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * ti + acc_row(0.0, g, r);
-          acc[r] = (row < m1 && l16 <= row) ? Cb[(CB + row) * CLD + CB + l16] : 0.0;
-        }
-        if (has) {
-#pragma unroll
-          for (int kq = 0; kq < 4; ++kq) {
-            const double av = ra < m1 ? Cb[(CB + ra) * CLD + g + 4 * kq] : 0.0;
-            acc = mfma16(-av, qb1[kq], acc);
-          }
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = 16 * ti + acc_row(0.0, g, r);
-            if (row < m1 && l16 <= row && k0 + CB + l16 < n) Cb[(CB + row) * CLD + CB + l16] = acc[r];
-          }
+          if (row < m1 && l16 <= row && k0 + CB + l16 < n) Cb[(CB + row) * CLD + CB + l16] = acc[r];
         }
       }
-      __syncthreads();
-    }
+    };
     if (wv == 0) {
-      double Lr[CB];
-#pragma unroll
-      for (int t = 0; t < CB; ++t)
-        Lr[t] = (lane < kb && t <= lane) ? Cb[(c0 + lane) * CLD + c0 + t] : (t == lane ? 1.0 : 0.0);
-      wave_factor_invert(Lr, kb, A + (int64_t)(k0 + c0) * ld + k0 + c0, ld, Linv, ax.dinv + k0 + c0, bad);
+      update1(0);
+      wave_sync();
+      factor(1, Linv1);
+    } else {
+      // a wave reads back only the rows (and the flag) it has just written
+      for (int rb = wv; rb < T1; rb += NWAVES - 1) {
+        trsm(0, Linv, rb);
+        wave_sync();
+        update1(rb);
+      }
     }
     __syncthreads();
-    const int r0 = k0 + c0 + kb, m = n + 1 - r0;
-    {
-      auto rows = [&](int r) { return (const double*)(Cb + (c0 + kb + r) * CLD + c0); };
-      auto dst = [&](int r) { return Cb + (c0 + kb + r) * CLD + c0; };
-      auto dst2 = [&](int r, int c, double v) { A[(int64_t)(r0 + r) * ld + k0 + c0 + c] = v; };
-      panel_trsm_mfma(m, kb, Linv, rows, dst, dst2, nzb + 32 * sb);
-    }
-    __syncthreads();
-    if (tid < (m + 15) / 16) ax.nzb[64 * (j & 1) + 32 * sb + tid] = nzb[32 * sb + tid];
+    const int m2 = n + 1 - (k0 + kw), nb1 = (m2 + 15) / 16;
+    for (int rb = wv; rb < nb1; rb += NWAVES) trsm(1, Linv1, rb);
+  }
+  __syncthreads();
+  {
+    const int m2 = n + 1 - (k0 + kw);
+    if (tid < nb0) ax.nzb[64 * (j & 1) + tid] = nzb[tid];
+    if (kw > CB && tid < (m2 + 15) / 16) ax.nzb[64 * (j & 1) + 32 + tid] = nzb[32 + tid];
   }
   if (wv == 0 && lane == 0) *ax.bad = (j == 0 ? 0 : *ax.bad) | bad;
 }

@@ -211,6 +211,16 @@ __device__ __forceinline__ void lds_barrier() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Makes what the lanes of a wave wrote to LDS visible to the other lanes of
+// the same wave (fences at wave scope around a wave barrier).  Without it the
+// compiler, reasoning lane by lane, may move a lane's read above a store that
+// only another lane performs.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Exclusive scan of data[0..n) in place by the whole workgroup; returns the
 // total.  lds must hold WG ints.  All threads must call it.
 __device__ __forceinline__ int wg_exclusive_scan(int32_t* data, int n, int* lds) {

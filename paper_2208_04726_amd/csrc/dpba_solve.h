@@ -315,52 +315,57 @@ __device__ __forceinline__ void wave_factor_invert(double (&Lr)[CBS], int kb, do
 // 16x16x4 FP64 matrix-core products (K = 32).  rows(r) returns the address of
 // column k0 of row r (r < m) of the source; results go to dst(r) (and, when
 // given, to a second destination).  Rows are read before they are written by
-// the same wave, so the product may be in place.
+// the same wave, so the product may be in place.  trsm_row_block forms row
+// block rb (rows 16 rb ..) with the calling wave; panel_trsm_mfma deals the
+// blocks to the waves.
 template <typename Src, typename Dst, typename Dst2>
-__device__ __forceinline__ void panel_trsm_mfma(int m, int kb, const double* Linv, Src rows, Dst dst, Dst2 dst2,
-                                       int* nzb) {
-  const int lane = lane_id(), wv = wave_id();
+__device__ __forceinline__ void trsm_row_block(int rb, int m, int kb, const double* Linv, Src rows, Dst dst, Dst2 dst2,
+                                               int* nzb) {
+  const int lane = lane_id();
   const int l16 = lane & 15, g = lane >> 4;
-  const int nblk = (m + 15) / 16;
-  for (int rb = wv; rb < nblk; rb += NWAVES) {
-    const int ra = min(16 * rb + l16, m - 1);   // operand row (clamped; extra rows not stored)
-    const double* src = rows(ra);
-    double av[CBS / 4];
+  const int ra = min(16 * rb + l16, m - 1);   // operand row (clamped; extra rows not stored)
+  const double* src = rows(ra);
+  double av[CBS / 4];
 #pragma unroll
-    for (int kq = 0; kq < CBS / 4; ++kq) {
-      const int k = 4 * kq + g;
-      av[kq] = k < kb ? src[k] : 0.0;
-    }
-    f64x4 acc[CBS / 16];
+  for (int kq = 0; kq < CBS / 4; ++kq) {
+    const int k = 4 * kq + g;
+    av[kq] = k < kb ? src[k] : 0.0;
+  }
+  f64x4 acc[CBS / 16];
 #pragma unroll
-    for (int h = 0; h < CBS / 16; ++h) acc[h] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int h = 0; h < CBS / 16; ++h) acc[h] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int kq = 0; kq < CBS / 4; ++kq) {
-      const int k = 4 * kq + g;
+  for (int kq = 0; kq < CBS / 4; ++kq) {
+    const int k = 4 * kq + g;
 #pragma unroll
-      for (int h = 0; h < CBS / 16; ++h) acc[h] = mfma16(av[kq], Linv[(16 * h + l16) * (CBS + 1) + k], acc[h]);
-    }
-    bool nz = false;
+    for (int h = 0; h < CBS / 16; ++h) acc[h] = mfma16(av[kq], Linv[(16 * h + l16) * (CBS + 1) + k], acc[h]);
+  }
+  bool nz = false;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * rb + acc_row(0.0, g, r);
-      if (row < m) {
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * rb + acc_row(0.0, g, r);
+    if (row < m) {
 #pragma unroll
-        for (int h = 0; h < CBS / 16; ++h) {
-          if (16 * h + l16 < kb) {
-            dst(row)[16 * h + l16] = acc[h][r];
-            dst2(row, 16 * h + l16, acc[h][r]);
-            nz |= acc[h][r] != 0.0;
-          }
+      for (int h = 0; h < CBS / 16; ++h) {
+        if (16 * h + l16 < kb) {
+          dst(row)[16 * h + l16] = acc[h][r];
+          dst2(row, 16 * h + l16, acc[h][r]);
+          nz |= acc[h][r] != 0.0;
         }
       }
     }
-    // row blocks whose panel entries are all zero (outside the envelope of
-    // the matrix: frames that share no patch) contribute nothing to the
-    // trailing update, which then skips their tiles
-    const bool any = __any(nz);
-    if (lane == 0) nzb[rb] = any ? 1 : 0;
   }
+  // row blocks whose panel entries are all zero (outside the envelope of
+  // the matrix: frames that share no patch) contribute nothing to the
+  // trailing update, which then skips their tiles
+  const bool any = __any(nz);
+  if (lane == 0) nzb[rb] = any ? 1 : 0;
+}
+template <typename Src, typename Dst, typename Dst2>
+__device__ __forceinline__ void panel_trsm_mfma(int m, int kb, const double* Linv, Src rows, Dst dst, Dst2 dst2,
+                                       int* nzb) {
+  const int nblk = (m + 15) / 16;
+  for (int rb = wave_id(); rb < nblk; rb += NWAVES) trsm_row_block(rb, m, kb, Linv, rows, dst, dst2, nzb);
 }
 
 // Blocked right-looking Cholesky of the augmented (n+1) x (n+1) matrix in LDS
@@ -432,6 +437,7 @@ __device__ __forceinline__ void wg_cholesky_lds(double* A, int lda, int n, doubl
       // the rest of the trailing matrix.
       if (wv == 0) {
         update(0);
+        wave_sync();
         if (r0 < n) factor(r0);
       } else {
         for (int t = wv; t < ntile; t += NWAVES - 1) update(t);
