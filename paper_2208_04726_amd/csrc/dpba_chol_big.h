@@ -472,18 +472,25 @@ __device__ __forceinline__ void wg_chol_panel(const Params& P, int w, int j, int
   if (wv == 0 && lane == 0) *ax.bad = (j == 0 ? 0 : *ax.bad) | bad;
 }
 
+// Blocks of the triangular solves whose rows are in flight while a block is
+// solved (a ring of SOLVE_AHEAD + 1 register blocks): enough to cover the
+// memory latency with the few microseconds a block takes.
+constexpr int SOLVE_AHEAD = 4;
+constexpr int SOLVE_RING = SOLVE_AHEAD + 1;
+
 // One 16-row block b of the back substitution L^T x = y (rows b0 .. b0+bs-1).
 // Thread t < n holds entry t of the running right-hand side in `z` and, in
 // `cur`, its column of the block's rows: cur[s] = L[b0 + s][t] for t <= b0 + s.
 // The wave holding entries b0 .. b0+15 (one wave: b0 is a multiple of 16)
 // solves the block's triangle from its registers, lane b0 + r taking x_r;
 // then every thread above the block subtracts the block's products.  `nxt`
-// receives the rows of block b - 2 (loads in flight across the step).
+// receives the rows of block b - SOLVE_AHEAD (loads in flight across the
+// steps).
 __device__ __forceinline__ void backsolve_block(const double* A, int ld, int n, int b, double& z, double dv,
                                                 double (&cur)[CB], double (&nxt)[CB], double* x, double* xl) {
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   {
-    const int bp = b - 2, p0 = bp * CB, ps = min(CB, n - p0);
+    const int bp = b - SOLVE_AHEAD, p0 = bp * CB, ps = min(CB, n - p0);
 #pragma unroll
     for (int s = 0; s < CB; ++s)
       nxt[s] = (bp >= 0 && s < ps && tid <= p0 + s && tid < n) ? A[(int64_t)(p0 + s) * ld + tid] : 0.0;
@@ -515,27 +522,29 @@ __device__ __forceinline__ void backsolve_block(const double* A, int ld, int n, 
 
 // L^T x = y, L in A (lower, ld), y = row n of A (or y0 in LDS), 1/L_ii in
 // dinv; x into LDS `x` (n entries); xl: 2 x 16 doubles of LDS.  By 16-row blocks from the
-// bottom (backsolve_block), the rows of each block fetched two blocks ahead;
-// the block's values are double-buffered in xl, so each block needs one
-// barrier.
+// bottom (backsolve_block), the rows of each block fetched SOLVE_AHEAD blocks
+// ahead (block nb - 1 - k of round r in ring slot k: the loop is unrolled
+// over the ring); the block's values are double-buffered in xl, so each
+// block needs one barrier.
 static_assert(NBIG_MAX < WG, "a row of the reduced system is staged one entry per thread");
 __device__ __forceinline__ void wg_backsolve_big(const double* A, int ld, int n, const double* dinv, double* x,
                                         double* xl, const double* y0 = nullptr) {
   const int tid = threadIdx.x;
   double z = tid < n ? (y0 ? y0[tid] : A[(int64_t)n * ld + tid]) : 0.0;
   const double dv = tid < n ? dinv[tid] : 0.0;
-  double c0[CB], c1[CB], c2[CB];
+  double ring[SOLVE_RING][CB];
   const int nb = (n + CB - 1) / CB;
 #pragma unroll
-  for (int s = 0; s < CB; ++s) {
-    const int b0 = (nb - 1) * CB, q0 = (nb - 2) * CB;
-    c0[s] = (s < n - b0 && tid <= b0 + s && tid < n) ? A[(int64_t)(b0 + s) * ld + tid] : 0.0;
-    c1[s] = (nb >= 2 && tid <= q0 + s) ? A[(int64_t)(q0 + s) * ld + tid] : 0.0;
+  for (int q = 0; q < SOLVE_AHEAD; ++q) {
+    const int p0 = (nb - 1 - q) * CB;
+#pragma unroll
+    for (int s = 0; s < CB; ++s)
+      ring[q][s] = (p0 >= 0 && s < n - p0 && tid <= p0 + s && tid < n) ? A[(int64_t)(p0 + s) * ld + tid] : 0.0;
   }
-  for (int b = nb - 1; b >= 0; b -= 3) {
-    backsolve_block(A, ld, n, b, z, dv, c0, c2, x, xl);
-    if (b - 1 >= 0) backsolve_block(A, ld, n, b - 1, z, dv, c1, c0, x, xl);
-    if (b - 2 >= 0) backsolve_block(A, ld, n, b - 2, z, dv, c2, c1, x, xl);
+  for (int b = nb - 1; b >= 0; b -= SOLVE_RING) {
+#pragma unroll
+    for (int q = 0; q < SOLVE_RING; ++q)
+      if (b - q >= 0) backsolve_block(A, ld, n, b - q, z, dv, ring[q], ring[(q + SOLVE_AHEAD) % SOLVE_RING], x, xl);
   }
   __syncthreads();
 }
@@ -545,12 +554,12 @@ __device__ __forceinline__ void wg_backsolve_big(const double* A, int ld, int n,
 // row's entries in the block's columns: cur[s] = L[t][b0 + s] for
 // b0 + s <= t.  The wave holding entries b0 .. b0+15 solves the block's
 // triangle from its registers; then every thread below the block subtracts
-// the block's products.  `nxt` receives the columns of block b + 2.
+// the block's products.  `nxt` receives the columns of block b + SOLVE_AHEAD.
 __device__ __forceinline__ void forwardsolve_block(const double* A, int ld, int n, int b, double& z, double dv,
                                                    double (&cur)[CB], double (&nxt)[CB], double* y, double* yl) {
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   {
-    const int p0 = (b + 2) * CB;
+    const int p0 = (b + SOLVE_AHEAD) * CB;
 #pragma unroll
     for (int s = 0; s < CB; ++s)
       nxt[s] = (p0 + s < n && p0 + s <= tid && tid < n) ? A[(int64_t)tid * ld + p0 + s] : 0.0;
@@ -582,24 +591,28 @@ __device__ __forceinline__ void forwardsolve_block(const double* A, int ld, int 
 
 // L y = r, L in A (lower, ld), r in LDS (n entries), 1/L_ii in dinv; y into
 // LDS `y` (may be r); yl: 2 x 16 doubles of LDS.  By 16-row blocks from the
-// top (forwardsolve_block), columns fetched two blocks ahead.
+// top (forwardsolve_block), columns fetched SOLVE_AHEAD blocks ahead (ring
+// slots as in the back substitution).
 __device__ __forceinline__ void wg_forwardsolve_big(const double* A, int ld, int n, const double* dinv,
                                                     const double* r, double* y, double* yl) {
   const int tid = threadIdx.x;
   double z = tid < n ? r[tid] : 0.0;
   const double dv = tid < n ? dinv[tid] : 0.0;
   __syncthreads();   // r read before y (possibly the same array) is written
-  double c0[CB], c1[CB], c2[CB];
+  double ring[SOLVE_RING][CB];
 #pragma unroll
-  for (int s = 0; s < CB; ++s) {
-    c0[s] = (s < n && s <= tid && tid < n) ? A[(int64_t)tid * ld + s] : 0.0;
-    c1[s] = (CB + s < n && CB + s <= tid && tid < n) ? A[(int64_t)tid * ld + CB + s] : 0.0;
+  for (int q = 0; q < SOLVE_AHEAD; ++q) {
+#pragma unroll
+    for (int s = 0; s < CB; ++s) {
+      const int c = q * CB + s;
+      ring[q][s] = (c < n && c <= tid && tid < n) ? A[(int64_t)tid * ld + c] : 0.0;
+    }
   }
   const int nb = (n + CB - 1) / CB;
-  for (int b = 0; b < nb; b += 3) {
-    forwardsolve_block(A, ld, n, b, z, dv, c0, c2, y, yl);
-    if (b + 1 < nb) forwardsolve_block(A, ld, n, b + 1, z, dv, c1, c0, y, yl);
-    if (b + 2 < nb) forwardsolve_block(A, ld, n, b + 2, z, dv, c2, c1, y, yl);
+  for (int b = 0; b < nb; b += SOLVE_RING) {
+#pragma unroll
+    for (int q = 0; q < SOLVE_RING; ++q)
+      if (b + q < nb) forwardsolve_block(A, ld, n, b + q, z, dv, ring[q], ring[(q + SOLVE_AHEAD) % SOLVE_RING], y, yl);
   }
   __syncthreads();
 }
