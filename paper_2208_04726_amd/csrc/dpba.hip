@@ -230,7 +230,7 @@ struct ba_handle {
   hipStream_t last_stream = nullptr;
   int last_W = 0;
   int32_t* eflags = nullptr;
-  int32_t *status = nullptr, *wmeta = nullptr, *cnt = nullptr, *ptr = nullptr, *fill = nullptr;
+  int32_t *status = nullptr, *wmeta = nullptr, *cnt = nullptr, *ptr = nullptr, *fill = nullptr, *jrun = nullptr;
   int32_t *acnt = nullptr, *afill = nullptr, *plist = nullptr, *csr = nullptr, *arange = nullptr,
           *cstate = nullptr, *estart = nullptr, *sbstart = nullptr, *gj = nullptr;
   int4* sbd = nullptr;
@@ -378,6 +378,7 @@ void carve_workspace(ba_handle* h, Take take) {
   take((void**)&h->cnt, 4 * Pn);
   take((void**)&h->ptr, 4 * Pn);
   take((void**)&h->fill, 4 * Pn);
+  take((void**)&h->jrun, 8 * Pn);
   take((void**)&h->acnt, 4 * (F + W));
   take((void**)&h->afill, 4 * F);
   take((void**)&h->plist, 4 * Pn);
@@ -606,6 +607,7 @@ void fill_params(ba_handle* h, const ba_problem* p, const Plan& pl, Params& P) {
   P.cnt = h->cnt;
   P.ptr = h->ptr;
   P.fill = h->fill;
+  P.jrun = h->jrun;
   P.acnt = h->acnt;
   P.afill = h->afill;
   P.plist = h->plist;
@@ -1130,6 +1132,7 @@ void ba_destroy(ba_handle* h) {
   hipFree(h->cnt);
   hipFree(h->ptr);
   hipFree(h->fill);
+  hipFree(h->jrun);
   hipFree(h->acnt);
   hipFree(h->afill);
   hipFree(h->plist);

@@ -59,6 +59,7 @@ struct Params {
   int32_t* cnt;         // [P] edges per patch
   int32_t* ptr;         // [P] first CSR slot of each patch (window-local)
   int32_t* fill;        // [P] scatter cursor
+  int32_t* jrun;        // [P][2] target frames of the first and last edge of a patch's run (edges in order)
   int32_t* acnt;        // [F+W] patches per anchor -> offsets
   int32_t* afill;       // [F] scatter cursor
   int32_t* plist;       // [P] patch at each position (positions sorted by (anchor, index))

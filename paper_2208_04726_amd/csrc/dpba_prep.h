@@ -27,7 +27,7 @@ namespace dpba {
 // Sub-batch width (patches) and lane segment width (edges per patch) for a
 // window's largest patch degree: one segment of lanes per patch, at most 1024
 // staged edges per sub-batch.
-constexpr int PU = 8;   // edges per thread in flight in the preparation loops
+constexpr int PU = 16;   // edges (patches) per thread in flight in the preparation loops
 // LDS of the preparation pass (ints): scan scratch, flags, per-frame ranges,
 // and per frame a regularity flag and the extremes of its patches' first and
 // last target frames
@@ -51,9 +51,9 @@ __device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }
 // Exclusive prefix sum of data[0, n) in place, by tiles of SCAN_TILE entries:
 // coalesced loads into LDS, each thread sums its SCAN_PER consecutive
 // entries, a wave scan of the thread sums and one of the wave totals, then
-// coalesced stores.  `part` holds NWAVES ints, `tile` SCAN_TILE_PAD.
-// Returns the total.  All threads call.
-__device__ int wg_scan_tiled(int32_t* data, int n, int* part, int* tile) {
+// coalesced stores (also into `copy` when given).  `part` holds NWAVES ints,
+// `tile` SCAN_TILE_PAD.  Returns the total.  All threads call.
+__device__ int wg_scan_tiled(int32_t* data, int n, int* part, int* tile, int32_t* copy = nullptr) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   int carry = 0;
   for (int base = 0; base < n; base += SCAN_TILE) {
@@ -93,7 +93,11 @@ __device__ int wg_scan_tiled(int32_t* data, int n, int* part, int* tile) {
 #pragma unroll
     for (int u = 0; u < SCAN_PER; ++u) {
       const int i = u * WG + tid;
-      if (i < m) data[base + i] = tile[scan_pad(i)];
+      if (i < m) {
+        const int v = tile[scan_pad(i)];
+        data[base + i] = v;
+        if (copy) copy[base + i] = v;
+      }
     }
     carry += total;
     __syncthreads();
@@ -107,7 +111,8 @@ constexpr int EPB = PU * WG;
 // The edge pass over edges [lo, hi) of window W (window-local indices, in
 // batches of PU per thread from lo + tid): index checks, order checks, and
 // where each patch's run of edges starts (fill) and ends (cnt), which gives
-// the counts when the edges turn out to be sorted.
+// the counts when the edges turn out to be sorted, and the target frames of
+// the run's first and last edge (jrun).
 __device__ __forceinline__ void prep_edge_range(const Params& P, const WinDesc& W, int lo, int hi, bool& bad,
                                                 bool& uns_e, bool& dup_e) {
   const int M = W.n_patches, N = W.n_frames, E = W.n_edges;
@@ -115,6 +120,7 @@ __device__ __forceinline__ void prep_edge_range(const Params& P, const WinDesc& 
   const int32_t* jj = P.jj + W.edge_off;
   int32_t* cnt = P.cnt + W.patch_off;
   int32_t* fill = P.fill + W.patch_off;
+  int32_t* jrun = P.jrun + 2 * W.patch_off;
   for (int e0 = lo + (int)threadIdx.x; e0 < hi; e0 += PU * WG) {
     int k[PU], j[PU], kp[PU], jp[PU], kn[PU];
 #pragma unroll
@@ -136,8 +142,14 @@ __device__ __forceinline__ void prep_edge_range(const Params& P, const WinDesc& 
         uns_e |= (kp[u] > k[u] || (kp[u] == k[u] && jp[u] > j[u]));
         dup_e |= kp[u] == k[u] && jp[u] == j[u];
         if (!kbad) {
-          if (kp[u] != k[u]) fill[k[u]] = e;
-          if (kn[u] != k[u]) cnt[k[u]] = e + 1;
+          if (kp[u] != k[u]) {
+            fill[k[u]] = e;
+            jrun[2 * k[u]] = j[u];
+          }
+          if (kn[u] != k[u]) {
+            cnt[k[u]] = e + 1;
+            jrun[2 * k[u] + 1] = j[u];
+          }
         }
       }
     }
@@ -335,7 +347,9 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds, bool e
   }
   atomicMax(&flags[3], mx);
   __syncthreads();
-  wg_scan_tiled(ptr, M, lds, tile);
+  // with patches in frame order, positions are patch indices and the edge
+  // offsets per position are the CSR offsets: one scan writes both
+  wg_scan_tiled(ptr, M, lds, tile, unsorted_p ? nullptr : est);
   if (unsorted_e) {
     for (int e = tid; e < E; e += WG) {
       const int k = kk[e];
@@ -413,8 +427,8 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds, bool e
   }
   __syncthreads();
 
-  // ---- edge order offsets per position
-  for (int q0 = tid; q0 < M; q0 += PU * WG) {
+  // ---- edge order offsets per position (patches out of frame order)
+  for (int q0 = tid; unsorted_p && q0 < M; q0 += PU * WG) {
     int k[PU], c[PU];
 #pragma unroll
     for (int u = 0; u < PU; ++u) {
@@ -428,7 +442,7 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds, bool e
       if (q0 + u * WG < M) est[q0 + u * WG] = c[u];
   }
   __syncthreads();
-  wg_scan_tiled(est, M, lds, tile);
+  if (unsorted_p) wg_scan_tiled(est, M, lds, tile);
   if (tid == 0) est[M] = E;
   // per-position pixel rays, initial depths, frame ranges
   T* pxy = (T*)P.pxy + 2 * W.patch_off;
@@ -436,6 +450,7 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds, bool e
   for (int i = tid; i < 7 * N; i += WG) P.pose_buf[7 * W.frame_off + i] = P.poses_in[7 * W.frame_off + i];
   for (int q0 = tid; q0 < M; q0 += PU * WG) {
     int k[PU], n[PU], a[PU], b[PU], j0[PU], j1[PU];
+    int2 jr[PU];
     double x[PU], y[PU], d[PU];
 #pragma unroll
     for (int u = 0; u < PU; ++u) {
@@ -452,13 +467,16 @@ __device__ __forceinline__ void wg_prep(const Params& P, int w, int* lds, bool e
       n[u] = in ? cnt[k[u]] : 0;
       a[u] = in ? anc[k[u]] : 0;
       b[u] = in ? ptr[k[u]] : 0;
+      // edges in order: the run's first and last target frames, recorded by
+      // the edge pass (meaningful for a patch with edges)
+      jr[u] = (in && !unsorted_e) ? ((const int2*)(P.jrun + 2 * W.patch_off))[k[u]] : make_int2(0, 0);
     }
 #pragma unroll
     for (int u = 0; u < PU; ++u) {
       j0[u] = j1[u] = 0;
       if (n[u] > 0) {
-        j0[u] = unsorted_e ? jj[csr[b[u]]] : jj[b[u]];
-        j1[u] = unsorted_e ? jj[csr[b[u] + n[u] - 1]] : jj[b[u] + n[u] - 1];
+        j0[u] = unsorted_e ? jj[csr[b[u]]] : jr[u].x;
+        j1[u] = unsorted_e ? jj[csr[b[u] + n[u] - 1]] : jr[u].y;
       }
     }
 #pragma unroll
