@@ -283,6 +283,8 @@ int set_kernel_attrs() {
   if (hipFuncSetAttribute((const void*)k_assemble<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_assemble<T, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_assemble<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
+  if constexpr (sizeof(T) == 4)
+    if (hipFuncSetAttribute((const void*)k_assemble<T, 12>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_fused<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_fused<T, 5>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
   if (hipFuncSetAttribute((const void*)k_fused<T, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess) return -1;
@@ -424,11 +426,25 @@ int check_config_numerics(const ba_config* cfg) {
 
 // Accumulator tiles per wave: the smallest instantiated count that holds a
 // chunk's lower-triangle tiles in one pass (larger chunks take several passes
-// with 8).
-int maxt_for(int tiles) {
+// with 8, or in FP32 with 12, whose running sums stay in memory).
+int maxt_for(int tiles, bool fp32) {
   if (tiles <= NWAVES * 4) return 4;
   if (tiles <= NWAVES * 5) return 5;
-  return 8;
+  if (tiles <= NWAVES * 8 || !fp32) return 8;
+  return 12;
+}
+
+// k_assemble with the tile count the plan selected (12 exists in FP32 only).
+template <typename T>
+void launch_assemble(int maxt, dim3 grid, int lds, hipStream_t s, const Params& P, int iter, int Rcap) {
+  if (maxt == 4) hipLaunchKernelGGL((k_assemble<T, 4>), grid, dim3(WG), lds, s, P, iter, Rcap);
+  else if (maxt == 5) hipLaunchKernelGGL((k_assemble<T, 5>), grid, dim3(WG), lds, s, P, iter, Rcap);
+  else if constexpr (sizeof(T) == 4) {
+    if (maxt == 12) hipLaunchKernelGGL((k_assemble<T, 12>), grid, dim3(WG), lds, s, P, iter, Rcap);
+    else hipLaunchKernelGGL((k_assemble<T, 8>), grid, dim3(WG), lds, s, P, iter, Rcap);
+  } else {
+    hipLaunchKernelGGL((k_assemble<T, 8>), grid, dim3(WG), lds, s, P, iter, Rcap);
+  }
 }
 
 struct Plan {
@@ -476,7 +492,7 @@ int validate_and_plan(ba_handle* h, const ba_problem* p, Plan& pl) {
       // accumulator tiles per wave: lower-triangle 16x16 tiles of (n+1)^2 over 8 waves
       const int T16 = (n + 1 + 15) / 16;
       const int L = T16 * (T16 + 1) / 2;
-      pl.maxt = std::max(pl.maxt, maxt_for(L));
+      pl.maxt = std::max(pl.maxt, maxt_for(L, cfg.precision == BA_PREC_FP32));
     }
     pl.Rcap = std::max<int>(pl.Rcap, (int)N);
     const double* K = p->intrinsics + 4 * w;
@@ -697,9 +713,7 @@ int launch_solve(ba_handle* h, const ba_problem* p, const Plan& pl, hipStream_t 
     for (int it = 0; it < P.iterations; ++it) {
       if (gC > 0) {
         KernelTimer kt(h, s, BA_STAGE_ASSEMBLE);
-        if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<T, 4>), dim3(gC), dim3(WG), asm_lds, s, P, it, Rcap);
-        else if (pl.maxt == 5) hipLaunchKernelGGL((k_assemble<T, 5>), dim3(gC), dim3(WG), asm_lds, s, P, it, Rcap);
-        else hipLaunchKernelGGL((k_assemble<T, 8>), dim3(gC), dim3(WG), asm_lds, s, P, it, Rcap);
+        launch_assemble<T>(pl.maxt, dim3(gC), asm_lds, s, P, it, Rcap);
       }
       HIPCHK(h, hipGetLastError());
       {
@@ -767,9 +781,7 @@ int launch_backward(ba_handle* h, const ba_problem* p, const Plan& pl, const dou
   };
   // recompute the iterates x_1 .. x_{K-1}
   for (int it = 0; it + 1 < K; ++it) {
-    if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<T, 4>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
-    else if (pl.maxt == 5) hipLaunchKernelGGL((k_assemble<T, 5>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
-    else hipLaunchKernelGGL((k_assemble<T, 8>), dim3(pl.C), dim3(WG), asm_lds, s, P, it, Rcap);
+    launch_assemble<T>(pl.maxt, dim3(pl.C), asm_lds, s, P, it, Rcap);
     if (pl.small) hipLaunchKernelGGL(k_chol<T>, dim3(pl.W), dim3(WG), chol_lds, s, P, it);
     if (pl.big) {
       big_factor(P);
@@ -783,9 +795,7 @@ int launch_backward(ba_handle* h, const ba_problem* p, const Plan& pl, const dou
   Params PA = P;
   PA.adjoint = 1;
   for (int it = K - 1; it >= 0; --it) {
-    if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<T, 4>), dim3(pl.C), dim3(WG), asm_lds, s, PA, it, Rcap);
-    else if (pl.maxt == 5) hipLaunchKernelGGL((k_assemble<T, 5>), dim3(pl.C), dim3(WG), asm_lds, s, PA, it, Rcap);
-    else hipLaunchKernelGGL((k_assemble<T, 8>), dim3(pl.C), dim3(WG), asm_lds, s, PA, it, Rcap);
+    launch_assemble<T>(pl.maxt, dim3(pl.C), asm_lds, s, PA, it, Rcap);
     if (pl.small) hipLaunchKernelGGL(k_chol_adj<T>, dim3(pl.W), dim3(WG), chol_adj_lds, s, PA, it);
     if (pl.big) {
       big_factor(PA);
@@ -1073,7 +1083,7 @@ int ba_launch(ba_handle* h, void* stream) {
     // same results
     const int n2 = 6 * std::max(pl.Rcap - 2, 1);
     const int T16 = (std::min(pl.nmax, n2) + 1 + 15) / 16;
-    pl.maxt = maxt_for(T16 * (T16 + 1) / 2);
+    pl.maxt = maxt_for(T16 * (T16 + 1) / 2, h->cfg.precision == BA_PREC_FP32);
   }
   const ba_problem* p = &h->prep_problem;
   return h->cfg.precision == BA_PREC_FP32 ? launch_solve<float>(h, p, pl, s)
@@ -1199,13 +1209,9 @@ int ba_debug_reduced_system(ba_handle* h, const ba_problem* p, int32_t window, d
     // the accumulator-tile variant ba_solve selects for this batch
     const int al = asm_layout(pl.Rcap, esz, pl.maxt).total;
     if (f32) {
-      if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<float, 4>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
-      else if (pl.maxt == 5) hipLaunchKernelGGL((k_assemble<float, 5>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
-      else hipLaunchKernelGGL((k_assemble<float, 8>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
+      launch_assemble<float>(pl.maxt, dim3(pl.C), al, s, P, 0, pl.Rcap);
     } else {
-      if (pl.maxt == 4) hipLaunchKernelGGL((k_assemble<double, 4>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
-      else if (pl.maxt == 5) hipLaunchKernelGGL((k_assemble<double, 5>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
-      else hipLaunchKernelGGL((k_assemble<double, 8>), dim3(pl.C), dim3(WG), al, s, P, 0, pl.Rcap);
+      launch_assemble<double>(pl.maxt, dim3(pl.C), al, s, P, 0, pl.Rcap);
     }
     HIPCHK(h, hipGetLastError());
   }

@@ -250,6 +250,15 @@ __device__ __forceinline__ T adj_at(const T* rel, int p, int q) {
   return q < 3 ? T(0) : rel[3 * (p - 3) + (q - 3)];
 }
 
+// Element (row, col) of a chunk's partial block: the lower triangle of the
+// D x D pose block row-major, then rows D .. Daug-1 (the right-hand side and,
+// in the adjoint, the cotangent column); -1 for an element outside it.
+__device__ __forceinline__ int part_slot(int row, int col, int D, int Daug) {
+  if (row < D && col <= row) return row * D + col;
+  if (row >= D && row < Daug && col < D) return D * D + (row - D) * D + col;
+  return -1;
+}
+
 // State after `iter` iterations: poses (slot iter of pose_buf) and inverse
 // depths (slot iter of depth_buf, position order); slot 0 holds the inputs.
 template <typename T>
@@ -507,7 +516,13 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
     const int ntl = Lp > wv ? (Lp - wv + NWAVES - 1) / NWAVES : 0;
     const int t_beg = p0 + wv;   // tile t of the wave is t_beg + NWAVES * t
     Acc acc[MAXT];
-    double sh[4 * MAXT];
+    // FP32 assembly keeps each tile element's FP64 running sum in registers,
+    // except the 12-tile variant (windows whose chunks span about 34 free
+    // frames, one tile pass instead of two): it has no register room for
+    // them and keeps them in the chunk's partial block, each element read and
+    // written by its own lane at the ends of source frames only
+    constexpr bool kGlobalFold = sizeof(T) == 4 && MAXT > 8;
+    double sh[kGlobalFold ? 1 : 4 * MAXT];
     // Regular source frames (every patch with the same target-frame sequence)
     // with one table copy per lane segment: each lane accumulates the
     // pair-table row of its one target frame, in registers for the whole
@@ -518,8 +533,10 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
     bool regular = false;
 #pragma unroll
     for (int t = 0; t < MAXT; ++t) acc[t] = Acc{T(0), T(0), T(0), T(0)};
+    if constexpr (!kGlobalFold) {
 #pragma unroll
-    for (int t = 0; t < 4 * MAXT; ++t) sh[t] = 0.0;
+      for (int t = 0; t < 4 * MAXT; ++t) sh[t] = 0.0;
+    }
 
     StageRegs<T> R;
     int4 dcur = make_int4(0, 0, 0, 0), dnxt = dcur;
@@ -530,6 +547,22 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
     }
     __syncthreads();   // previous pass done with the stage and the poses are in LDS
     if (s_lo < s_hi) stage_store<T>(dcur, R, S, dbar_in != nullptr);
+    if constexpr (kGlobalFold) {
+      // the running sums of this wave's tiles start from zero
+      const int l16 = lane & 15, g = lane >> 4;
+#pragma unroll
+      for (int t = 0; t < MAXT; ++t) {
+        if (t < ntl) {
+          const int code = tiles[t_beg + NWAVES * t];
+          const int ti = code >> 16, tj = code & 0xffff;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int sl = part_slot(16 * ti + acc_row(T(0), g, r), 16 * tj + l16, D, Daug);
+            if (sl >= 0) part[sl] = 0.0;
+          }
+        }
+      }
+    }
 
     int a = -1, lo = 0, hi = -1, Ra = 0, nz_lo = 0, nz_hi = 0;
     unsigned tmask = 0;   // this wave's tiles reached by the current source frame
@@ -693,8 +726,28 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
           const int o_tbl = L.tbl / ES, o_G = L.G / ES, o_AQA = o_G + Ra * 36;
           const int o_zero = (L.misc + 32) / ES;
           const T* base = (const T*)smem;
+          // kGlobalFold: the running sums of a group of FG tiles are loaded
+          // together (one memory round trip per group) before their entries
+          constexpr int FG = kGlobalFold ? 4 : 1;
+          double old[FG][4];
+          int osl[FG][4];
 #pragma unroll
           for (int t = 0; t < MAXT; ++t) {
+            if constexpr (kGlobalFold) {
+              if (t % FG == 0) {
+#pragma unroll
+                for (int q = 0; q < FG; ++q) {
+                  const bool in = t + q < MAXT && (tmask & (1u << (t + q)));
+                  const int code = in ? tiles[t_beg + NWAVES * (t + q)] : 0;
+                  const int ti = code >> 16, tj = code & 0xffff;
+#pragma unroll
+                  for (int r = 0; r < 4; ++r) {
+                    osl[q][r] = in ? part_slot(16 * ti + acc_row(T(0), g, r), 16 * tj + l16, D, Daug) : -1;
+                    old[q][r] = osl[q][r] >= 0 ? part[osl[q][r]] : 0.0;
+                  }
+                }
+              }
+            }
             // tiles the source frame does not reach hold no products and no
             // B / v entries of it
             if (tmask & (1u << t)) {
@@ -730,7 +783,11 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const T v = neg[r] ? -val[r] : val[r];
-                if constexpr (sizeof(T) == 4) {
+                if constexpr (kGlobalFold) {
+                  const int sl = osl[t % FG][r];
+                  if (sl >= 0) part[sl] = old[t % FG][r] + ((double)v - (double)acc[t][r]);
+                  acc[t][r] = T(0);
+                } else if constexpr (sizeof(T) == 4) {
                   sh[t * 4 + r] += (double)v - (double)acc[t][r];
                   acc[t][r] = T(0);
                 } else {
@@ -934,15 +991,15 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
       const int l16 = lane & 15, g = lane >> 4;
 #pragma unroll
       for (int t = 0; t < MAXT; ++t) {
-        if (t < ntl) {
+        if (!kGlobalFold && t < ntl) {
           const int code = tiles[t_beg + NWAVES * t];
           const int ti = code >> 16, tj = code & 0xffff;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int row = 16 * ti + acc_row(T(0), g, r), col = 16 * tj + l16;
-            const double v = (sizeof(T) == 4) ? sh[t * 4 + r] : -(double)acc[t][r];
-            if (row < D && col <= row) part[row * D + col] = v;
-            else if (row >= D && row < Daug && col < D) part[D * D + (row - D) * D + col] = v;
+            const int sl = part_slot(16 * ti + acc_row(T(0), g, r), 16 * tj + l16, D, Daug);
+            double v = -(double)acc[t][r];
+            if constexpr (sizeof(T) == 4 && !kGlobalFold) v = sh[t * 4 + r];
+            if (sl >= 0) part[sl] = v;
           }
         }
       }
