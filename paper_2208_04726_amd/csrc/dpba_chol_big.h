@@ -490,10 +490,13 @@ __device__ __forceinline__ void backsolve_block(const double* A, int ld, int n, 
                                                 double (&cur)[CB], double (&nxt)[CB], double* x, double* xl) {
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   {
-    const int bp = b - SOLVE_AHEAD, p0 = bp * CB, ps = min(CB, n - p0);
+    // unconditional loads at clamped addresses: the entries are read only
+    // where they belong to the triangle (below the diagonal, inside the
+    // matrix), and straight-line loads let each block wait for its own rows
+    // only, not for the loads in flight behind them
+    const int p0 = max(b - SOLVE_AHEAD, 0) * CB;
 #pragma unroll
-    for (int s = 0; s < CB; ++s)
-      nxt[s] = (bp >= 0 && s < ps && tid <= p0 + s && tid < n) ? A[(int64_t)(p0 + s) * ld + tid] : 0.0;
+    for (int s = 0; s < CB; ++s) nxt[s] = A[(int64_t)min(p0 + s, n - 1) * ld + min(tid, n - 1)];
   }
   const int b0 = b * CB, bs = min(CB, n - b0);
   double* xb = xl + (b & 1) * CB;
@@ -536,10 +539,9 @@ __device__ __forceinline__ void wg_backsolve_big(const double* A, int ld, int n,
   const int nb = (n + CB - 1) / CB;
 #pragma unroll
   for (int q = 0; q < SOLVE_AHEAD; ++q) {
-    const int p0 = (nb - 1 - q) * CB;
+    const int p0 = max(nb - 1 - q, 0) * CB;
 #pragma unroll
-    for (int s = 0; s < CB; ++s)
-      ring[q][s] = (p0 >= 0 && s < n - p0 && tid <= p0 + s && tid < n) ? A[(int64_t)(p0 + s) * ld + tid] : 0.0;
+    for (int s = 0; s < CB; ++s) ring[q][s] = A[(int64_t)min(p0 + s, n - 1) * ld + min(tid, n - 1)];
   }
   for (int b = nb - 1; b >= 0; b -= SOLVE_RING) {
 #pragma unroll
@@ -559,10 +561,10 @@ __device__ __forceinline__ void forwardsolve_block(const double* A, int ld, int 
                                                    double (&cur)[CB], double (&nxt)[CB], double* y, double* yl) {
   const int tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   {
+    // unconditional loads at clamped addresses, as in the back substitution
     const int p0 = (b + SOLVE_AHEAD) * CB;
 #pragma unroll
-    for (int s = 0; s < CB; ++s)
-      nxt[s] = (p0 + s < n && p0 + s <= tid && tid < n) ? A[(int64_t)tid * ld + p0 + s] : 0.0;
+    for (int s = 0; s < CB; ++s) nxt[s] = A[(int64_t)min(tid, n - 1) * ld + min(p0 + s, n - 1)];
   }
   const int b0 = b * CB, bs = min(CB, n - b0);
   double* yb = yl + (b & 1) * CB;
@@ -603,10 +605,7 @@ __device__ __forceinline__ void wg_forwardsolve_big(const double* A, int ld, int
 #pragma unroll
   for (int q = 0; q < SOLVE_AHEAD; ++q) {
 #pragma unroll
-    for (int s = 0; s < CB; ++s) {
-      const int c = q * CB + s;
-      ring[q][s] = (c < n && c <= tid && tid < n) ? A[(int64_t)tid * ld + c] : 0.0;
-    }
+    for (int s = 0; s < CB; ++s) ring[q][s] = A[(int64_t)min(tid, n - 1) * ld + min(q * CB + s, n - 1)];
   }
   const int nb = (n + CB - 1) / CB;
   for (int b = 0; b < nb; b += SOLVE_RING) {
