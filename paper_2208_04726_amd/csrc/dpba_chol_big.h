@@ -9,7 +9,9 @@
 //     (one wave) and turns the rows below it (the right-hand-side row
 //     included, which folds the forward substitution L y = -s into the
 //     factorisation) into A L^{-T} with matrix-core products, the first
-//     sub-block's rows updating the second's columns in between;
+//     sub-block's rows updating the second's columns in between (with a
+//     look-ahead: the second diagonal block is factorised while the other
+//     waves finish the first sub-block's rows);
 //   * in the same launch, many more workgroups apply panel j-1 to the rest
 //     of the trailing lower triangle (16x16x4 FP64 matrix-core products),
 //     so the update of a window is spread over the chip instead of one CU.
@@ -262,8 +264,9 @@ __device__ __forceinline__ void apply_panel(double* A, const double* Pt, int ld,
 // Launch j of the factorisation of window w (k0 = 32 j).  Workgroup b = 0
 // brings column block j (32 columns) up to date with panel j-1 in LDS, then
 // per 16-column sub-block: one wave factorises and inverts the diagonal
-// block, the rows below become A L^{-T} (written to A), and after the first
-// sub-block the second one's columns receive its update in LDS.
+// block, the rows below become A L^{-T} (written to A and to the panel's
+// column-major copy), and after the first sub-block the second one's
+// columns receive its update in LDS.
 // Workgroups b >= 1 apply panel j-1 to their share of the tiles right of
 // column block j.  The two sets of entries are disjoint, and both only read
 // panel j-1, which launch j-1 finished.  Pivot problems accumulate BA_W_*
