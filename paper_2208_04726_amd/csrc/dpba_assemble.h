@@ -580,8 +580,11 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
 #pragma unroll
             for (int q = 0; q < TBL; ++q) qacc[q] = swap_add<32>(qacc[q]);
             qj = max(qj, __shfl_xor(qj, 32, 64));
-            if (sidx == 0 && qj >= 0) {
-              T* row = tbl + (wv * 2 * Ra + (qj - lo)) * TBL;
+            // lane x holds target frame lo + x (zeros if no edge of it was
+            // active), so every row of the wave's copy is written and the
+            // copy needs no clearing
+            if (sidx == 0 && lseg < Ra) {
+              T* row = tbl + (wv * 2 * Ra + lseg) * TBL;
 #pragma unroll
               for (int q = 0; q < TBL; ++q) row[q] = qacc[q];
             }
@@ -589,9 +592,10 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
             T* c0 = tbl + wv * 2 * Ra * TBL;
             for (int i = lane; i < Ra * TBL; i += 64) c0[i] = c0[i] + c0[Ra * TBL + i];
           }
-        } else if (kRegTbl && regular && qj >= 0) {
-          // the lane's register row into its wave's table copy
-          T* row = tbl + ((wv * tslots + sidx) * Ra + (qj - lo)) * TBL;
+        } else if (kRegTbl && regular && lseg < Ra) {
+          // the lane's register row into its wave's table copy (every row,
+          // as above)
+          T* row = tbl + ((wv * tslots + sidx) * Ra + lseg) * TBL;
 #pragma unroll
           for (int q = 0; q < TBL; ++q) row[q] = qacc[q];
         }
@@ -808,16 +812,18 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
         hi = arng[2 * (a - cd.a_lo) + 1];
         Ra = hi - lo + 1;
         load_relposes<T>(lp, a, lo, hi, f_lo, rel);
-        {
-          const int nt = NWAVES * tslots * Ra * TBL, n4 = (nt * (int)sizeof(T)) / 16;
-          for (int i = tid; i < n4; i += WG) ((float4*)tbl)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-          for (int i = (n4 * 16) / (int)sizeof(T) + tid; i < nt; i += WG) tbl[i] = T(0);
-        }
         // one table copy per lane segment and one target frame per lane: the
         // rows are summed in the same order in registers (five-tile FP32
         // passes) or in LDS (otherwise), so the sums do not depend on the
         // kernel variant a batch selects
         regular = sizeof(T) == 4 && (dcur.y & SB_REGULAR) && tslots == segs;   // FP32 assembly
+        // the tables start from zero, except the register rows' copies, which
+        // the frame end writes in full
+        if (!(kRegTbl && regular)) {
+          const int nt = NWAVES * tslots * Ra * TBL, n4 = (nt * (int)sizeof(T)) / 16;
+          for (int i = tid; i < n4; i += WG) ((float4*)tbl)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+          for (int i = (n4 * 16) / (int)sizeof(T) + tid; i < nt; i += WG) tbl[i] = T(0);
+        }
         if constexpr (kRegTbl) {
 #pragma unroll
           for (int q = 0; q < TBL; ++q) qacc[q] = T(0);
