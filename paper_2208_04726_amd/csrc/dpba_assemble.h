@@ -529,7 +529,6 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
     // source frame in the FP32 passes of at most five tiles per wave
     constexpr bool kRegTbl = sizeof(T) == 4 && MAXT <= 5;
     T qacc[kRegTbl ? TBL : 1];
-    int qj = -1;
     bool regular = false;
 #pragma unroll
     for (int t = 0; t < MAXT; ++t) acc[t] = Acc{T(0), T(0), T(0), T(0)};
@@ -579,7 +578,6 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
           if constexpr (kRegTbl) {
 #pragma unroll
             for (int q = 0; q < TBL; ++q) qacc[q] = swap_add<32>(qacc[q]);
-            qj = max(qj, __shfl_xor(qj, 32, 64));
             // lane x holds target frame lo + x (zeros if no edge of it was
             // active), so every row of the wave's copy is written and the
             // copy needs no clearing
@@ -827,7 +825,6 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
         if constexpr (kRegTbl) {
 #pragma unroll
           for (int q = 0; q < TBL; ++q) qacc[q] = T(0);
-          qj = -1;
         }
         nz_lo = 6 * (max(lo, lo_free) - lo_free);
         nz_hi = (hi >= lo_free) ? 6 * (hi - lo_free + 1) : 0;
@@ -883,8 +880,7 @@ __device__ __forceinline__ void wg_assemble(const Params& P, int c, int iter, ch
         if (sizeof(T) == 4 && regular) {
           if (eo.active) {
             T* racc = qacc;
-            if constexpr (kRegTbl) qj = j;
-            else racc = mytbl + (sidx * Ra + (j - lo)) * TBL;
+            if constexpr (!kRegTbl) racc = mytbl + (sidx * Ra + (j - lo)) * TBL;
             // Q += w0 J0 J0^T + w1 J1 J1^T, V += w0 r0 J0 + w1 r1 J1, with the
             // structural zeros J0[1] = J1[0] = 0 left out
             int q = 0;
