@@ -36,11 +36,16 @@ def _wide(n_frames, ppf, r, seed, fp32=True, n_fixed=2):
                              n_fixed=n_fixed)
 
 
-def test_reduced_system_372_matches_oracle():
+@pytest.mark.parametrize("chunk_frames", [0, 64])
+def test_reduced_system_372_matches_oracle(chunk_frames):
+    """S and s of a 64-frame window (n = 372).  With the automatic chunking
+    each chunk spans about 34 free frames (one pass of 12 accumulator tiles
+    per wave); with one chunk of all 64 frames the FP32 assembly takes four
+    tile passes, each keeping its FP64 running sums in the partial block."""
     need_gpu()
     from paper_2208_04726_amd.solver import Solver, make_batch, capacities_for
     w = _wide(64, 16, 16, 0)
-    s = Solver(precision="fp32", **capacities_for([w]))
+    s = Solver(precision="fp32", chunk_frames=chunk_frames, **capacities_for([w]))
     S, sv = s.reduced_system(make_batch([w], "fp32"))
     torch.cuda.synchronize()
     S_ref, s_ref = O.reduced_system(w)
