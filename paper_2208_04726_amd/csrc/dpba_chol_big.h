@@ -123,18 +123,22 @@ __device__ __forceinline__ void gather_big_passes(const Params& P, const WinDesc
       const int off = 6 * (__builtin_amdgcn_readlane(lo_l, cc) - W.n_fixed);
       const int Dc = __builtin_amdgcn_readlane(dc_l, cc);
       const double* part = P.partial + W.part_off + (int64_t)cc * W.part_stride;
+      // unconditional loads (index 0 where the element takes nothing from
+      // the chunk) and selects afterwards: loads under divergent branches
+      // would each wait for all loads in flight
 #pragma unroll
       for (int u = 0; u < GEPT; ++u) {
         const int r = rr[u], c = cc_[u];
-        a[q][u] = 0.0;
-        a2[q][u] = 0.0;
-        if (ch[q] >= 0 && r <= n && c <= r && c < n && c >= off && c < off + Dc) {
-          if (r == n) {
-            a[q][u] = part[Dc * Dc + (c - off)];
-            if (ADJ) a2[q][u] = part[Dc * Dc + Dc + (c - off)];
-          } else if (r < off + Dc) {
-            a[q][u] = part[(r - off) * Dc + (c - off)];
-          }
+        const bool in = ch[q] >= 0 && r <= n && c <= r && c < n && c >= off && c < off + Dc;
+        const bool rhs = in && r == n, body = in && r != n && r < off + Dc;
+        const int i1 = rhs ? Dc * Dc + (c - off) : (body ? (r - off) * Dc + (c - off) : 0);
+        const double x = part[i1];
+        a[q][u] = (rhs || body) ? x : 0.0;
+        if (ADJ) {
+          const double y = part[rhs ? Dc * Dc + Dc + (c - off) : 0];
+          a2[q][u] = rhs ? y : 0.0;
+        } else {
+          a2[q][u] = 0.0;
         }
       }
     }
